@@ -1,0 +1,179 @@
+"""CPU oracle for batched Keplerian radial-velocity chi-square — TEST INFRASTRUCTURE.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never imports, links or
+calls it, and it shares no code with the GPU library.
+
+The arithmetic lives in ``kepler_oracle.c`` (plain C, binary64 inputs, long
+double internals); this module only marshals numpy arrays into it.  Functions
+follow the paper (Ford 2008) section by section:
+
+* ``kepler``        — root of Kepler's equation M = E - e sin E (Eq. 1, Sec. 4.3)
+* ``mean_anomaly``  — Eq. 4 / Eq. 6 with the binary64 bracket of Sec. 5.1
+* ``planet_rv``     — one planet's Keplerian velocity (Eq. 3, standard form)
+* ``rv_model``      — planet sum plus offset (Eq. 2)
+* ``chisq``         — Eq. 5 with per-system jitter
+* ``chisq_grad``    — analytic gradient of Eq. 5 (partial derivatives, Sec. 6)
+* ``chisq_ragged``  — Eq. 5 over CSR-packed systems of uneven size
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+
+
+class _Dense(ctypes.Structure):
+    _fields_ = [("t", _D), ("v", _D), ("sigma", _D), ("n_obs", ctypes.c_int64),
+                ("t0", ctypes.c_double),
+                ("P", _D), ("K", _D), ("e", _D), ("w", _D), ("M0", _D),
+                ("offset", _D), ("jitter", _D),
+                ("n_sys", ctypes.c_int64), ("n_pl", ctypes.c_int64)]
+
+
+class _Ragged(ctypes.Structure):
+    _fields_ = [("t", _D), ("v", _D), ("sigma", _D), ("obs_off", _I64),
+                ("t0", ctypes.c_double),
+                ("P", _D), ("K", _D), ("e", _D), ("w", _D), ("M0", _D),
+                ("pl_off", _I64), ("offset", _D), ("jitter", _D),
+                ("n_sys", ctypes.c_int64)]
+
+
+def lib():
+    """Load (building first if nothing is built) the oracle shared library."""
+    global _LIB
+    if _LIB is None:
+        path = os.environ.get("KEP_ORACLE_LIB")     # a deliberately broken copy (mutation tests)
+        if path is None:
+            path = _build.LIB
+            if not os.path.exists(path):
+                _build.build()
+        L = ctypes.CDLL(path)
+        L.oracle_kepler.restype = ctypes.c_double
+        L.oracle_kepler.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.oracle_kepler_batch.restype = None
+        L.oracle_kepler_batch.argtypes = [_D, _D, _D, ctypes.c_int64]
+        L.oracle_mean_anomaly.restype = ctypes.c_double
+        L.oracle_mean_anomaly.argtypes = [ctypes.c_double] * 4
+        L.oracle_planet_rv.restype = ctypes.c_double
+        L.oracle_planet_rv.argtypes = [ctypes.c_double] * 7
+        for name in ("oracle_rv_model", "oracle_chisq"):
+            f = getattr(L, name)
+            f.restype = None
+            f.argtypes = [ctypes.POINTER(_Dense), _D, ctypes.c_int64, ctypes.c_int64]
+        L.oracle_chisq_grad.restype = None
+        L.oracle_chisq_grad.argtypes = [ctypes.POINTER(_Dense), _D, _D, ctypes.c_int64, ctypes.c_int64]
+        L.oracle_chisq_ragged.restype = None
+        L.oracle_chisq_ragged.argtypes = [ctypes.POINTER(_Ragged), _D, ctypes.c_int64, ctypes.c_int64]
+        _LIB = L
+    return _LIB
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def kepler(M, e):
+    """E with E - e sin E = M for every pair (Eq. 1); NaN outside e in [0, 1)."""
+    M, e = np.broadcast_arrays(_f64(M), _f64(e))
+    M, e = _f64(M), _f64(e)
+    out = np.empty_like(M)
+    lib().oracle_kepler_batch(_ptr(M), _ptr(e), _ptr(out), M.size)
+    return out
+
+
+def mean_anomaly(t, t0, P, M0):
+    """M in [0, 2 pi) for scalars (Eq. 4 with the binary64 bracket of Eq. 6)."""
+    return lib().oracle_mean_anomaly(float(t), float(t0), float(P), float(M0))
+
+
+def planet_rv(t, t0, P, K, e, w, M0):
+    """Velocity of one planet at time t (scalars)."""
+    return lib().oracle_planet_rv(float(t), float(t0), float(P), float(K), float(e), float(w), float(M0))
+
+
+class Dense:
+    """Dense batch: observations [n_obs] shared by all systems, parameter
+    planes [n_pl, n_sys] (system index fastest), optional offset/jitter [n_sys]."""
+
+    def __init__(self, t, v, sigma, P, K, e, w, M0, offset=None, jitter=None, t0=0.0):
+        self.t, self.v, self.sigma = _f64(t), _f64(v), _f64(sigma)
+        planes = [np.atleast_2d(_f64(x)) for x in (P, K, e, w, M0)]
+        self.P, self.K, self.e, self.w, self.M0 = [_f64(x) for x in planes]
+        self.n_pl, self.n_sys = self.P.shape
+        self.offset = None if offset is None else _f64(offset)
+        self.jitter = None if jitter is None else _f64(jitter)
+        self.t0 = float(t0)
+        self._s = _Dense(_ptr(self.t), _ptr(self.v), _ptr(self.sigma), self.t.size, self.t0,
+                         _ptr(self.P), _ptr(self.K), _ptr(self.e), _ptr(self.w), _ptr(self.M0),
+                         _ptr(self.offset), _ptr(self.jitter), self.n_sys, self.n_pl)
+
+    def _range(self, i0, i1):
+        i1 = self.n_sys if i1 is None else i1
+        if not (0 <= i0 <= i1 <= self.n_sys):
+            raise ValueError("bad system range")
+        return i0, i1
+
+
+def rv_model(d: Dense, i0=0, i1=None):
+    """Model velocity [n_sys, n_obs] (Eq. 2 plus offset); rows outside [i0, i1) are NaN."""
+    i0, i1 = d._range(i0, i1)
+    out = np.full((d.n_sys, d.t.size), np.nan)
+    lib().oracle_rv_model(ctypes.byref(d._s), _ptr(out), i0, i1)
+    return out
+
+
+def chisq(d: Dense, i0=0, i1=None, out=None):
+    """chi-square per system (Eq. 5); entries outside [i0, i1) are left untouched."""
+    i0, i1 = d._range(i0, i1)
+    if out is None:
+        out = np.full(d.n_sys, np.nan)
+    lib().oracle_chisq(ctypes.byref(d._s), _ptr(out), i0, i1)
+    return out
+
+
+def chisq_grad(d: Dense, i0=0, i1=None):
+    """(chi2 [n_sys], grad [5*n_pl+1, n_sys]); gradient rows are P,K,e,omega,M0 per planet, then offset."""
+    i0, i1 = d._range(i0, i1)
+    chi2 = np.full(d.n_sys, np.nan)
+    grad = np.full((5 * d.n_pl + 1, d.n_sys), np.nan)
+    lib().oracle_chisq_grad(ctypes.byref(d._s), _ptr(chi2), _ptr(grad), i0, i1)
+    return chi2, grad
+
+
+class Ragged:
+    """CSR batch: system i owns observations obs_off[i]:obs_off[i+1] and
+    planets pl_off[i]:pl_off[i+1]."""
+
+    def __init__(self, t, v, sigma, obs_off, P, K, e, w, M0, pl_off, offset=None, jitter=None, t0=0.0):
+        self.t, self.v, self.sigma = _f64(t), _f64(v), _f64(sigma)
+        self.obs_off = np.ascontiguousarray(obs_off, dtype=np.int64)
+        self.pl_off = np.ascontiguousarray(pl_off, dtype=np.int64)
+        self.P, self.K, self.e, self.w, self.M0 = [_f64(x) for x in (P, K, e, w, M0)]
+        self.n_sys = self.obs_off.size - 1
+        self.offset = None if offset is None else _f64(offset)
+        self.jitter = None if jitter is None else _f64(jitter)
+        self.t0 = float(t0)
+        self._s = _Ragged(_ptr(self.t), _ptr(self.v), _ptr(self.sigma),
+                          self.obs_off.ctypes.data_as(_I64), self.t0,
+                          _ptr(self.P), _ptr(self.K), _ptr(self.e), _ptr(self.w), _ptr(self.M0),
+                          self.pl_off.ctypes.data_as(_I64), _ptr(self.offset), _ptr(self.jitter),
+                          self.n_sys)
+
+
+def chisq_ragged(d: Ragged, i0=0, i1=None, out=None):
+    """chi-square per CSR system (Eq. 5)."""
+    i1 = d.n_sys if i1 is None else i1
+    if out is None:
+        out = np.full(d.n_sys, np.nan)
+    lib().oracle_chisq_ragged(ctypes.byref(d._s), _ptr(out), i0, i1)
+    return out

@@ -1,0 +1,318 @@
+/*
+ * CPU oracle for batched Keplerian radial-velocity models and their chi-square.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct reference
+ * that the GPU library is checked against.  Only the test suite, the smoke check
+ * and the benchmark's CPU-baseline leg may load it.  It shares no code, header,
+ * constant or helper with the GPU library, and the GPU library never calls it.
+ *
+ * Precision.  Inputs and outputs are IEEE binary64.  The quotient
+ * q = (t - t0) / P is rounded to binary64 exactly as the paper prescribes for
+ * the bracketed term of the mean anomaly (Sec. 4.2, Eq. 6; Sec. 5.1 stores t and
+ * P in double and evaluates the bracket in double).  Every later step (Kepler
+ * root, true anomaly, velocity, planet sum, chi-square sum, gradient) runs in
+ * x86 extended precision (long double, 64-bit significand) and is rounded to
+ * binary64 once at the end, so the oracle is more accurate than any GPU path.
+ *
+ * Readings of the paper used here (each is listed with its reason in the
+ * design notes of the repository):
+ *  - Mean anomaly M = 2*pi*frac((t - t0)/P) + M0 with a PLUS sign on M0: Eq. 4
+ *    writes +M0 and calls M0 the mean anomaly at the epoch; Eq. 6 prints -M0.
+ *    The epoch t0 is an explicit input (the paper fixes t0 = 0, Sec. 2.1).
+ *  - Velocity of one planet v = K [cos(omega + f) + e cos(omega)] with K the
+ *    usual semi-amplitude, omega the argument of pericentre and f the true
+ *    anomaly.  The printed Eq. 3 mixes conventions (its K' and the bracket);
+ *    this is the standard Keplerian velocity it stands for.
+ *  - Jitter: one value s per system, w_k = 1 / (sigma_k^2 + s^2) (Eq. 5).
+ *  - An optional per-system velocity offset gamma is added to the planet sum.
+ *  - Domain: e in [0, 1), P > 0 and every input finite, else the system's
+ *    chi-square (and gradient) is NaN.
+ *
+ * Parity pins for each function live in the CPU test suite; none is unpinned.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <float.h>
+
+typedef long double ld;
+
+static const ld PI_L = 3.14159265358979323846264338327950288L;
+#define TWO_PI_L (2.0L * PI_L)
+
+static int finite_d(double x) { return isfinite(x) != 0; }
+
+/* ------------------------------------------------------------------ */
+/* Kepler's equation, Eq. 1:  M = E - e sin E.                          */
+/* g(E) = E - e sin E - M is strictly increasing (g' = 1 - e cos E >=  */
+/* 1 - e > 0), so the root is unique and lies in [M - e, M + e].  The  */
+/* oracle runs Newton's method on g, kept inside that bracket (a step  */
+/* that leaves the bracket is replaced by bisection), started from the */
+/* paper's guess E0 = M + 0.85 e sign(sin M) (Sec. 4.3).  It stops     */
+/* when the bracket or the Newton step is below the long-double        */
+/* resolution; at most 400 steps.  This deliberately differs from the  */
+/* GPU's Danby iteration: both must reach the same unique root.        */
+/* ------------------------------------------------------------------ */
+static ld kepler_root_l(ld M, ld e)
+{
+    if (e == 0.0L) return M;
+    ld lo = M - e, hi = M + e;
+    ld E = M + 0.85L * e * (sinl(M) >= 0.0L ? 1.0L : -1.0L);
+    if (E < lo) E = lo;
+    if (E > hi) E = hi;
+    for (int it = 0; it < 400; ++it) {
+        ld g = E - e * sinl(E) - M;
+        if (g == 0.0L) return E;
+        if (g > 0.0L) hi = E; else lo = E;
+        ld dg = 1.0L - e * cosl(E);
+        ld En = E - g / dg;
+        if (!(En > lo && En < hi)) En = 0.5L * (lo + hi);
+        ld step = fabsl(En - E);
+        E = En;
+        ld scale = fabsl(E) > 1.0L ? fabsl(E) : 1.0L;
+        if (step <= 4.0L * LDBL_EPSILON * scale) {
+            /* one more Newton step from a point this close cannot leave the bracket */
+            g = E - e * sinl(E) - M;
+            dg = 1.0L - e * cosl(E);
+            return E - g / dg;
+        }
+        if (hi - lo <= 2.0L * LDBL_EPSILON * scale) return 0.5L * (lo + hi);
+    }
+    return E;
+}
+
+double oracle_kepler(double M, double e)
+{
+    if (!finite_d(M) || !finite_d(e) || !(e >= 0.0 && e < 1.0)) return NAN;
+    return (double)kepler_root_l((ld)M, (ld)e);
+}
+
+void oracle_kepler_batch(const double *M, const double *e, double *E, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) E[i] = oracle_kepler(M[i], e[i]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Mean anomaly, Eq. 4 and Eq. 6: q = (t - t0)/P in binary64 (Sec. 5.1),*/
+/* phi = q - floor(q) (exact), M = 2 pi phi + M0, brought into [0, 2pi)*/
+/* by subtracting whole turns (Sec. 4.2 keeps M in [0, 2pi)).          */
+/* ------------------------------------------------------------------ */
+static ld mean_anomaly_l(double t, double t0, double P, double M0)
+{
+    double dt = t - t0;
+    double q = dt / P;                 /* IEEE binary64 division, round to nearest */
+    double phi = q - floor(q);         /* exact in binary64 */
+    ld M = TWO_PI_L * (ld)phi + (ld)M0;
+    M -= TWO_PI_L * floorl(M / TWO_PI_L);
+    return M;
+}
+
+double oracle_mean_anomaly(double t, double t0, double P, double M0)
+{
+    return (double)mean_anomaly_l(t, t0, P, M0);
+}
+
+/* ------------------------------------------------------------------ */
+/* True anomaly from E (half-angle form) and the velocity of one planet */
+/* (Eq. 3 in its standard reading): v = K [cos(omega + f) + e cos omega]*/
+/* ------------------------------------------------------------------ */
+static ld true_anomaly_l(ld E, ld e)
+{
+    return 2.0L * atan2l(sqrtl(1.0L + e) * sinl(0.5L * E), sqrtl(1.0L - e) * cosl(0.5L * E));
+}
+
+static int planet_ok(double P, double K, double e, double w, double M0)
+{
+    return finite_d(P) && P > 0.0 && finite_d(K) && finite_d(e) && e >= 0.0 && e < 1.0 &&
+           finite_d(w) && finite_d(M0);
+}
+
+static ld planet_rv_l(double t, double t0, double P, double K, double e, double w, double M0)
+{
+    ld M = mean_anomaly_l(t, t0, P, M0);
+    ld E = kepler_root_l(M, (ld)e);
+    ld f = true_anomaly_l(E, (ld)e);
+    return (ld)K * (cosl((ld)w + f) + (ld)e * cosl((ld)w));
+}
+
+double oracle_planet_rv(double t, double t0, double P, double K, double e, double w, double M0)
+{
+    if (!finite_d(t) || !finite_d(t0) || !planet_ok(P, K, e, w, M0)) return NAN;
+    return (double)planet_rv_l(t, t0, P, K, e, w, M0);
+}
+
+/* ------------------------------------------------------------------ */
+/* Dense batch.  Observations t, v, sigma [n_obs] are shared by every  */
+/* system (Sec. 4.1).  Parameter planes P, K, e, w, M0 are [n_pl][n_sys]*/
+/* with the system index fastest.  offset and jitter are [n_sys] or   */
+/* NULL (zero).  Only systems i in [i0, i1) are evaluated.             */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const double *t, *v, *sigma;
+    int64_t n_obs;
+    double t0;
+    const double *P, *K, *e, *w, *M0;
+    const double *offset, *jitter;
+    int64_t n_sys, n_pl;
+} oracle_dense;
+
+static int system_ok(const oracle_dense *d, int64_t i)
+{
+    for (int64_t j = 0; j < d->n_pl; ++j) {
+        int64_t p = j * d->n_sys + i;
+        if (!planet_ok(d->P[p], d->K[p], d->e[p], d->w[p], d->M0[p])) return 0;
+    }
+    if (d->offset && !finite_d(d->offset[i])) return 0;
+    if (d->jitter && !(finite_d(d->jitter[i]) && d->jitter[i] >= 0.0)) return 0;
+    if (!finite_d(d->t0)) return 0;
+    return 1;
+}
+
+/* Weight of one observation for a system with jitter s (Eq. 5).  Returns 0
+   (the caller turns it into NaN) unless sigma >= 0, sigma^2 + s^2 > 0 and
+   t, v, sigma are finite. */
+static ld weight_l(double sigma, double v, double t, double s)
+{
+    if (!finite_d(sigma) || !(sigma >= 0.0) || !finite_d(v) || !finite_d(t)) return 0.0L;
+    ld var = (ld)sigma * (ld)sigma + (ld)s * (ld)s;
+    if (!(var > 0.0L) || !isfinite(var)) return 0.0L;
+    return 1.0L / var;
+}
+
+/* Eq. 2 plus offset: model velocity of system i at time t. */
+static ld model_l(const oracle_dense *d, int64_t i, double t)
+{
+    ld sum = 0.0L;
+    for (int64_t j = 0; j < d->n_pl; ++j) {
+        int64_t p = j * d->n_sys + i;
+        sum += planet_rv_l(t, d->t0, d->P[p], d->K[p], d->e[p], d->w[p], d->M0[p]);
+    }
+    if (d->offset) sum += (ld)d->offset[i];
+    return sum;
+}
+
+void oracle_rv_model(const oracle_dense *d, double *out, int64_t i0, int64_t i1)
+{
+    for (int64_t i = i0; i < i1; ++i) {
+        int ok = system_ok(d, i);
+        for (int64_t k = 0; k < d->n_obs; ++k)
+            out[i * d->n_obs + k] = (ok && finite_d(d->t[k])) ? (double)model_l(d, i, d->t[k]) : NAN;
+    }
+}
+
+/* Eq. 5: chi2_i = sum_k (model_ik - v_k)^2 / (sigma_k^2 + s_i^2). */
+void oracle_chisq(const oracle_dense *d, double *chi2, int64_t i0, int64_t i1)
+{
+    for (int64_t i = i0; i < i1; ++i) {
+        if (!system_ok(d, i)) { chi2[i] = NAN; continue; }
+        double s = d->jitter ? d->jitter[i] : 0.0;
+        ld acc = 0.0L;
+        int bad = 0;
+        for (int64_t k = 0; k < d->n_obs; ++k) {
+            ld w = weight_l(d->sigma[k], d->v[k], d->t[k], s);
+            if (w == 0.0L) { bad = 1; break; }
+            ld r = model_l(d, i, d->t[k]) - (ld)d->v[k];
+            acc += w * r * r;
+        }
+        chi2[i] = bad ? NAN : (double)acc;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Gradient of Eq. 5 with respect to (P, K, e, omega, M0) of every     */
+/* planet and the offset gamma; the paper asks for parallel partial    */
+/* derivatives of the goodness of fit (Sec. 6).  Analytic, using the   */
+/* implicit-function derivatives of Kepler's equation, no iteration   */
+/* is differentiated:                                                  */
+/*   df/dM = (1 + e cos f)^2 / (1 - e^2)^(3/2)                         */
+/*   df/de (M fixed) = sin f (2 + e cos f) / (1 - e^2)                 */
+/*   dv/dK = cos(w+f) + e cos w,  dv/dw = -K [sin(w+f) + e sin w]       */
+/*   dv/dM0 = -K sin(w+f) df/dM,  dv/dP = dv/dM0 * (-2 pi q / P)       */
+/*   dv/de = K cos w - K sin(w+f) df/de                                */
+/*   dchi2/dtheta = sum_k 2 w_k r_k dv/dtheta,  dchi2/dgamma = sum 2 w r*/
+/* grad layout: [(5*n_pl + 1)][n_sys], planet j uses rows 5j..5j+4 in  */
+/* the order P, K, e, omega, M0; the last row is the offset.           */
+/* ------------------------------------------------------------------ */
+void oracle_chisq_grad(const oracle_dense *d, double *chi2, double *grad, int64_t i0, int64_t i1)
+{
+    const int64_t npar = 5 * d->n_pl + 1;
+    ld g[5 * 64 + 1];
+    for (int64_t i = i0; i < i1; ++i) {
+        int ok = system_ok(d, i) && d->n_pl <= 64;
+        double s = d->jitter ? d->jitter[i] : 0.0;
+        for (int64_t a = 0; a < npar; ++a) g[a] = 0.0L;
+        ld acc = 0.0L;
+        for (int64_t k = 0; ok && k < d->n_obs; ++k) {
+            ld wk = weight_l(d->sigma[k], d->v[k], d->t[k], s);
+            if (wk == 0.0L) { ok = 0; break; }
+            ld r = model_l(d, i, d->t[k]) - (ld)d->v[k];
+            acc += wk * r * r;
+            ld c = 2.0L * wk * r;
+            for (int64_t j = 0; j < d->n_pl; ++j) {
+                int64_t p = j * d->n_sys + i;
+                ld P = d->P[p], K = d->K[p], e = d->e[p], om = d->w[p];
+                ld q = (ld)((d->t[k] - d->t0) / d->P[p]);
+                ld M = mean_anomaly_l(d->t[k], d->t0, d->P[p], d->M0[p]);
+                ld E = kepler_root_l(M, e);
+                ld f = true_anomaly_l(E, e);
+                ld one_m_e2 = (1.0L - e) * (1.0L + e);
+                ld b = sqrtl(one_m_e2);
+                ld ecf = 1.0L + e * cosl(f);
+                ld dfdM = ecf * ecf / (one_m_e2 * b);
+                ld dfde = sinl(f) * (2.0L + e * cosl(f)) / one_m_e2;
+                ld swf = sinl(om + f);
+                ld dv_dK = cosl(om + f) + e * cosl(om);
+                ld dv_dw = -K * (swf + e * sinl(om));
+                ld dv_dM0 = -K * swf * dfdM;
+                ld dv_dP = dv_dM0 * (-TWO_PI_L * q / P);
+                ld dv_de = K * cosl(om) - K * swf * dfde;
+                g[5 * j + 0] += c * dv_dP;
+                g[5 * j + 1] += c * dv_dK;
+                g[5 * j + 2] += c * dv_de;
+                g[5 * j + 3] += c * dv_dw;
+                g[5 * j + 4] += c * dv_dM0;
+            }
+            g[npar - 1] += c;
+        }
+        chi2[i] = ok ? (double)acc : NAN;
+        for (int64_t a = 0; a < npar; ++a) grad[a * d->n_sys + i] = ok ? (double)g[a] : NAN;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Ragged batch: system i owns observations obs_off[i]..obs_off[i+1]-1 */
+/* and planets pl_off[i]..pl_off[i+1]-1 (CSR).  Same chi-square.       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    const double *t, *v, *sigma;
+    const int64_t *obs_off;
+    double t0;
+    const double *P, *K, *e, *w, *M0;
+    const int64_t *pl_off;
+    const double *offset, *jitter;
+    int64_t n_sys;
+} oracle_ragged;
+
+void oracle_chisq_ragged(const oracle_ragged *d, double *chi2, int64_t i0, int64_t i1)
+{
+    for (int64_t i = i0; i < i1; ++i) {
+        int ok = finite_d(d->t0);
+        for (int64_t p = d->pl_off[i]; p < d->pl_off[i + 1]; ++p)
+            ok = ok && planet_ok(d->P[p], d->K[p], d->e[p], d->w[p], d->M0[p]);
+        if (d->offset) ok = ok && finite_d(d->offset[i]);
+        if (d->jitter) ok = ok && finite_d(d->jitter[i]) && d->jitter[i] >= 0.0;
+        double s = d->jitter ? d->jitter[i] : 0.0;
+        ld acc = 0.0L;
+        for (int64_t k = d->obs_off[i]; ok && k < d->obs_off[i + 1]; ++k) {
+            ld wk = weight_l(d->sigma[k], d->v[k], d->t[k], s);
+            if (wk == 0.0L) { ok = 0; break; }
+            ld m = 0.0L;
+            for (int64_t p = d->pl_off[i]; p < d->pl_off[i + 1]; ++p)
+                m += planet_rv_l(d->t[k], d->t0, d->P[p], d->K[p], d->e[p], d->w[p], d->M0[p]);
+            if (d->offset) m += (ld)d->offset[i];
+            ld r = m - (ld)d->v[k];
+            acc += wk * r * r;
+        }
+        chi2[i] = ok ? (double)acc : NAN;
+    }
+}

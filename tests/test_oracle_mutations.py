@@ -1,0 +1,45 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's C source (on the CPU,
+in a temporary directory), builds it, and runs the pin suite against the
+broken copy in a subprocess: the suite has to fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from oracle import build as obuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "sign_of_e_cos_omega": ("+ (ld)e * cosl((ld)w));", "- (ld)e * cosl((ld)w));"),
+    "minus_M0": ("ld M = TWO_PI_L * (ld)phi + (ld)M0;", "ld M = TWO_PI_L * (ld)phi - (ld)M0;"),
+    "half_angle_dropped": ("sinl(0.5L * E), sqrtl(1.0L - e) * cosl(0.5L * E)", "sinl(E), sqrtl(1.0L - e) * cosl(E)"),
+    "sqrt_swapped": ("sqrtl(1.0L + e) * sinl(0.5L * E), sqrtl(1.0L - e)", "sqrtl(1.0L - e) * sinl(0.5L * E), sqrtl(1.0L + e)"),
+    "weight_sigma_not_squared": ("ld var = (ld)sigma * (ld)sigma + (ld)s * (ld)s;", "ld var = (ld)sigma + (ld)s * (ld)s;"),
+    "jitter_dropped": ("ld var = (ld)sigma * (ld)sigma + (ld)s * (ld)s;", "ld var = (ld)sigma * (ld)sigma;"),
+    "offset_dropped": ("if (d->offset) sum += (ld)d->offset[i];", ""),
+    "dfde_factor": ("ld dfde = sinl(f) * (2.0L + e * cosl(f)) / one_m_e2;", "ld dfde = sinl(f) * (1.0L + e * cosl(f)) / one_m_e2;"),
+    "dP_sign": ("ld dv_dP = dv_dM0 * (-TWO_PI_L * q / P);", "ld dv_dP = dv_dM0 * (TWO_PI_L * q / P);"),
+    "dfdM_power": ("ld dfdM = ecf * ecf / (one_m_e2 * b);", "ld dfdM = ecf * ecf / one_m_e2;"),
+    "kepler_wrong_sign": ("ld g = E - e * sinl(E) - M;\n        if (g == 0.0L) return E;", "ld g = E + e * sinl(E) - M;\n        if (g == 0.0L) return E;"),
+    "phase_not_binary64": ("double q = dt / P;", "double q = (double)((float)dt / (float)P);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(obuild.SRC).read()
+    assert src.count(old) >= 1, name
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(src.replace(old, new))
+    lib = obuild.build(src=str(mutated), out=str(tmp_path / "libmutant.so"))
+    env = dict(os.environ, KEP_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
