@@ -1,0 +1,261 @@
+"""Benchmark: batched Keplerian RV chi-square on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--rows ...]
+
+One step is one chi-square evaluation of the whole batch through the fused
+mixed-precision kernel (mean anomaly in binary64, Kepler solve, velocity,
+planet sum and compensated chi-square in binary32, binary64 final sum) on the
+workload of 1,048,576 systems x 4 planets x 256 observations, inputs resident
+in device memory.  W untimed steps, then K timed steps bracketed by
+torch.cuda.synchronize(), timed with HIP events on the launch stream.
+
+Printed as ONE JSON line: the headline value (chi-square evaluations per
+second), Kepler solves per second, the binary64 plain kernel on the
+65,536 x 4 x 256 workload and the speed-up over it, the VALU roofline of the
+fused kernel, the CPU oracle on a bounded sample, and one entry per other
+path (gradient, ragged batch, standalone Kepler solve).
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# VALU instruction occupies a SIMD for 4 cycles).  Equals the non-packed FP32
+# FMA rate (78.6 TFLOP/s = 157.3 packed / 2) in instructions, and the FP64
+# vector rate (78.6 TFLOP/s) in instructions.
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+
+# Algorithmic VALU operations per (system, planet, observation) triple of the
+# mixed-precision formulation (operation count of the method as written, each
+# add/mul/fma/convert/compare/select/reciprocal counted once):
+#   phase in binary64                                   10
+#   bracket and starting guess                           4
+#   one Danby iteration (sin, 1-cos, E-sin E polynomials
+#     22, f and derivatives 6, three corrections 12, update 3)   43
+#   velocity (polynomials 22, 1-e cos E, numerator, reciprocal, product 5),
+#     Kahan planet sum 4                                31
+#   per observation: residual, weight, Kahan chi2 (10) / n_pl
+# The eccentricity schedule takes 2 iterations for e <= 0.8525 and 3 up to
+# 0.975; with e ~ U[0, 0.9] the mean is 2 + (0.9 - 0.8525)/0.9 = 2.0528.
+OPS_PHASE, OPS_START, OPS_ITER, OPS_VEL, OPS_OBS = 10, 4, 43, 31, 10
+
+
+def mixed_ops_per_triple(n_pl, mean_iter):
+    return OPS_PHASE + OPS_START + OPS_ITER * mean_iter + OPS_VEL + OPS_OBS / n_pl
+
+
+def mean_iterations(e_max, s2=0.8525, s3=0.975):
+    return 2.0 + max(0.0, min(e_max, s3) - s2) / e_max
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kep_kernels.hip", "kep_device.h", "kep_tables.h"):
+        with open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_b or m_h.group(1) != kernel_source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def timed(fn, steps, warmup, torch):
+    """Mean milliseconds per call of fn over `steps` calls after `warmup` calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return a.elapsed_time(b) / steps, wall
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--rows", default="fp64,grad,ragged,kepler", help="extra paths to time (comma list or 'none')")
+    ap.add_argument("--cpu-sample", type=int, default=16384, help="systems in the CPU oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the systems are independent and the path has no cross-GPU "
+              f"step; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_0812_2976_amd as kp
+    import synth
+
+    dev = torch.device("cuda", 0)
+    kp.load_library()
+    rows = [] if args.rows == "none" else args.rows.split(",")
+
+    def gpu(x):
+        return None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+    def gpu_truth_model(t, t0, truth):
+        cols = [gpu(np.asarray(truth[k], dtype=np.float64)[:, None]) for k in ("P", "K", "e", "w", "M0")]
+        return kp.rv_model(gpu(t), *cols, t0=t0, prec="fp64").cpu().numpy()[0]
+
+    # ------------------------------------------------------------ headline
+    log("generating workload c2 (1,048,576 x 4 x 256)")
+    wl = synth.with_observations(synth.dense("c2"), gpu_truth_model)
+    g = dict(t=gpu(wl.t), v=gpu(wl.v), sigma=gpu(wl.sigma), P=gpu(wl.P), K=gpu(wl.K), e=gpu(wl.e),
+             omega=gpu(wl.w), M0=gpu(wl.M0), t0=wl.t0)
+    out = torch.empty(wl.n_sys, dtype=torch.float64, device=dev)
+    step = lambda: kp.rv_chisq(**g, prec="mixed", out=out)
+    ms, wall = timed(step, args.steps, args.warmup, torch)
+    triples = wl.n_sys * wl.n_pl * wl.n_obs
+    value = wl.n_sys / (ms * 1e-3)
+    log(f"mixed rv_chisq c2: {ms:.3f} ms/launch, {value:.4e} chi2/s")
+    chi2 = out.cpu().numpy()
+    if not np.all(np.isfinite(chi2)):
+        raise RuntimeError("non-finite chi-square in the benchmark batch")
+
+    ops = mixed_ops_per_triple(wl.n_pl, mean_iterations(0.9)) * triples
+    achieved = ops / (ms * 1e-3) / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+                "frac": round(achieved / peak, 4), "traffic": recorded_traffic("rv_chisq_mixed_c2"),
+                "kernel": "k_dense<PolMixed,4,false>", "ops_per_triple": round(ops / triples, 2),
+                "launch_ms": round(ms, 4)}
+
+    result = {
+        "metric": "Kepler solves/s and chi2 evals/s (n_pl=4,n_obs=256) vs FP64 GPU, % VALU peak",
+        "value": value, "unit": "chi2 evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "c2 mixed-precision chi2: n_sys=1048576, n_pl=4, n_obs=256, e~U[0,0.9]",
+                   "n_sys": wl.n_sys, "n_pl": wl.n_pl, "n_obs": wl.n_obs, "precision": "mixed"},
+        "kepler_solves_per_s": triples / (ms * 1e-3),
+        "valu_peak_frac": round(achieved / peak, 4),
+        "roofline": roofline,
+    }
+    del g, out
+
+    # ------------------------------------------------------------ FP64 plain kernel
+    if "fp64" in rows:
+        log("plain FP64 kernel on c1 (65,536 x 4 x 256, 30 fixed iterations)")
+        w1 = synth.with_observations(synth.dense("c1"), gpu_truth_model)
+        g1 = dict(t=gpu(w1.t), v=gpu(w1.v), sigma=gpu(w1.sigma), P=gpu(w1.P), K=gpu(w1.K), e=gpu(w1.e),
+                  omega=gpu(w1.w), M0=gpu(w1.M0), t0=w1.t0)
+        o1 = torch.empty(w1.n_sys, dtype=torch.float64, device=dev)
+        ms64, _ = timed(lambda: kp.rv_chisq(**g1, prec="fp64", out=o1), 3, 1, torch)
+        ms64e, _ = timed(lambda: kp.rv_chisq(**g1, prec="fp64", out=o1, opts=dict(fixed_iter=-1)), 5, 1, torch)
+        msm1, _ = timed(lambda: kp.rv_chisq(**g1, prec="mixed", out=o1), 10, 2, torch)
+        r64 = w1.n_sys / (ms64 * 1e-3)
+        result["fp64_gpu"] = {"workload": "c1 n_sys=65536 n_pl=4 n_obs=256", "chi2_per_s": r64,
+                              "kepler_solves_per_s": r64 * 1024, "launch_ms": ms64,
+                              "early_exit_chi2_per_s": w1.n_sys / (ms64e * 1e-3),
+                              "mixed_same_workload_chi2_per_s": w1.n_sys / (msm1 * 1e-3)}
+        result["speedup_vs_fp64_gpu"] = value / r64
+        result["speedup_vs_fp64_gpu_same_workload"] = (w1.n_sys / (msm1 * 1e-3)) / r64
+        del g1, o1
+
+    # ------------------------------------------------------------ gradient
+    if "grad" in rows:
+        log("gradient on c4 (262,144 x 4 x 256)")
+        w4 = synth.with_observations(synth.dense("c4"), gpu_truth_model)
+        g4 = dict(t=gpu(w4.t), v=gpu(w4.v), sigma=gpu(w4.sigma), P=gpu(w4.P), K=gpu(w4.K), e=gpu(w4.e),
+                  omega=gpu(w4.w), M0=gpu(w4.M0), offset=gpu(w4.offset), t0=w4.t0)
+        o4 = torch.empty(w4.n_sys, dtype=torch.float64, device=dev)
+        gr = torch.empty((5 * w4.n_pl + 1, w4.n_sys), dtype=torch.float64, device=dev)
+        msg, _ = timed(lambda: kp.rv_chisq_grad(**g4, prec="mixed", out=o4, grad=gr), 10, 2, torch)
+        result["gradient_c4"] = {"chi2_grad_per_s": w4.n_sys / (msg * 1e-3), "launch_ms": msg,
+                                 "triples_per_s": w4.n_sys * 1024 / (msg * 1e-3)}
+        del g4, o4, gr
+
+    # ------------------------------------------------------------ ragged
+    if "ragged" in rows:
+        log("ragged c3 (262,144 CSR systems)")
+        rw = synth.ragged_with_observations(synth.ragged(), gpu_truth_model)
+        plan = kp.RaggedPlan(gpu(rw.t), gpu(rw.v), gpu(rw.sigma), gpu(rw.obs_off), gpu(rw.P), gpu(rw.K),
+                             gpu(rw.e), gpu(rw.w), gpu(rw.M0), gpu(rw.pl_off), t0=rw.t0)
+        o3 = torch.empty(rw.n_sys, dtype=torch.float64, device=dev)
+        msr, _ = timed(lambda: plan(o3), 10, 2, torch)
+        info = plan.info()
+        result["ragged_c3"] = {"chi2_per_s": rw.n_sys / (msr * 1e-3), "launch_ms": msr,
+                               "kepler_solves_per_s": info["triples"] / (msr * 1e-3), "triples": info["triples"],
+                               "plan": {k: info[k] for k in ("block_threads", "blocks", "sys_per_batch", "tuned")}}
+        plan.close()
+        del o3
+
+    # ------------------------------------------------------------ Kepler only
+    if "kepler" in rows:
+        log("standalone Kepler solve (2^26 pairs)")
+        M, e = synth.kepler_pairs(1 << 26)
+        Mg, eg = gpu(M), gpu(e)
+        Eg = torch.empty_like(Mg)
+        msk, _ = timed(lambda: kp.kepler_solve(Mg, eg, prec="mixed", out=Eg), 10, 2, torch)
+        msk64, _ = timed(lambda: kp.kepler_solve(Mg, eg, prec="fp64", out=Eg), 3, 1, torch)
+        n = M.size
+        result["kepler_solve"] = {"n": n, "mixed_solves_per_s": n / (msk * 1e-3), "mixed_launch_ms": msk,
+                                  "mixed_hbm_GBps": 24 * n / (msk * 1e-3) / 1e9,
+                                  "fp64_solves_per_s": n / (msk64 * 1e-3), "fp64_launch_ms": msk64}
+        del Mg, eg, Eg
+
+    # ------------------------------------------------------------ CPU oracle
+    if not args.no_cpu:
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+
+        n = min(args.cpu_sample, wl.n_sys)
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            cores = os.cpu_count() or 1
+        cores = max(1, min(cores, 16))
+        d = oracle.Dense(wl.t, wl.v, wl.sigma, wl.P[:, :n], wl.K[:, :n], wl.e[:, :n], wl.w[:, :n], wl.M0[:, :n],
+                         None, None, wl.t0)
+        oracle.lib()
+        bounds = np.linspace(0, n, cores * 4 + 1).astype(int)
+        out_c = np.full(n, np.nan)
+        log(f"CPU oracle on {n} systems with {cores} threads")
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda ab: oracle.chisq(d, int(ab[0]), int(ab[1]), out=out_c), zip(bounds[:-1], bounds[1:])))
+        dt = time.perf_counter() - t0
+        rel = np.max(np.abs(chi2[:n] - out_c) / np.maximum(out_c, 1.0))
+        result["cpu_baseline"] = {"value": n / dt, "unit": "chi2 evals/s", "cores": cores, "kind": "oracle",
+                                  "sample": f"first {n} systems of the same c2 batch ({n * 1024} Kepler solves), "
+                                            f"{dt:.2f} s wall",
+                                  "gpu_vs_oracle_max_rel_err": float(rel)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * kepler.h -- C ABI of the MI355X (gfx950) Keplerian radial-velocity library.
+ *
+ * The library evaluates, for a batch of planetary-system models, the radial
+ * velocity of a star perturbed by n_pl planets on independent Keplerian
+ * orbits and the chi-square of each model against one set of observations,
+ * following Ford (2008), "Parallel Algorithm for Solving Kepler's Equation on
+ * Graphics Processing Units" (arXiv:0812.2976):
+ *
+ *   mean anomaly   M_ijk = 2 pi frac((t_k - t0) / P_ij) + M0_ij        Sec. 2.1 Eq. 4, Sec. 4.2 Eq. 6
+ *   Kepler         M = E - e sin E, solved by Danby's quartic iteration Sec. 4.3, Eq. 1
+ *   velocity       v_ijk = K [cos(omega + f) + e cos omega]             Sec. 2.1 Eq. 3 (standard form)
+ *   planet sum     model_ik = sum_j v_ijk + gamma_i                     Sec. 2.1 Eq. 2
+ *   chi-square     chi2_i = sum_k (model_ik - v_k)^2 / (sigma_k^2 + s_i^2)   Sec. 2.2 Eq. 5
+ *
+ * Conventions that the paper leaves open and this library fixes:
+ *   - M0 enters with a plus sign (Eq. 4; Eq. 6 prints a minus) and the epoch
+ *     t0 is an argument (the paper uses t0 = 0).
+ *   - omega is the argument of pericentre and K the usual semi-amplitude; the
+ *     printed Eq. 3 mixes conventions and is read as the standard velocity.
+ *   - s_i is one jitter per system (Eq. 5 writes sigma_j); gamma_i is an
+ *     optional per-system velocity offset.  Both default to 0 (NULL pointer).
+ *
+ * Memory.  Every array pointer is a DEVICE pointer owned by the caller; the
+ * library never frees or retains one beyond the call (ragged plans keep the
+ * pointers they were built with, see below).  Arrays are binary64, densely
+ * packed, naturally aligned.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  The batch calls enqueue their kernels on it and return without
+ * waiting for them; they allocate nothing and never synchronise.
+ *
+ * Errors.  Argument and shape errors detected on the host return a non-zero
+ * kep_status before anything is launched and set a message readable with
+ * kep_last_error().  A launch failure returns KEP_ERR_LAUNCH.  Data outside
+ * the model's domain is NOT an error: e outside [0, 1), P <= 0, a non-finite
+ * parameter, t, v or sigma, sigma < 0 or sigma^2 + s^2 = 0 make that system's
+ * chi-square (and gradient, and model velocities) NaN, without affecting any
+ * other system.  Accuracy is stated for e <= 0.99 (the paper's range, Sec. 4.3).
+ *
+ * Precision (kep_prec):
+ *   KEP_FP64  plain binary64 everywhere: IEEE-rounded quotient (t - t0)/P,
+ *             Danby iteration with a fixed 30 steps by default, binary64 sums.
+ *   KEP_MIXED the paper's mixed precision (Sec. 5.1): the orbital phase
+ *             (t - t0)/P reduced modulo one orbit is computed in binary64,
+ *             Kepler's equation, the velocity and the planet sum in binary32
+ *             (compensated, Sec. 4.4), chi-square accumulated in binary32 with
+ *             Kahan compensation and finished in binary64.
+ */
+#ifndef KEPLER_MI355X_H
+#define KEPLER_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KEP_MAX_PL 8          /* planets per system accepted by every entry point */
+#define KEP_ABI_VERSION 1
+
+typedef enum kep_status {
+    KEP_OK = 0,
+    KEP_ERR_ARG = 1,          /* null pointer, negative size, bad enum or option */
+    KEP_ERR_SHAPE = 2,        /* sizes inconsistent with each other (n_pl, CSR offsets) */
+    KEP_ERR_DEVICE = 3,       /* no usable HIP device or a HIP runtime call failed */
+    KEP_ERR_LAUNCH = 4,       /* a kernel launch was rejected */
+    KEP_ERR_UNSUPPORTED = 5   /* valid request this build does not implement */
+} kep_status;
+
+typedef enum kep_prec {
+    KEP_FP64 = 0,
+    KEP_MIXED = 1
+} kep_prec;
+
+/* Observations shared by every system (Sec. 4.1): times t [d], velocities v
+   [m/s] and uncertainties sigma [m/s], each of length n_obs >= 0; t0 is the
+   epoch of the mean anomaly. */
+typedef struct kep_obs {
+    const double *t, *v, *sigma;
+    int64_t n_obs;
+    double t0;
+} kep_obs;
+
+/* Model parameters (Sec. 4.1: n_sys x n_pl x 5 values).  Each of P [d],
+   K [m/s], e, omega [rad], M0 [rad] is a plane of n_pl * n_sys values laid out
+   [n_pl][n_sys] (system index fastest, so consecutive systems are adjacent in
+   memory).  offset (gamma, m/s) and jitter (s, m/s) are [n_sys] or NULL.
+   1 <= n_pl <= KEP_MAX_PL, n_sys >= 0. */
+typedef struct kep_params {
+    const double *P, *K, *e, *omega, *M0;
+    const double *offset, *jitter;
+    int64_t n_sys, n_pl;
+} kep_params;
+
+/* Options; pass NULL for the defaults.  A zero field means "default".
+   fixed_iter  > 0: exactly this many Danby iterations for every solve.
+               = 0: KEP_FP64 uses 30 (the plain kernel); KEP_MIXED uses the
+                    eccentricity schedule (2 iterations for e <= 0.8525, 3 up to
+                    0.975, 4 up to 0.9955, 5 up to 0.999, then a convergence
+                    test), derived offline for a 1e-9 rad worst-case error.
+               < 0: early exit in both precisions (schedule, then convergence test).
+   max_iter    cap of the convergence-tested iteration (default 10, Sec. 4.3).
+   block_threads, blocks_per_cu: launch shape (multiples of 64 / >= 1); 0 = tuned or built-in default. */
+typedef struct kep_options {
+    int32_t fixed_iter;
+    int32_t max_iter;
+    int32_t block_threads;
+    int32_t blocks_per_cu;
+} kep_options;
+
+/* Kepler's equation (Eq. 1; the paper's Kepler-only mode, Sec. 5.2): for
+   i < n, E[i] is the real root of E - e[i] sin E = M[i].  M may be any finite
+   value (E is returned on the same branch, E(M + 2 pi) = E(M) + 2 pi); e[i]
+   outside [0, 1) or a non-finite input gives NaN.  M, e, E are device arrays of
+   n >= 0 doubles; E may alias neither input. */
+kep_status kepler_solve(const double *M, const double *e, double *E, int64_t n,
+                        kep_prec prec, const kep_options *opts, void *stream);
+
+/* Model velocities (Eq. 2 plus offset): v_model[i * n_obs + k] = model_ik for
+   every system i and observation k.  obs->v and obs->sigma are not read and
+   may be NULL. */
+kep_status rv_model(const kep_obs *obs, const kep_params *par, double *v_model,
+                    kep_prec prec, const kep_options *opts, void *stream);
+
+/* Chi-square of every system (Eq. 5): chi2[i], i < n_sys. */
+kep_status rv_chisq(const kep_obs *obs, const kep_params *par, double *chi2,
+                    kep_prec prec, const kep_options *opts, void *stream);
+
+/* Chi-square and its gradient (the parallel partial derivatives asked for in
+   Sec. 6), by the implicit-function adjoint of Kepler's equation:
+   dE/dM = 1/(1 - e cos E), dE/de = sin E/(1 - e cos E); no iteration is
+   differentiated.  grad is [(5 * n_pl + 1)][n_sys]: rows 5j..5j+4 are
+   d chi2 / d(P_j, K_j, e_j, omega_j, M0_j), the last row d chi2 / d gamma.
+   The jitter is an input, not differentiated. */
+kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2, double *grad,
+                         kep_prec prec, const kep_options *opts, void *stream);
+
+/* ---- ragged batches (systems of uneven n_pl and n_obs, CSR-packed) ----
+   System i owns observations obs_off[i] .. obs_off[i+1]-1 of t, v, sigma and
+   planets pl_off[i] .. pl_off[i+1]-1 of P, K, e, omega, M0 (flat arrays of
+   n_pl_total values).  obs_off and pl_off are device arrays of n_sys + 1
+   non-decreasing int64 starting at 0 and ending at n_obs_total / n_pl_total;
+   every system needs 1 <= n_pl <= KEP_MAX_PL planets and n_obs >= 0. */
+typedef struct kep_obs_csr {
+    const double *t, *v, *sigma;
+    const int64_t *obs_off;
+    int64_t n_obs_total;
+    double t0;
+} kep_obs_csr;
+
+typedef struct kep_params_csr {
+    const double *P, *K, *e, *omega, *M0;
+    const int64_t *pl_off;
+    const double *offset, *jitter;
+    int64_t n_sys, n_pl_total;
+} kep_params_csr;
+
+typedef struct kep_plan kep_plan;   /* opaque; owned by the library */
+
+/* Build a plan for one ragged batch: copies the CSR offsets to the host,
+   checks them, orders the systems by work (n_pl * n_obs, largest first),
+   picks the launch shape (the autotuner times candidates on this batch unless
+   opts fixes block_threads), and records {queue reset, persistent kernel} as a
+   HIP graph.  May allocate and synchronises `stream`.  The plan keeps the
+   input pointers: their contents may change between calls, their addresses
+   and sizes may not.  Only KEP_MIXED is implemented for ragged batches
+   (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */
+kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, kep_prec prec,
+                           const kep_options *opts, void *stream, kep_plan **out);
+
+/* Chi-square of every system of the plan's batch into chi2[n_sys] (one graph
+   launch on `stream`; does not allocate or synchronise).  Calls on one plan
+   must not overlap in time (they share the plan's work-queue counter). */
+kep_status rv_chisq_ragged(kep_plan *plan, double *chi2, void *stream);
+
+/* Same work launched directly, without the graph (for comparison). */
+kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream);
+
+typedef struct kep_plan_info {
+    int64_t n_sys, n_obs_total, n_pl_total, triples;
+    int32_t block_threads, blocks, sys_per_batch, tuned;
+    double tuned_ms;          /* best candidate's time during tuning, 0 if not tuned */
+} kep_plan_info;
+
+kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info);
+
+void kep_plan_destroy(kep_plan *plan);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *kep_last_error(void);
+
+int kep_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KEPLER_MI355X_H */

@@ -68,6 +68,8 @@ def lib():
             f.argtypes = [ctypes.POINTER(_Dense), _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_grad.restype = None
         L.oracle_chisq_grad.argtypes = [ctypes.POINTER(_Dense), _D, _D, ctypes.c_int64, ctypes.c_int64]
+        L.oracle_chisq_grad_scales.restype = None
+        L.oracle_chisq_grad_scales.argtypes = [ctypes.POINTER(_Dense), _D, _D, _D, _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_ragged.restype = None
         L.oracle_chisq_ragged.argtypes = [ctypes.POINTER(_Ragged), _D, ctypes.c_int64, ctypes.c_int64]
         _LIB = L
@@ -148,6 +150,18 @@ def chisq_grad(d: Dense, i0=0, i1=None):
     grad = np.full((5 * d.n_pl + 1, d.n_sys), np.nan)
     lib().oracle_chisq_grad(ctypes.byref(d._s), _ptr(chi2), _ptr(grad), i0, i1)
     return chi2, grad
+
+
+def chisq_grad_scales(d: Dense, i0=0, i1=None):
+    """(chi2, grad, scale_r, scale_1): scale_r = sum_k |2 w r dv/dtheta|, scale_1 = sum_k 2 w |dv/dtheta|
+    per gradient component; a residual error dr and a relative error eps per term change the gradient
+    by at most dr * scale_1 + eps * scale_r."""
+    i0, i1 = d._range(i0, i1)
+    shp = (5 * d.n_pl + 1, d.n_sys)
+    chi2 = np.full(d.n_sys, np.nan)
+    grad, sr, s1 = np.full(shp, np.nan), np.full(shp, np.nan), np.full(shp, np.nan)
+    lib().oracle_chisq_grad_scales(ctypes.byref(d._s), _ptr(chi2), _ptr(grad), _ptr(sr), _ptr(s1), i0, i1)
+    return chi2, grad, sr, s1
 
 
 class Ragged:

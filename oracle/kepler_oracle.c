@@ -233,14 +233,15 @@ void oracle_chisq(const oracle_dense *d, double *chi2, int64_t i0, int64_t i1)
 /* grad layout: [(5*n_pl + 1)][n_sys], planet j uses rows 5j..5j+4 in  */
 /* the order P, K, e, omega, M0; the last row is the offset.           */
 /* ------------------------------------------------------------------ */
-void oracle_chisq_grad(const oracle_dense *d, double *chi2, double *grad, int64_t i0, int64_t i1)
+static void chisq_grad_impl(const oracle_dense *d, double *chi2, double *grad, double *scale_r,
+                            double *scale_1, int64_t i0, int64_t i1)
 {
     const int64_t npar = 5 * d->n_pl + 1;
-    ld g[5 * 64 + 1];
+    ld g[5 * 64 + 1], sr[5 * 64 + 1], s1[5 * 64 + 1];
     for (int64_t i = i0; i < i1; ++i) {
         int ok = system_ok(d, i) && d->n_pl <= 64;
         double s = d->jitter ? d->jitter[i] : 0.0;
-        for (int64_t a = 0; a < npar; ++a) g[a] = 0.0L;
+        for (int64_t a = 0; a < npar; ++a) g[a] = sr[a] = s1[a] = 0.0L;
         ld acc = 0.0L;
         for (int64_t k = 0; ok && k < d->n_obs; ++k) {
             ld wk = weight_l(d->sigma[k], d->v[k], d->t[k], s);
@@ -266,17 +267,39 @@ void oracle_chisq_grad(const oracle_dense *d, double *chi2, double *grad, int64_
                 ld dv_dM0 = -K * swf * dfdM;
                 ld dv_dP = dv_dM0 * (-TWO_PI_L * q / P);
                 ld dv_de = K * cosl(om) - K * swf * dfde;
-                g[5 * j + 0] += c * dv_dP;
-                g[5 * j + 1] += c * dv_dK;
-                g[5 * j + 2] += c * dv_de;
-                g[5 * j + 3] += c * dv_dw;
-                g[5 * j + 4] += c * dv_dM0;
+                const ld dv[5] = {dv_dP, dv_dK, dv_de, dv_dw, dv_dM0};
+                for (int a = 0; a < 5; ++a) {
+                    g[5 * j + a] += c * dv[a];
+                    sr[5 * j + a] += fabsl(c * dv[a]);
+                    s1[5 * j + a] += 2.0L * wk * fabsl(dv[a]);
+                }
             }
             g[npar - 1] += c;
+            sr[npar - 1] += fabsl(c);
+            s1[npar - 1] += 2.0L * wk;
         }
         chi2[i] = ok ? (double)acc : NAN;
-        for (int64_t a = 0; a < npar; ++a) grad[a * d->n_sys + i] = ok ? (double)g[a] : NAN;
+        for (int64_t a = 0; a < npar; ++a) {
+            grad[a * d->n_sys + i] = ok ? (double)g[a] : NAN;
+            if (scale_r) scale_r[a * d->n_sys + i] = ok ? (double)sr[a] : NAN;
+            if (scale_1) scale_1[a * d->n_sys + i] = ok ? (double)s1[a] : NAN;
+        }
     }
+}
+
+void oracle_chisq_grad(const oracle_dense *d, double *chi2, double *grad, int64_t i0, int64_t i1)
+{
+    chisq_grad_impl(d, chi2, grad, NULL, NULL, i0, i1);
+}
+
+/* Error scales of the gradient (for stating tolerances): per component,
+   scale_r = sum_k |2 w_k r_k dv/dtheta| and scale_1 = sum_k 2 w_k |dv/dtheta|,
+   so a residual error dr and a relative error eps in each term move the
+   gradient by at most dr * scale_1 + eps * scale_r. */
+void oracle_chisq_grad_scales(const oracle_dense *d, double *chi2, double *grad, double *scale_r,
+                              double *scale_1, int64_t i0, int64_t i1)
+{
+    chisq_grad_impl(d, chi2, grad, scale_r, scale_1, i0, i1);
 }
 
 /* ------------------------------------------------------------------ */

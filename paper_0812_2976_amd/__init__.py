@@ -1,0 +1,312 @@
+"""MI355X (gfx950) Keplerian radial-velocity chi-square — Python binding.
+
+A thin ctypes layer over ``libkepler.so`` (C ABI in ``include/kepler.h``).
+Every computation runs in the library's HIP kernels; this module only checks
+and marshals torch tensors (device memory) and passes torch's current HIP
+stream.  There is no CPU fallback: without the built library or a GPU every
+call raises.
+
+Functions keep the C names:
+  kepler_solve(M, e)                       Kepler's equation (Eq. 1)
+  rv_model(t, P, K, e, omega, M0, ...)     model velocities (Eq. 2, 3)
+  rv_chisq(t, v, sigma, P, K, e, ...)      chi-square (Eq. 5)
+  rv_chisq_grad(...)                       chi-square and its gradient
+  RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
+  RVChiSq.apply(...)                       torch.autograd.Function over rv_chisq_grad
+Parameter planes are float64 CUDA tensors shaped (n_pl, n_sys) (system index
+fastest); observations are 1-D float64 CUDA tensors.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkepler.so")
+
+KEP_FP64, KEP_MIXED = 0, 1
+KEP_MAX_PL = 8
+_PREC = {"fp64": KEP_FP64, "f64": KEP_FP64, "double": KEP_FP64, "mixed": KEP_MIXED}
+_STATUS = {0: "KEP_OK", 1: "KEP_ERR_ARG", 2: "KEP_ERR_SHAPE", 3: "KEP_ERR_DEVICE", 4: "KEP_ERR_LAUNCH",
+           5: "KEP_ERR_UNSUPPORTED"}
+
+_D = ctypes.c_void_p
+
+
+class KepObs(ctypes.Structure):
+    _fields_ = [("t", _D), ("v", _D), ("sigma", _D), ("n_obs", ctypes.c_int64), ("t0", ctypes.c_double)]
+
+
+class KepParams(ctypes.Structure):
+    _fields_ = [("P", _D), ("K", _D), ("e", _D), ("omega", _D), ("M0", _D), ("offset", _D), ("jitter", _D),
+                ("n_sys", ctypes.c_int64), ("n_pl", ctypes.c_int64)]
+
+
+class KepOptions(ctypes.Structure):
+    _fields_ = [("fixed_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+
+class KepObsCSR(ctypes.Structure):
+    _fields_ = [("t", _D), ("v", _D), ("sigma", _D), ("obs_off", _D), ("n_obs_total", ctypes.c_int64),
+                ("t0", ctypes.c_double)]
+
+
+class KepParamsCSR(ctypes.Structure):
+    _fields_ = [("P", _D), ("K", _D), ("e", _D), ("omega", _D), ("M0", _D), ("pl_off", _D),
+                ("offset", _D), ("jitter", _D), ("n_sys", ctypes.c_int64), ("n_pl_total", ctypes.c_int64)]
+
+
+class KepPlanInfo(ctypes.Structure):
+    _fields_ = [("n_sys", ctypes.c_int64), ("n_obs_total", ctypes.c_int64), ("n_pl_total", ctypes.c_int64),
+                ("triples", ctypes.c_int64), ("block_threads", ctypes.c_int32), ("blocks", ctypes.c_int32),
+                ("sys_per_batch", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tuned_ms", ctypes.c_double)]
+
+
+class KeplerError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "kep_plan_ragged", "rv_chisq_ragged",
+           "rv_chisq_ragged_direct", "kep_plan_get_info", "kep_plan_destroy", "kep_last_error", "kep_abi_version")
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkepler.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_0812_2976_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.kepler_solve.argtypes = [_D, _D, _D, ctypes.c_int64, ctypes.c_int, P(KepOptions), _D]
+    for name in ("rv_model", "rv_chisq"):
+        getattr(L, name).argtypes = [P(KepObs), P(KepParams), _D, ctypes.c_int, P(KepOptions), _D]
+    L.rv_chisq_grad.argtypes = [P(KepObs), P(KepParams), _D, _D, ctypes.c_int, P(KepOptions), _D]
+    L.kep_plan_ragged.argtypes = [P(KepObsCSR), P(KepParamsCSR), ctypes.c_int, P(KepOptions), _D, P(_D)]
+    L.rv_chisq_ragged.argtypes = [_D, _D, _D]
+    L.rv_chisq_ragged_direct.argtypes = [_D, _D, _D]
+    L.kep_plan_get_info.argtypes = [_D, P(KepPlanInfo)]
+    L.kep_plan_destroy.argtypes = [_D]
+    L.kep_plan_destroy.restype = None
+    L.kep_last_error.restype = ctypes.c_char_p
+    L.kep_last_error.argtypes = []
+    L.kep_abi_version.restype = ctypes.c_int
+    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "kep_plan_ragged", "rv_chisq_ragged",
+                 "rv_chisq_ragged_direct", "kep_plan_get_info"):
+        getattr(L, name).restype = ctypes.c_int
+    _LIB = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise KeplerError(status, load_library().kep_last_error().decode())
+
+
+def _prec(prec):
+    if isinstance(prec, int):
+        return prec
+    try:
+        return _PREC[prec]
+    except KeyError:
+        raise ValueError(f"unknown precision {prec!r}; use 'fp64' or 'mixed'") from None
+
+
+def _opts(opts):
+    if opts is None:
+        return None
+    if isinstance(opts, KepOptions):
+        return ctypes.byref(opts)
+    o = KepOptions(int(opts.get("fixed_iter", 0)), int(opts.get("max_iter", 0)),
+                   int(opts.get("block_threads", 0)), int(opts.get("blocks_per_cu", 0)))
+    return ctypes.byref(o)
+
+
+def _dev(x, name, ndim=None, dtype=torch.float64):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor on the GPU")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be on the GPU (got {x.device}); there is no CPU path")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {x.dtype})")
+    if ndim is not None and x.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions (got shape {tuple(x.shape)})")
+    return x.contiguous()
+
+
+def _opt_dev(x, name, n):
+    if x is None:
+        return None
+    x = _dev(x, name, 1)
+    if x.numel() != n:
+        raise ValueError(f"{name} must have n_sys = {n} elements")
+    return x
+
+
+def _ptr(x):
+    return None if x is None else x.data_ptr()
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _planes(P, K, e, omega, M0):
+    planes = [_dev(x, n, 2) for x, n in zip((P, K, e, omega, M0), ("P", "K", "e", "omega", "M0"))]
+    shape = planes[0].shape
+    for x in planes:
+        if x.shape != shape:
+            raise ValueError("P, K, e, omega, M0 must share the shape (n_pl, n_sys)")
+    return planes
+
+
+def kepler_solve(M, e, prec="mixed", out=None, opts=None):
+    """E with E - e sin E = M, elementwise (Eq. 1)."""
+    M = _dev(M, "M")
+    e = _dev(e, "e")
+    if M.shape != e.shape:
+        raise ValueError("M and e must have the same shape")
+    if out is None:
+        out = torch.empty_like(M)
+    L = load_library()
+    _check(L.kepler_solve(M.data_ptr(), e.data_ptr(), out.data_ptr(), M.numel(), _prec(prec), _opts(opts),
+                          _stream(M.device)))
+    return out
+
+
+def _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0):
+    P, K, e, omega, M0 = _planes(P, K, e, omega, M0)
+    n_pl, n_sys = P.shape
+    t = _dev(t, "t", 1)
+    v = None if v is None else _dev(v, "v", 1)
+    sigma = None if sigma is None else _dev(sigma, "sigma", 1)
+    for x, nm in ((v, "v"), (sigma, "sigma")):
+        if x is not None and x.numel() != t.numel():
+            raise ValueError(f"{nm} must have n_obs = {t.numel()} elements")
+    offset = _opt_dev(offset, "offset", n_sys)
+    jitter = _opt_dev(jitter, "jitter", n_sys)
+    obs = KepObs(t.data_ptr(), _ptr(v), _ptr(sigma), t.numel(), float(t0))
+    par = KepParams(P.data_ptr(), K.data_ptr(), e.data_ptr(), omega.data_ptr(), M0.data_ptr(), _ptr(offset),
+                    _ptr(jitter), n_sys, n_pl)
+    keep = (t, v, sigma, P, K, e, omega, M0, offset, jitter)
+    return obs, par, keep, t.device
+
+
+def rv_model(t, P, K, e, omega, M0, offset=None, t0=0.0, prec="mixed", out=None, opts=None):
+    """Model velocities (n_sys, n_obs): sum over planets of the Keplerian velocity plus offset."""
+    obs, par, keep, dev = _obs_params(t, None, None, P, K, e, omega, M0, offset, None, t0)
+    if out is None:
+        out = torch.empty((par.n_sys, obs.n_obs), dtype=torch.float64, device=dev)
+    L = load_library()
+    _check(L.rv_model(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec), _opts(opts), _stream(dev)))
+    return out
+
+
+def rv_chisq(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.0, prec="mixed", out=None, opts=None):
+    """chi-square per system (Eq. 5), shape (n_sys,)."""
+    obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
+    if out is None:
+        out = torch.empty(par.n_sys, dtype=torch.float64, device=dev)
+    L = load_library()
+    _check(L.rv_chisq(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec), _opts(opts), _stream(dev)))
+    return out
+
+
+def rv_chisq_grad(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.0, prec="mixed",
+                  out=None, grad=None, opts=None):
+    """(chi2 (n_sys,), grad (5 n_pl + 1, n_sys)); rows P, K, e, omega, M0 per planet, then offset."""
+    obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
+    if out is None:
+        out = torch.empty(par.n_sys, dtype=torch.float64, device=dev)
+    if grad is None:
+        grad = torch.empty((5 * par.n_pl + 1, par.n_sys), dtype=torch.float64, device=dev)
+    L = load_library()
+    _check(L.rv_chisq_grad(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), grad.data_ptr(), _prec(prec),
+                           _opts(opts), _stream(dev)))
+    return out, grad
+
+
+class RaggedPlan:
+    """Plan for a CSR batch (one persistent kernel replayed from a HIP graph).
+    Holds references to the input tensors, whose addresses the plan keeps."""
+
+    def __init__(self, t, v, sigma, obs_off, P, K, e, omega, M0, pl_off, offset=None, jitter=None, t0=0.0,
+                 prec="mixed", opts=None):
+        self.t, self.v, self.sigma = (_dev(x, n, 1) for x, n in ((t, "t"), (v, "v"), (sigma, "sigma")))
+        self.obs_off = _dev(obs_off, "obs_off", 1, torch.int64)
+        self.pl_off = _dev(pl_off, "pl_off", 1, torch.int64)
+        self.P, self.K, self.e, self.omega, self.M0 = (_dev(x, n, 1) for x, n in
+                                                      ((P, "P"), (K, "K"), (e, "e"), (omega, "omega"), (M0, "M0")))
+        self.n_sys = self.obs_off.numel() - 1
+        self.offset = _opt_dev(offset, "offset", self.n_sys)
+        self.jitter = _opt_dev(jitter, "jitter", self.n_sys)
+        self.device = self.t.device
+        obs = KepObsCSR(self.t.data_ptr(), self.v.data_ptr(), self.sigma.data_ptr(), self.obs_off.data_ptr(),
+                        self.t.numel(), float(t0))
+        par = KepParamsCSR(self.P.data_ptr(), self.K.data_ptr(), self.e.data_ptr(), self.omega.data_ptr(),
+                           self.M0.data_ptr(), self.pl_off.data_ptr(), _ptr(self.offset), _ptr(self.jitter),
+                           self.n_sys, self.P.numel())
+        L = load_library()
+        h = ctypes.c_void_p()
+        _check(L.kep_plan_ragged(ctypes.byref(obs), ctypes.byref(par), _prec(prec), _opts(opts),
+                                 _stream(self.device), ctypes.byref(h)))
+        self._h = h
+
+    def __call__(self, out=None):
+        """chi-square per system through the plan's HIP graph."""
+        if out is None:
+            out = torch.empty(self.n_sys, dtype=torch.float64, device=self.device)
+        _check(load_library().rv_chisq_ragged(self._h, out.data_ptr(), _stream(self.device)))
+        return out
+
+    def direct(self, out=None):
+        """Same computation launched directly (no graph)."""
+        if out is None:
+            out = torch.empty(self.n_sys, dtype=torch.float64, device=self.device)
+        _check(load_library().rv_chisq_ragged_direct(self._h, out.data_ptr(), _stream(self.device)))
+        return out
+
+    def info(self):
+        i = KepPlanInfo()
+        _check(load_library().kep_plan_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in KepPlanInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().kep_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RVChiSq(torch.autograd.Function):
+    """chi-square per system with a backward pass from the implicit-function
+    adjoint kernel (rv_chisq_grad); the forward computes both in one launch.
+    Differentiable inputs: P, K, e, omega, M0 (n_pl, n_sys) and offset (n_sys,)."""
+
+    @staticmethod
+    def forward(ctx, P, K, e, omega, M0, offset, t, v, sigma, jitter=None, t0=0.0, prec="mixed"):
+        chi2, grad = rv_chisq_grad(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0, prec)
+        ctx.save_for_backward(grad)
+        ctx.n_pl = P.shape[0]
+        return chi2
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        n_pl = ctx.n_pl
+        gp = grad[:5 * n_pl].view(n_pl, 5, -1) * g[None, None, :]
+        d = [gp[:, i, :] for i in range(5)]
+        doff = grad[5 * n_pl] * g
+        return d[0], d[1], d[2], d[3], d[4], doff, None, None, None, None, None, None

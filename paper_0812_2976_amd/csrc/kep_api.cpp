@@ -1,0 +1,552 @@
+// C ABI of the library (include/kepler.h): argument checking, launch shape,
+// ragged plans (work ordering, autotuning, HIP graph) and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kep_internal.h"
+#include "kepler.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+kep_status fail(kep_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+kep_status launch_status(hipError_t err, const char *what)
+{
+    if (err == hipSuccess) return KEP_OK;
+    return fail(KEP_ERR_LAUNCH, "%s: kernel launch failed: %s", what, hipGetErrorString(err));
+}
+
+struct Opts {
+    int fixed_iter = 0;
+    int max_iter = 10;
+    kep::LaunchShape shape{0, 0};
+};
+
+kep_status parse_opts(const kep_options *o, const char *fn, Opts &out)
+{
+    out = Opts();
+    if (!o) return KEP_OK;
+    if (o->fixed_iter > 1000) return fail(KEP_ERR_ARG, "%s: fixed_iter = %d exceeds 1000", fn, o->fixed_iter);
+    if (o->max_iter < 0 || o->max_iter > 1000)
+        return fail(KEP_ERR_ARG, "%s: max_iter = %d outside [0, 1000]", fn, o->max_iter);
+    if (o->block_threads < 0 || o->block_threads > 256 || o->block_threads % 64 != 0)
+        return fail(KEP_ERR_ARG, "%s: block_threads = %d must be 0 or a multiple of 64 up to 256", fn,
+                    o->block_threads);
+    if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64)
+        return fail(KEP_ERR_ARG, "%s: blocks_per_cu = %d outside [0, 64]", fn, o->blocks_per_cu);
+    out.fixed_iter = o->fixed_iter;
+    if (o->max_iter > 0) out.max_iter = o->max_iter;
+    out.shape.block = o->block_threads;
+    out.shape.blocks_per_cu = o->blocks_per_cu;
+    return KEP_OK;
+}
+
+kep_status check_prec(kep_prec p, const char *fn)
+{
+    if (p != KEP_FP64 && p != KEP_MIXED) return fail(KEP_ERR_ARG, "%s: unknown precision %d", fn, (int)p);
+    return KEP_OK;
+}
+
+kep_status check_device(const char *fn)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(KEP_ERR_DEVICE, "%s: no HIP device", fn);
+    return KEP_OK;
+}
+
+bool mul_overflows(int64_t a, int64_t b) { return a != 0 && b > INT64_MAX / a; }
+
+kep_status check_dense(const kep_obs *obs, const kep_params *par, bool need_v, const char *fn)
+{
+    if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
+    if (obs->n_obs < 0) return fail(KEP_ERR_ARG, "%s: n_obs = %lld < 0", fn, (long long)obs->n_obs);
+    if (par->n_sys < 0) return fail(KEP_ERR_ARG, "%s: n_sys = %lld < 0", fn, (long long)par->n_sys);
+    if (par->n_pl < 1 || par->n_pl > KEP_MAX_PL)
+        return fail(KEP_ERR_SHAPE, "%s: n_pl = %lld outside [1, %d]", fn, (long long)par->n_pl, KEP_MAX_PL);
+    if (mul_overflows(par->n_sys, par->n_pl) || mul_overflows(par->n_sys, obs->n_obs) ||
+        mul_overflows(par->n_sys, 5 * par->n_pl + 1))
+        return fail(KEP_ERR_SHAPE, "%s: n_sys x n_pl or n_sys x n_obs overflows", fn);
+    if (obs->n_obs > 0 && !obs->t) return fail(KEP_ERR_ARG, "%s: obs->t is NULL", fn);
+    if (need_v && obs->n_obs > 0 && (!obs->v || !obs->sigma))
+        return fail(KEP_ERR_ARG, "%s: obs->v and obs->sigma must not be NULL", fn);
+    if (par->n_sys > 0 && (!par->P || !par->K || !par->e || !par->omega || !par->M0))
+        return fail(KEP_ERR_ARG, "%s: a parameter plane (P, K, e, omega, M0) is NULL", fn);
+    return KEP_OK;
+}
+
+kep::DenseArgs make_dense(const kep_obs *obs, const kep_params *par, const Opts &o, double *out, double *grad)
+{
+    kep::DenseArgs a;
+    a.t = obs->t;
+    a.v = obs->v;
+    a.sigma = obs->sigma;
+    a.n_obs = obs->n_obs;
+    a.t0 = obs->t0;
+    a.P = par->P;
+    a.K = par->K;
+    a.e = par->e;
+    a.w = par->omega;
+    a.M0 = par->M0;
+    a.offset = par->offset;
+    a.jitter = par->jitter;
+    a.n_sys = par->n_sys;
+    a.n_pl = (int)par->n_pl;
+    a.sb = 1;
+    a.out = out;
+    a.grad = grad;
+    a.fixed_iter = o.fixed_iter;
+    a.max_iter = o.max_iter;
+    return a;
+}
+
+kep::Prec to_prec(kep_prec p) { return p == KEP_MIXED ? kep::Prec::Mixed : kep::Prec::F64; }
+
+}  // namespace
+
+extern "C" {
+
+const char *kep_last_error(void) { return g_last_error.c_str(); }
+
+int kep_abi_version(void) { return KEP_ABI_VERSION; }
+
+kep_status kepler_solve(const double *M, const double *e, double *E, int64_t n, kep_prec prec,
+                        const kep_options *opts, void *stream)
+{
+    static const char *fn = "kepler_solve";
+    if (n < 0) return fail(KEP_ERR_ARG, "%s: n = %lld < 0", fn, (long long)n);
+    if (kep_status s = check_prec(prec, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (n == 0) return KEP_OK;
+    if (!M || !e || !E) return fail(KEP_ERR_ARG, "%s: M, e and E must not be NULL", fn);
+    if (E == M || E == e) return fail(KEP_ERR_ARG, "%s: E must not alias M or e", fn);
+    if (kep_status s = check_device(fn)) return s;
+    return launch_status(kep::launch_kepler_solve(M, e, E, n, to_prec(prec), o.fixed_iter, o.max_iter, o.shape,
+                                                  (hipStream_t)stream),
+                         fn);
+}
+
+kep_status rv_model(const kep_obs *obs, const kep_params *par, double *v_model, kep_prec prec,
+                    const kep_options *opts, void *stream)
+{
+    static const char *fn = "rv_model";
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_dense(obs, par, false, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0 || obs->n_obs == 0) return KEP_OK;
+    if (!v_model) return fail(KEP_ERR_ARG, "%s: v_model is NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, v_model, nullptr);
+    return launch_status(kep::launch_dense(a, to_prec(prec), true, o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status rv_chisq(const kep_obs *obs, const kep_params *par, double *chi2, kep_prec prec,
+                    const kep_options *opts, void *stream)
+{
+    static const char *fn = "rv_chisq";
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_dense(obs, par, true, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0) return KEP_OK;
+    if (!chi2) return fail(KEP_ERR_ARG, "%s: chi2 is NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, chi2, nullptr);
+    return launch_status(kep::launch_dense(a, to_prec(prec), false, o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2, double *grad, kep_prec prec,
+                         const kep_options *opts, void *stream)
+{
+    static const char *fn = "rv_chisq_grad";
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_dense(obs, par, true, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0) return KEP_OK;
+    if (!chi2 || !grad) return fail(KEP_ERR_ARG, "%s: chi2 and grad must not be NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, chi2, grad);
+    return launch_status(kep::launch_dense_grad(a, to_prec(prec), o.shape, (hipStream_t)stream), fn);
+}
+
+}  // extern "C"
+
+// ====================================================================== ragged
+struct kep_plan {
+    kep::RaggedArgs args;
+    kep::LaunchShape shape;
+    int grid = 0;
+    int tuned = 0;
+    double tuned_ms = 0.0;
+    int64_t n_obs_total = 0, n_pl_total = 0, triples = 0;
+    int32_t *d_order = nullptr;
+    unsigned int *d_queue = nullptr;
+    double *bound_out = nullptr;      // output pointer recorded in the graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t kernel_node = nullptr;
+};
+
+namespace {
+
+struct TuneEntry {
+    std::string key;
+    int block, sb;
+    double ms;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+std::string device_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName);
+}
+
+// Shape class of a ragged batch: log2 buckets of the system count and of the
+// mean work per system.
+std::string tune_key(int64_t n_sys, double mean_work)
+{
+    int b_sys = 0, b_work = 0;
+    while ((1LL << (b_sys + 1)) <= n_sys) ++b_sys;
+    while ((double)(1LL << (b_work + 1)) <= mean_work) ++b_work;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/ragged_mixed/s%d/w%d", device_name().c_str(), b_sys, b_work);
+    return buf;
+}
+
+// Optional persistence: KEP_TUNE_CACHE names a text file of "key block sb ms" lines.
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("KEP_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[200];
+    int block, sb;
+    double ms;
+    while (fscanf(f, "%199s %d %d %lf", key, &block, &sb, &ms) == 4) g_tune.push_back({key, block, sb, ms});
+    fclose(f);
+}
+
+void tune_store_locked(const TuneEntry &e)
+{
+    for (auto &x : g_tune)
+        if (x.key == e.key) { x = e; goto save; }
+    g_tune.push_back(e);
+save:
+    const char *path = getenv("KEP_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    for (auto &x : g_tune) fprintf(f, "%s %d %d %.6f\n", x.key.c_str(), x.block, x.sb, x.ms);
+    fclose(f);
+}
+
+kep_status plan_capture(kep_plan *p, hipStream_t user)
+{
+    (void)user;
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(KEP_ERR_DEVICE, "kep_plan_ragged: hipStreamCreate failed");
+    hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) err = kep::launch_fill_u32(p->d_queue, 0u, 1, cap);
+    if (err == hipSuccess) err = kep::launch_ragged(p->args, p->shape, p->grid, cap);
+    hipGraph_t g = nullptr;
+    hipError_t err2 = hipStreamEndCapture(cap, &g);
+    (void)hipStreamDestroy(cap);
+    if (err != hipSuccess || err2 != hipSuccess || !g)
+        return fail(KEP_ERR_LAUNCH, "kep_plan_ragged: graph capture failed: %s",
+                    hipGetErrorString(err != hipSuccess ? err : err2));
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(KEP_ERR_LAUNCH, "kep_plan_ragged: graph instantiation failed");
+    }
+    // the kernel node that runs the persistent kernel (the last node of the chain)
+    size_t n = 0;
+    (void)hipGraphGetNodes(g, nullptr, &n);
+    std::vector<hipGraphNode_t> nodes(n);
+    if (n) (void)hipGraphGetNodes(g, nodes.data(), &n);
+    hipGraphNode_t kn = nullptr;
+    for (auto nd : nodes) {
+        hipGraphNodeType ty;
+        if (hipGraphNodeGetType(nd, &ty) == hipSuccess && ty == hipGraphNodeTypeKernel) {
+            hipKernelNodeParams kp;
+            if (hipGraphKernelNodeGetParams(nd, &kp) == hipSuccess && kp.sharedMemBytes > 0) kn = nd;
+        }
+    }
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph = g;
+    p->exec = ex;
+    p->kernel_node = kn;
+    p->bound_out = p->args.out;
+    return KEP_OK;
+}
+
+double time_candidate(kep_plan *p, hipStream_t st, int reps)
+{
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    // warm-up
+    (void)kep::launch_fill_u32(p->d_queue, 0u, 1, st);
+    (void)kep::launch_ragged(p->args, p->shape, p->grid, st);
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < reps; ++r) {
+        (void)kep::launch_fill_u32(p->d_queue, 0u, 1, st);
+        (void)kep::launch_ragged(p->args, p->shape, p->grid, st);
+    }
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (hipGetLastError() != hipSuccess) return 1e30;
+    return (double)ms / reps;
+}
+
+void plan_free(kep_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_queue) (void)hipFree(p->d_queue);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, kep_prec prec,
+                           const kep_options *opts, void *stream, kep_plan **out)
+{
+    static const char *fn = "kep_plan_ragged";
+    if (!out) return fail(KEP_ERR_ARG, "%s: out is NULL", fn);
+    *out = nullptr;
+    if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (prec != KEP_MIXED) return fail(KEP_ERR_UNSUPPORTED, "%s: only KEP_MIXED is implemented for ragged batches", fn);
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    const int64_t n_sys = par->n_sys;
+    if (n_sys < 0 || n_sys > INT32_MAX) return fail(KEP_ERR_ARG, "%s: n_sys = %lld outside [0, 2^31)", fn, (long long)n_sys);
+    if (obs->n_obs_total < 0 || par->n_pl_total < 0) return fail(KEP_ERR_ARG, "%s: negative totals", fn);
+    if (!obs->obs_off || !par->pl_off) return fail(KEP_ERR_ARG, "%s: obs_off and pl_off must not be NULL", fn);
+    if (obs->n_obs_total > 0 && (!obs->t || !obs->v || !obs->sigma))
+        return fail(KEP_ERR_ARG, "%s: t, v, sigma must not be NULL", fn);
+    if (par->n_pl_total > 0 && (!par->P || !par->K || !par->e || !par->omega || !par->M0))
+        return fail(KEP_ERR_ARG, "%s: a parameter array is NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    hipStream_t st = (hipStream_t)stream;
+
+    std::vector<int64_t> ooff(n_sys + 1), poff(n_sys + 1);
+    if (hipMemcpyAsync(ooff.data(), obs->obs_off, sizeof(int64_t) * (n_sys + 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(poff.data(), par->pl_off, sizeof(int64_t) * (n_sys + 1), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(KEP_ERR_DEVICE, "%s: cannot read the CSR offsets", fn);
+    if (ooff[0] != 0 || poff[0] != 0) return fail(KEP_ERR_SHAPE, "%s: offsets must start at 0", fn);
+    if (ooff[n_sys] != obs->n_obs_total || poff[n_sys] != par->n_pl_total)
+        return fail(KEP_ERR_SHAPE, "%s: last offsets (%lld, %lld) differ from the totals (%lld, %lld)", fn,
+                    (long long)ooff[n_sys], (long long)poff[n_sys], (long long)obs->n_obs_total,
+                    (long long)par->n_pl_total);
+    std::vector<int64_t> work(n_sys);
+    int64_t triples = 0;
+    for (int64_t i = 0; i < n_sys; ++i) {
+        const int64_t no = ooff[i + 1] - ooff[i], np = poff[i + 1] - poff[i];
+        if (no < 0) return fail(KEP_ERR_SHAPE, "%s: obs_off decreases at system %lld", fn, (long long)i);
+        if (np < 1 || np > KEP_MAX_PL)
+            return fail(KEP_ERR_SHAPE, "%s: system %lld has %lld planets, outside [1, %d]", fn, (long long)i,
+                        (long long)np, KEP_MAX_PL);
+        work[i] = np * std::max<int64_t>(no, 1);
+        triples += np * no;
+    }
+    std::vector<int32_t> order(n_sys);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+
+    kep_plan *p = new kep_plan();
+    p->n_obs_total = obs->n_obs_total;
+    p->n_pl_total = par->n_pl_total;
+    p->triples = triples;
+    if (n_sys > 0 && (hipMalloc(&p->d_order, sizeof(int32_t) * n_sys) != hipSuccess ||
+                      hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess)) {
+        plan_free(p);
+        return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work order", fn);
+    }
+    if (hipMalloc(&p->d_queue, sizeof(unsigned int)) != hipSuccess) {
+        plan_free(p);
+        return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work queue", fn);
+    }
+    kep::RaggedArgs &a = p->args;
+    a.t = obs->t;
+    a.v = obs->v;
+    a.sigma = obs->sigma;
+    a.obs_off = obs->obs_off;
+    a.t0 = obs->t0;
+    a.P = par->P;
+    a.K = par->K;
+    a.e = par->e;
+    a.w = par->omega;
+    a.M0 = par->M0;
+    a.pl_off = par->pl_off;
+    a.offset = par->offset;
+    a.jitter = par->jitter;
+    a.order = p->d_order;
+    a.n_sys = n_sys;
+    a.queue = p->d_queue;
+    a.out = nullptr;
+    a.fixed_iter = o.fixed_iter;
+    a.max_iter = o.max_iter;
+
+    auto configure = [&](int block, int sb) {
+        p->shape.block = block;
+        p->shape.blocks_per_cu = o.shape.blocks_per_cu;
+        a.sb = sb;
+        a.n_items = (n_sys + sb - 1) / sb;
+        const int wpb = block / 64;
+        int64_t g = (a.n_items + wpb - 1) / wpb;
+        const int cap = kep::ragged_max_grid(p->shape, sb);
+        p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+    };
+
+    const double mean_work = n_sys > 0 ? (double)triples / (double)n_sys : 0.0;
+    int best_block = o.shape.block > 0 ? o.shape.block : 256;
+    int best_sb = 4;
+    if (o.shape.block == 0 && n_sys > 0) {
+        const std::string key = tune_key(n_sys, mean_work);
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_load_locked();
+        bool found = false;
+        for (auto &x : g_tune)
+            if (x.key == key) { best_block = x.block; best_sb = x.sb; p->tuned_ms = x.ms; found = true; }
+        if (!found && triples > 0) {
+            // autotune: time every (block, systems per item) candidate on this batch
+            double *scratch = nullptr;
+            if (hipMalloc(&scratch, sizeof(double) * n_sys) != hipSuccess) {
+                plan_free(p);
+                return fail(KEP_ERR_DEVICE, "%s: cannot allocate tuning scratch", fn);
+            }
+            a.out = scratch;
+            double best = 1e30;
+            const int blocks[] = {64, 128, 256};
+            const int sbs[] = {1, 2, 4, 8, 16, 32};
+            for (int b : blocks)
+                for (int sb : sbs) {
+                    configure(b, sb);
+                    const double ms = time_candidate(p, st, 2);
+                    if (ms < best) { best = ms; best_block = b; best_sb = sb; }
+                }
+            (void)hipFree(scratch);
+            a.out = nullptr;
+            p->tuned_ms = best;
+            tune_store_locked({key, best_block, best_sb, best});
+        }
+        p->tuned = 1;
+    }
+    configure(best_block, best_sb);
+    *out = p;
+    return KEP_OK;
+}
+
+static kep_status ragged_check(kep_plan *plan, double *chi2, const char *fn)
+{
+    if (!plan) return fail(KEP_ERR_ARG, "%s: plan is NULL", fn);
+    if (plan->args.n_sys > 0 && !chi2) return fail(KEP_ERR_ARG, "%s: chi2 is NULL", fn);
+    return KEP_OK;
+}
+
+kep_status rv_chisq_ragged(kep_plan *plan, double *chi2, void *stream)
+{
+    static const char *fn = "rv_chisq_ragged";
+    if (kep_status s = ragged_check(plan, chi2, fn)) return s;
+    if (plan->args.n_sys == 0) return KEP_OK;
+    if (!plan->exec || plan->bound_out != chi2) {
+        // (re)record the graph for this output buffer
+        plan->args.out = chi2;
+        if (!plan->exec) {
+            if (kep_status s = plan_capture(plan, (hipStream_t)stream)) return s;
+        } else {
+            bool updated = false;
+            if (plan->kernel_node) {
+                void *kargs[] = {&plan->args};
+                hipKernelNodeParams kp;
+                if (hipGraphKernelNodeGetParams(plan->kernel_node, &kp) == hipSuccess) {
+                    kp.kernelParams = kargs;
+                    updated = hipGraphExecKernelNodeSetParams(plan->exec, plan->kernel_node, &kp) == hipSuccess &&
+                              hipGraphKernelNodeSetParams(plan->kernel_node, &kp) == hipSuccess;
+                }
+            }
+            if (updated) plan->bound_out = chi2;
+            else if (kep_status s = plan_capture(plan, (hipStream_t)stream)) return s;
+        }
+    }
+    hipError_t err = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    if (err != hipSuccess) return fail(KEP_ERR_LAUNCH, "%s: graph launch failed: %s", fn, hipGetErrorString(err));
+    return KEP_OK;
+}
+
+kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream)
+{
+    static const char *fn = "rv_chisq_ragged_direct";
+    if (kep_status s = ragged_check(plan, chi2, fn)) return s;
+    if (plan->args.n_sys == 0) return KEP_OK;
+    kep::RaggedArgs a = plan->args;
+    a.out = chi2;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t err = kep::launch_fill_u32(plan->d_queue, 0u, 1, st);
+    if (err == hipSuccess) err = kep::launch_ragged(a, plan->shape, plan->grid, st);
+    return launch_status(err, fn);
+}
+
+kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info)
+{
+    if (!plan || !info) return fail(KEP_ERR_ARG, "kep_plan_get_info: NULL argument");
+    info->n_sys = plan->args.n_sys;
+    info->n_obs_total = plan->n_obs_total;
+    info->n_pl_total = plan->n_pl_total;
+    info->triples = plan->triples;
+    info->block_threads = plan->shape.block;
+    info->blocks = plan->grid;
+    info->sys_per_batch = plan->args.sb;
+    info->tuned = plan->tuned;
+    info->tuned_ms = plan->tuned_ms;
+    return KEP_OK;
+}
+
+void kep_plan_destroy(kep_plan *plan) { plan_free(plan); }
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Internal interface between the C ABI (kep_api.cpp) and the kernels
+// (kep_kernels.hip).  Not installed; the public interface is include/kepler.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kep {
+
+// Arguments of the dense kernels (observations shared by every system).
+struct DenseArgs {
+    const double *t, *v, *sigma;
+    int64_t n_obs;
+    double t0;
+    const double *P, *K, *e, *w, *M0;
+    const double *offset, *jitter;
+    int64_t n_sys;
+    int n_pl;
+    int sb;            // systems per setup batch of one wavefront (1..kMaxSB)
+    double *out;       // chi2 [n_sys] or model [n_sys][n_obs]
+    double *grad;      // gradient [(5 n_pl + 1)][n_sys] (gradient kernel only)
+    int fixed_iter;    // > 0: fixed Danby count; <= 0: eccentricity schedule
+    int max_iter;      // cap of the convergence-tested loop
+};
+
+// Ragged (CSR) batch, one persistent launch.
+struct RaggedArgs {
+    const double *t, *v, *sigma;
+    const int64_t *obs_off;
+    double t0;
+    const double *P, *K, *e, *w, *M0;
+    const int64_t *pl_off;
+    const double *offset, *jitter;
+    const int32_t *order;     // systems by decreasing work
+    int64_t n_sys;
+    int64_t n_items;          // number of work items = ceil(n_sys / sb)
+    int sb;                   // systems per work item
+    unsigned int *queue;      // work-queue counter (reset before every launch)
+    double *out;
+    int fixed_iter, max_iter;
+};
+
+constexpr int kMaxSB = 32;
+constexpr int kMaxPl = 8;
+
+enum class Prec { F64 = 0, Mixed = 1 };
+
+struct LaunchShape {
+    int block;         // threads per block (multiple of 64)
+    int blocks_per_cu; // 0 = occupancy limit
+};
+
+// Launchers return hipSuccess or the launch error.  They do not synchronise.
+hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int64_t n, Prec prec,
+                               int fixed_iter, int max_iter, LaunchShape shape, hipStream_t st);
+hipError_t launch_dense(DenseArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
+hipError_t launch_dense_grad(DenseArgs a, Prec prec, LaunchShape shape, hipStream_t st);
+hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
+hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
+int ragged_max_grid(LaunchShape shape, int sb);
+int device_cu_count();
+
+}  // namespace kep

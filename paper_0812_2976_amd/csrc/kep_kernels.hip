@@ -1,0 +1,881 @@
+// gfx950 kernels for batched Keplerian radial-velocity models (Ford 2008).
+//
+// Dense batches (every system sees the same n_obs observations) use one
+// wavefront per system at a time with the 64 lanes spread over observations:
+// lane l evaluates observations l, l + 64, ... (NCH chunks held in registers
+// for the whole launch), so every parameter a lane needs is wave-uniform and
+// the eccentricity schedule of the Kepler solve is uniform across the wave.
+// Per-planet constants (reciprocal period, phase offset, amplitudes) are
+// computed with the lanes spread over systems instead -- one lane per system
+// for a batch of up to 32 systems -- and handed over through the wave's slice
+// of LDS, so that setup is paid once per system rather than once per lane.
+// The chi-square is reduced across the wave in binary64 (Sec. 4.4's final sum).
+#include <hip/hip_runtime.h>
+
+#include "kep_device.h"
+#include "kep_internal.h"
+
+namespace kep {
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool planet_ok(double P, double K, double e, double w, double M0)
+{
+    return isfinite(P) && P > 0.0 && isfinite(K) && isfinite(e) && e >= 0.0 && e < 1.0 &&
+           isfinite(w) && isfinite(M0);
+}
+
+// ------------------------------------------------------------------ mixed
+struct RecMixed {          // 48 bytes, one per (system, planet)
+    double P, rP, m0r;     // period, 1/P, M0 / (2 pi) reduced to [-1/2, 1/2]
+    float e, ome, A, B;    // e, 1 - e (rounded from binary64), K b^2 cos w, -K b sin w
+    int niter, pad;
+};
+
+struct ObsMixed {
+    double tt;   // t - t0
+    double v;    // observed velocity
+    float s2;    // sigma^2
+    float w;     // 1 / sigma^2 (no jitter)
+    bool in;     // lane holds a real observation
+    bool ok;     // t, v, sigma finite and sigma >= 0
+};
+
+struct PolMixed {
+    using Rec = RecMixed;
+    using Obs = ObsMixed;
+    struct ModelAcc { Kahan32 k; };
+    using ChiAcc = Kahan32;
+
+    static __device__ __forceinline__ bool setup(const DenseArgs &a, double P, double K, double e, double w,
+                                                 double M0, Rec &r)
+    {
+        bool ok = planet_ok(P, K, e, w, M0);
+        if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+        r.P = P;
+        r.rP = 1.0 / P;
+        double m0r = M0 * kInvTwoPi;
+        r.m0r = m0r - rint(m0r);
+        double ome = 1.0 - e;
+        double b2 = ome * (1.0 + e);
+        double b = sqrt(b2);
+        double sw, cw;
+        sincos(w, &sw, &cw);
+        r.e = (float)e;
+        r.ome = (float)ome;
+        r.A = (float)(K * b2 * cw);
+        r.B = (float)(-K * b * sw);
+        r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32((float)e);
+        r.pad = 0;
+        return ok;
+    }
+
+    static __device__ __forceinline__ void load_obs(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        double v = o.in ? a.v[k] : 0.0;
+        double s = o.in ? a.sigma[k] : 1.0;
+        o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
+        o.tt = t - a.t0;
+        o.v = v;
+        o.s2 = (float)(s * s);
+        o.w = (float)(1.0 / (s * s));
+    }
+
+    static __device__ __forceinline__ void load_obs_model(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        o.ok = isfinite(t);
+        o.tt = t - a.t0;
+        o.v = 0.0;
+        o.s2 = 1.0f;
+        o.w = 1.0f;
+    }
+
+    template <int NCH>
+    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
+                                                      int max_iter, int /*fixed: already in rr.niter*/)
+    {
+        const double P = uniform_double(rr.P), rP = uniform_double(rr.rP), m0r = uniform_double(rr.m0r);
+        const float e = uniform_float(rr.e), ome = uniform_float(rr.ome);
+        const float A = uniform_float(rr.A), B = uniform_float(rr.B);
+        const int niter = uniform_int(rr.niter);
+        float M[NCH], E[NCH], lo[NCH], hi[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            double ph = phase_rev(o[c].tt, P, rP, m0r);
+            M[c] = (float)(ph * kTwoPi);
+            lo[c] = M[c] - e;
+            hi[c] = M[c] + e;
+            E[c] = fmaf(copysignf(0.85f, M[c]), e, M[c]);
+        }
+        if (niter > 0) {
+            for (int it = 0; it < niter; ++it) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) danby_step32(E[c], M[c], e, ome, lo[c], hi[c]);
+            }
+        } else {
+            for (int it = 0; it < max_iter; ++it) {
+                bool conv = true;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    float st = danby_step32(E[c], M[c], e, ome, lo[c], hi[c]);
+                    conv = conv && (fabsf(st) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
+                }
+                if (__all(conv)) break;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            SinCos32 sc = sincos32(E[c]);
+            float D = fmaf(e, sc.omc, ome);                  // 1 - e cos E
+            float num = fmaf(B, sc.s, fmaf(-A, sc.omc, A));  // A cos E + B sin E
+            m[c].k.add(num * rcp32(D));
+        }
+    }
+
+    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.k.init(); }
+    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.k.value(); }
+
+    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x.init(); }
+    // One observation's contribution; returns false if the weight is invalid.
+    static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
+                                                   double jit, bool has_jit)
+    {
+        float ck = (float)(o.v - gam);
+        float r = (m.k.s - ck) - m.k.c;
+        float w = o.w;
+        bool okw = true;
+        if (has_jit) {
+            float var = o.s2 + (float)(jit * jit);
+            okw = var > 0.0f;
+            w = rcp32(var);
+        } else {
+            okw = o.s2 > 0.0f;
+        }
+        x.add(w * r * r);
+        return okw;
+    }
+    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x.value(); }
+};
+
+// ------------------------------------------------------------------ binary64
+struct Rec64 {            // 64 bytes
+    double P, M0, e, K, b, cw, sw;
+    int pad0, pad1;
+};
+
+struct Obs64 {
+    double tt, v, s2, w;
+    bool in, ok;
+};
+
+struct Pol64 {
+    using Rec = Rec64;
+    using Obs = Obs64;
+    struct ModelAcc { double s; };
+    using ChiAcc = double;
+
+    static __device__ __forceinline__ bool setup(const DenseArgs &, double P, double K, double e, double w,
+                                                 double M0, Rec &r)
+    {
+        bool ok = planet_ok(P, K, e, w, M0);
+        if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+        r.P = P;
+        r.M0 = M0;
+        r.e = e;
+        r.K = K;
+        r.b = sqrt((1.0 - e) * (1.0 + e));
+        sincos(w, &r.sw, &r.cw);
+        r.pad0 = r.pad1 = 0;
+        return ok;
+    }
+
+    static __device__ __forceinline__ void load_obs(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        double v = o.in ? a.v[k] : 0.0;
+        double s = o.in ? a.sigma[k] : 1.0;
+        o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
+        o.tt = t - a.t0;
+        o.v = v;
+        o.s2 = s * s;
+        o.w = 1.0 / (s * s);
+    }
+
+    static __device__ __forceinline__ void load_obs_model(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        o.ok = isfinite(t);
+        o.tt = t - a.t0;
+        o.v = 0.0;
+        o.s2 = 1.0;
+        o.w = 1.0;
+    }
+
+    // Plain binary64 (the paper's double-precision variant): IEEE quotient
+    // (t - t0)/P, exact fraction, M = 2 pi frac + M0 in [0, 2 pi), Danby's
+    // iteration, then v = K b (b cos w cos E - sin w sin E) / (1 - e cos E).
+    template <int NCH>
+    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
+                                                      int max_iter, int fixed)
+    {
+        const double P = uniform_double(rr.P), M0 = uniform_double(rr.M0), e = uniform_double(rr.e);
+        const double K = uniform_double(rr.K), b = uniform_double(rr.b);
+        const double cw = uniform_double(rr.cw), sw = uniform_double(rr.sw);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            double q = o[c].tt / P;
+            double phi = q - floor(q);
+            double M = fma(kTwoPi, phi, M0);
+            M = M - kTwoPi * floor(M * kInvTwoPi);
+            double E = kepler64(M, e, M < kPi ? 1.0 : -1.0, fixed, max_iter);
+            double s, cE;
+            sincos(E, &s, &cE);
+            m[c].s += K * b * (b * cw * cE - sw * s) / (1.0 - e * cE);
+        }
+    }
+
+    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.s = 0.0; }
+    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.s; }
+    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x = 0.0; }
+    static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
+                                                   double jit, bool has_jit)
+    {
+        double r = m.s + gam - o.v;
+        double w = o.w;
+        bool okw = o.s2 > 0.0;
+        if (has_jit) {
+            double var = o.s2 + jit * jit;
+            okw = var > 0.0;
+            w = 1.0 / var;
+        }
+        x = fma(w * r, r, x);
+        return okw;
+    }
+    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x; }
+};
+
+// Iteration count of the plain binary64 kernel: fixed_iter > 0 as given,
+// 0 -> the fixed 30 steps of the plain kernel, < 0 -> schedule + convergence test.
+__device__ __forceinline__ int fixed64(int fixed_iter) { return fixed_iter > 0 ? fixed_iter : (fixed_iter == 0 ? 30 : 0); }
+
+template <class Pol, int NCH>
+__device__ __forceinline__ void pol_add_planet(const typename Pol::Rec &r, const typename Pol::Obs (&o)[NCH],
+                                               typename Pol::ModelAcc (&m)[NCH], const DenseArgs &a)
+{
+    Pol::template add_planet<NCH>(r, o, m, a.max_iter, fixed64(a.fixed_iter));
+}
+
+// Dense kernel: chi-square (MODEL = false) or model velocities (MODEL = true).
+template <class Pol, int NCH, bool MODEL>
+__global__ void __launch_bounds__(256) k_dense(DenseArgs a)
+{
+    using Rec = typename Pol::Rec;
+    using Obs = typename Pol::Obs;
+    using ModelAcc = typename Pol::ModelAcc;
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int lane = __lane_id();
+    const int wpb = blockDim.x >> 6;
+    const int wib = uniform_int(threadIdx.x >> 6);
+    Rec *recs = reinterpret_cast<Rec *>(smem) + (size_t)wib * a.sb * a.n_pl;
+    int *sysbad = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * a.n_pl * sizeof(Rec)) + wib * a.sb;
+
+    const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    const int64_t n_batches = (a.n_sys + a.sb - 1) / a.sb;
+    const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
+    const bool has_jit = a.jitter != nullptr;
+
+    Obs o[NCH];
+    auto load_group = [&](int g) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
+            if (MODEL) Pol::load_obs_model(a, k, o[c]);
+            else Pol::load_obs(a, k, o[c]);
+        }
+    };
+    if (n_groups <= 1) load_group(0);
+
+    for (int64_t bt = gw; bt < n_batches; bt += n_waves) {
+        const int64_t s0 = bt * a.sb;
+        const int nb = (int)min((int64_t)a.sb, a.n_sys - s0);
+        wave_sync_lds();
+        if (lane < nb) {
+            const int64_t sys = s0 + lane;
+            bool ok = isfinite(a.t0);
+            for (int j = 0; j < a.n_pl; ++j) {
+                const int64_t p = (int64_t)j * a.n_sys + sys;
+                Rec r;
+                ok = Pol::setup(a, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r) && ok;
+                recs[lane * a.n_pl + j] = r;
+            }
+            if (a.offset) ok = ok && isfinite(a.offset[sys]);
+            if (a.jitter) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
+            sysbad[lane] = ok ? 0 : 1;
+        }
+        wave_sync_lds();
+
+        for (int s = 0; s < nb; ++s) {
+            const int64_t sys = s0 + s;
+            const double gam = a.offset ? a.offset[sys] : 0.0;
+            const double jit = a.jitter ? a.jitter[sys] : 0.0;
+            const bool sbad = uniform_int(sysbad[s]) != 0;
+            typename Pol::ChiAcc chi;
+            Pol::chi_init(chi);
+            bool bad_obs = false;
+            for (int g = 0; g < n_groups; ++g) {
+                if (n_groups > 1) load_group(g);
+                ModelAcc m[NCH];
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) Pol::model_init(m[c]);
+                for (int j = 0; j < a.n_pl; ++j) pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a);
+                if (MODEL) {
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        if (o[c].in) {
+                            int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
+                            double val = Pol::model_value(m[c]) + gam;
+                            a.out[sys * a.n_obs + k] = (sbad || !o[c].ok) ? __builtin_nan("") : val;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        if (o[c].in) {
+                            bool okw = Pol::chi_add(chi, m[c], o[c], gam, jit, has_jit);
+                            bad_obs = bad_obs || !okw || !o[c].ok;
+                        }
+                    }
+                }
+            }
+            if (!MODEL) {
+                double tot = wave_sum(Pol::chi_value(chi));
+                bool bad = sbad || __any(bad_obs);
+                if (lane == 0) a.out[sys] = bad ? __builtin_nan("") : tot;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ Kepler only
+// Standalone Kepler solve (the paper's Kepler-only mode): one lane per pair.
+// M is reduced to [-pi, pi] with 2 pi as a double-double; the root is returned
+// on the input's branch.
+template <bool MIXED>
+__global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, const double *__restrict__ ev,
+                                               double *__restrict__ Ev, int64_t n, int fixed, int max_iter)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double M = Mv[i], e = ev[i];
+        bool ok = isfinite(M) && isfinite(e) && e >= 0.0 && e < 1.0;
+        if (!ok) { M = 0.0; e = 0.0; }
+        double kq = rint(M * kInvTwoPi);
+        double Mr = fma(-kq, kTwoPiHi, M);
+        Mr = fma(-kq, kTwoPiLo, Mr);
+        double E;
+        if (MIXED) {
+            float M32 = (float)Mr;
+            float e32 = (float)e;
+            float ome = (float)(1.0 - e);
+            int niter = fixed > 0 ? fixed : sched32(e32);
+            float E32 = kepler32(M32, e32, ome, niter, max_iter);
+            E = (double)E32;
+        } else {
+            E = kepler64(Mr, e, Mr >= 0.0 ? 1.0 : -1.0, fixed, max_iter);
+        }
+        E = fma(kq, kTwoPiHi, E);
+        E = fma(kq, kTwoPiLo, E);
+        Ev[i] = ok ? E : __builtin_nan("");
+    }
+}
+
+__global__ void k_fill_u32(unsigned int *p, unsigned int value, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// ------------------------------------------------------------------ gradient
+// chi-square and its gradient with one lane per system (the adjoint needs
+// 5 n_pl + 1 running sums per system; keeping them in the lane that owns the
+// system avoids a cross-lane reduction per sum).  Observations are uniform
+// across the wave and arrive through scalar loads.  Derivatives use the
+// implicit-function relations of Kepler's equation, dE/dM = 1/(1 - e cos E)
+// and dE/de = sin E/(1 - e cos E), in the true-anomaly forms
+//   df/dM = b/D^2,  df/de = sin E (2 - e cos E - e^2)/(b D^2),  D = 1 - e cos E,
+// so no iteration is differentiated.
+template <class T> struct GradPlanet;
+
+template <> struct GradPlanet<float> {
+    double P, rP, m0r;
+    float e, ome, b, K, cw, sw;
+    int niter;
+};
+
+template <> struct GradPlanet<double> {
+    double P, rP, M0, e, b, K, cw, sw;
+};
+
+__device__ __forceinline__ bool grad_setup(double P, double K, double e, double w, double M0, int fixed_iter,
+                                           GradPlanet<float> &g)
+{
+    bool ok = planet_ok(P, K, e, w, M0);
+    if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+    g.P = P;
+    g.rP = 1.0 / P;
+    double m0r = M0 * kInvTwoPi;
+    g.m0r = m0r - rint(m0r);
+    double ome = 1.0 - e;
+    g.e = (float)e;
+    g.ome = (float)ome;
+    g.b = (float)sqrt(ome * (1.0 + e));
+    g.K = (float)K;
+    double sw, cw;
+    sincos(w, &sw, &cw);
+    g.cw = (float)cw;
+    g.sw = (float)sw;
+    g.niter = fixed_iter > 0 ? fixed_iter : sched32((float)e);
+    return ok;
+}
+
+__device__ __forceinline__ bool grad_setup(double P, double K, double e, double w, double M0, int,
+                                           GradPlanet<double> &g)
+{
+    bool ok = planet_ok(P, K, e, w, M0);
+    if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+    g.P = P;
+    g.rP = 1.0 / P;
+    g.M0 = M0;
+    g.e = e;
+    g.b = sqrt((1.0 - e) * (1.0 + e));
+    g.K = K;
+    sincos(w, &g.sw, &g.cw);
+    return ok;
+}
+
+// Velocity of one planet and its five partial derivatives at time tt = t - t0.
+// d[0..4] = dv/d(P, K, e, omega, M0).
+__device__ __forceinline__ float grad_eval(const GradPlanet<float> &g, double tt, int max_iter, float (&d)[5])
+{
+    double q = tt * g.rP;                       // unreduced quotient, only for dM/dP
+    double ph = phase_rev(tt, g.P, g.rP, g.m0r);
+    float M = (float)(ph * kTwoPi);
+    float E = kepler32(M, g.e, g.ome, g.niter, max_iter);
+    SinCos32 sc = sincos32(E);
+    float D = fmaf(g.e, sc.omc, g.ome);         // 1 - e cos E
+    float iD = rcp32(D);
+    float cf = (g.ome - sc.omc) * iD;           // cos f = (cos E - e)/D
+    float sf = g.b * sc.s * iD;                 // sin f = b sin E / D
+    float cwf = g.cw * cf - g.sw * sf;          // cos(w + f)
+    float swf = g.sw * cf + g.cw * sf;          // sin(w + f)
+    float dvdK = cwf + g.e * g.cw;
+    float v = g.K * dvdK;
+    float ecE = g.e - g.e * sc.omc;             // e cos E
+    float dfdM = g.b * iD * iD;
+    float dfde = sc.s * (2.0f - ecE - g.e * g.e) * iD * iD * rcp32(g.b);
+    float dvdM0 = -g.K * swf * dfdM;
+    d[0] = dvdM0 * (float)(-kTwoPi * q * g.rP);
+    d[1] = dvdK;
+    d[2] = g.K * g.cw - g.K * swf * dfde;
+    d[3] = -g.K * (swf + g.e * g.sw);
+    d[4] = dvdM0;
+    return v;
+}
+
+__device__ __forceinline__ double grad_eval(const GradPlanet<double> &g, double tt, int max_iter, int fixed,
+                                            double (&d)[5])
+{
+    double q = tt / g.P;
+    double phi = q - floor(q);
+    double M = fma(kTwoPi, phi, g.M0);
+    M = M - kTwoPi * floor(M * kInvTwoPi);
+    double E = kepler64(M, g.e, M < kPi ? 1.0 : -1.0, fixed, max_iter);
+    double s, c;
+    sincos(E, &s, &c);
+    double D = 1.0 - g.e * c;
+    double cf = (c - g.e) / D;
+    double sf = g.b * s / D;
+    double cwf = g.cw * cf - g.sw * sf;
+    double swf = g.sw * cf + g.cw * sf;
+    double dvdK = cwf + g.e * g.cw;
+    double dfdM = g.b / (D * D);
+    double dfde = s * (2.0 - g.e * c - g.e * g.e) / (g.b * D * D);
+    double dvdM0 = -g.K * swf * dfdM;
+    d[0] = dvdM0 * (-kTwoPi * q / g.P);
+    d[1] = dvdK;
+    d[2] = g.K * g.cw - g.K * swf * dfde;
+    d[3] = -g.K * (swf + g.e * g.sw);
+    d[4] = dvdM0;
+    return g.K * dvdK;
+}
+
+template <int NPL>
+__global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const bool has_jit = a.jitter != nullptr;
+    for (int64_t sys = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sys < a.n_sys; sys += stride) {
+        GradPlanet<float> pl[NPL];
+        bool ok = isfinite(a.t0);
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+            const int64_t p = (int64_t)j * a.n_sys + sys;
+            ok = grad_setup(a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], a.fixed_iter, pl[j]) && ok;
+        }
+        const double gam = a.offset ? a.offset[sys] : 0.0;
+        const double jit = a.jitter ? a.jitter[sys] : 0.0;
+        if (a.offset) ok = ok && isfinite(gam);
+        if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
+        const float jit2 = (float)(jit * jit);
+        Kahan32 chi, gacc[5 * NPL + 1];
+        chi.init();
+#pragma unroll
+        for (int i = 0; i < 5 * NPL + 1; ++i) gacc[i].init();
+        for (int64_t k = 0; k < a.n_obs; ++k) {
+            const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
+            ok = ok && isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0;
+            const double tt = t - a.t0;
+            float d[NPL][5];
+            Kahan32 msum;
+            msum.init();
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) msum.add(grad_eval(pl[j], tt, a.max_iter, d[j]));
+            const float ck = (float)(vo - gam);
+            const float r = (msum.s - ck) - msum.c;
+            const float var = (float)(sg * sg) + jit2;
+            ok = ok && var > 0.0f;
+            const float w = rcp32(var);
+            const float wr = w * r;
+            chi.add(wr * r);
+            const float c2 = 2.0f * wr;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) gacc[5 * j + i].add(c2 * d[j][i]);
+            }
+            gacc[5 * NPL].add(c2);
+        }
+        const double nan = __builtin_nan("");
+        a.out[sys] = ok ? chi.value() : nan;
+#pragma unroll
+        for (int i = 0; i < 5 * NPL + 1; ++i) a.grad[(int64_t)i * a.n_sys + sys] = ok ? gacc[i].value() : nan;
+    }
+}
+
+template <int NPL>
+__global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const bool has_jit = a.jitter != nullptr;
+    const int fixed = fixed64(a.fixed_iter);
+    for (int64_t sys = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sys < a.n_sys; sys += stride) {
+        GradPlanet<double> pl[NPL];
+        bool ok = isfinite(a.t0);
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) {
+            const int64_t p = (int64_t)j * a.n_sys + sys;
+            ok = grad_setup(a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], a.fixed_iter, pl[j]) && ok;
+        }
+        const double gam = a.offset ? a.offset[sys] : 0.0;
+        const double jit = a.jitter ? a.jitter[sys] : 0.0;
+        if (a.offset) ok = ok && isfinite(gam);
+        if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
+        double chi = 0.0, gacc[5 * NPL + 1];
+#pragma unroll
+        for (int i = 0; i < 5 * NPL + 1; ++i) gacc[i] = 0.0;
+        for (int64_t k = 0; k < a.n_obs; ++k) {
+            const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
+            ok = ok && isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0;
+            const double tt = t - a.t0;
+            double d[NPL][5];
+            double m = 0.0;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) m += grad_eval(pl[j], tt, a.max_iter, fixed, d[j]);
+            const double r = m + gam - vo;
+            const double var = sg * sg + jit * jit;
+            ok = ok && var > 0.0;
+            const double w = 1.0 / var;
+            chi = fma(w * r, r, chi);
+            const double c2 = 2.0 * w * r;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+#pragma unroll
+                for (int i = 0; i < 5; ++i) gacc[5 * j + i] = fma(c2, d[j][i], gacc[5 * j + i]);
+            }
+            gacc[5 * NPL] += c2;
+        }
+        const double nan = __builtin_nan("");
+        a.out[sys] = ok ? chi : nan;
+#pragma unroll
+        for (int i = 0; i < 5 * NPL + 1; ++i) a.grad[(int64_t)i * a.n_sys + sys] = ok ? gacc[i] : nan;
+    }
+}
+
+// ------------------------------------------------------------------ ragged
+// Persistent kernel over CSR systems.  Work items are runs of `sb` systems in
+// decreasing order of work; each wavefront takes the next item from an
+// atomic counter until the items run out.  Setup runs one lane per system of
+// the item; evaluation runs one system at a time with lanes over that
+// system's observations, in groups of up to 4 x 64 loaded with coalesced reads.
+struct RecRagged {
+    RecMixed pl[kMaxPl];
+};
+
+template <int NCH>
+__device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed *recs, int npl, int64_t o0,
+                                             int64_t nrem, double gam, double jit, bool has_jit, Kahan32 &chi,
+                                             bool &bad_obs)
+{
+    const int lane = __lane_id();
+    ObsMixed o[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int64_t k = c * 64 + lane;
+        o[c].in = k < nrem;
+        double t = o[c].in ? a.t[o0 + k] : a.t0;
+        double v = o[c].in ? a.v[o0 + k] : 0.0;
+        double s = o[c].in ? a.sigma[o0 + k] : 1.0;
+        o[c].ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
+        o[c].tt = t - a.t0;
+        o[c].v = v;
+        o[c].s2 = (float)(s * s);
+        o[c].w = (float)(1.0 / (s * s));
+    }
+    PolMixed::ModelAcc m[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) PolMixed::model_init(m[c]);
+    for (int j = 0; j < npl; ++j) PolMixed::add_planet<NCH>(recs[j], o, m, a.max_iter, 0);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        if (o[c].in) {
+            bool okw = PolMixed::chi_add(chi, m[c], o[c], gam, jit, has_jit);
+            bad_obs = bad_obs || !okw || !o[c].ok;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = __lane_id();
+    const int wpb = blockDim.x >> 6;
+    const int wib = uniform_int(threadIdx.x >> 6);
+    RecMixed *recs = reinterpret_cast<RecMixed *>(smem) + (size_t)wib * a.sb * kMaxPl;
+    int *meta = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * kMaxPl * sizeof(RecMixed)) + (size_t)wib * a.sb * 2;
+    const bool has_jit = a.jitter != nullptr;
+
+    for (;;) {
+        unsigned int item = 0;
+        if (lane == 0) item = atomicAdd(a.queue, 1u);
+        item = (unsigned int)uniform_int((int)__shfl(item, 0, 64));
+        if ((int64_t)item >= a.n_items) break;
+        const int64_t i0 = (int64_t)item * a.sb;
+        const int nb = (int)min((int64_t)a.sb, a.n_sys - i0);
+        wave_sync_lds();
+        if (lane < nb) {
+            const int64_t sys = a.order[i0 + lane];
+            const int64_t p0 = a.pl_off[sys];
+            const int npl = (int)(a.pl_off[sys + 1] - p0);
+            bool ok = isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
+            DenseArgs dummy;
+            dummy.fixed_iter = a.fixed_iter;
+            for (int j = 0; j < npl && j < kMaxPl; ++j) {
+                RecMixed r;
+                ok = PolMixed::setup(dummy, a.P[p0 + j], a.K[p0 + j], a.e[p0 + j], a.w[p0 + j], a.M0[p0 + j], r) && ok;
+                recs[lane * kMaxPl + j] = r;
+            }
+            if (a.offset) ok = ok && isfinite(a.offset[sys]);
+            if (a.jitter) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
+            meta[2 * lane] = ok ? npl : -npl;
+            meta[2 * lane + 1] = (int)sys;
+        }
+        wave_sync_lds();
+        for (int s = 0; s < nb; ++s) {
+            const int code = uniform_int(meta[2 * s]);
+            const int64_t sys = uniform_int(meta[2 * s + 1]);
+            const int npl = code < 0 ? -code : code;
+            const int64_t o0 = a.obs_off[sys];
+            const int64_t n = a.obs_off[sys + 1] - o0;
+            const double gam = a.offset ? a.offset[sys] : 0.0;
+            const double jit = a.jitter ? a.jitter[sys] : 0.0;
+            Kahan32 chi;
+            chi.init();
+            bool bad_obs = false;
+            for (int64_t g = 0; g < n; g += 256) {
+                const int64_t rem = n - g;
+                const RecMixed *rs = recs + s * kMaxPl;
+                if (rem <= 64) ragged_group<1>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+                else if (rem <= 128) ragged_group<2>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+                else if (rem <= 192) ragged_group<3>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+                else ragged_group<4>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+            }
+            const double tot = wave_sum(chi.value());
+            const bool bad = code <= 0 || __any(bad_obs);
+            if (lane == 0) a.out[sys] = bad ? __builtin_nan("") : tot;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static int g_cu_count = 0;
+
+int device_cu_count()
+{
+    if (g_cu_count == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        g_cu_count = cus;
+    }
+    return g_cu_count;
+}
+
+hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int64_t n, Prec prec, int fixed_iter,
+                               int max_iter, LaunchShape shape, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int block = shape.block > 0 ? shape.block : 256;
+    int per_cu = shape.blocks_per_cu > 0 ? shape.blocks_per_cu : 8;
+    int64_t need = (n + block - 1) / block;
+    int64_t cap = (int64_t)device_cu_count() * per_cu * (256 / block > 0 ? 256 / block : 1) * 4;
+    int grid = (int)(need < cap ? need : cap);
+    if (prec == Prec::Mixed)
+        hipLaunchKernelGGL(k_kepler<true>, dim3(grid), dim3(block), 0, st, M, e, E, n, fixed_iter, max_iter);
+    else
+        hipLaunchKernelGGL(k_kepler<false>, dim3(grid), dim3(block), 0, st, M, e, E, n,
+                           fixed_iter == 0 ? 30 : (fixed_iter < 0 ? 0 : fixed_iter), max_iter);
+    return hipGetLastError();
+}
+
+template <class Pol, bool MODEL>
+static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
+{
+    const int block = shape.block > 0 ? shape.block : 256;
+    const int wpb = block / 64;
+    const size_t rec_bytes = (size_t)wpb * a.n_pl * sizeof(typename Pol::Rec) + (size_t)wpb * sizeof(int);
+    // systems per setup batch: at most kMaxSB and at most 48 KiB of LDS per block
+    int64_t sb_cap = (int64_t)(48 * 1024) / (int64_t)rec_bytes;
+    sb_cap = sb_cap < 1 ? 1 : (sb_cap > kMaxSB ? kMaxSB : sb_cap);
+    size_t lds = rec_bytes * (size_t)sb_cap;
+    const int nch_needed = (int)((a.n_obs + 63) / 64);
+    void (*kern)(DenseArgs);
+    if (nch_needed <= 1) kern = k_dense<Pol, 1, MODEL>;
+    else if (nch_needed <= 2) kern = k_dense<Pol, 2, MODEL>;
+    else if (nch_needed <= 4) kern = k_dense<Pol, 4, MODEL>;
+    else kern = k_dense<Pol, 8, MODEL>;
+    int per_cu = shape.blocks_per_cu;
+    if (per_cu <= 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess || occ <= 0) occ = 1;
+        per_cu = occ;
+    }
+    const int64_t max_waves = (int64_t)device_cu_count() * per_cu * wpb;
+    int64_t sb = a.n_sys / (max_waves > 0 ? max_waves : 1);
+    sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
+    a.sb = (int)sb;
+    lds = rec_bytes * (size_t)sb;
+    const int64_t n_batches = (a.n_sys + sb - 1) / sb;
+    int64_t grid = (n_batches + wpb - 1) / wpb;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    if (grid > cap) grid = cap;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(DenseArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0) return hipSuccess;
+    if (model && a.n_obs <= 0) return hipSuccess;
+    if (prec == Prec::Mixed)
+        return model ? launch_dense_t<PolMixed, true>(a, shape, st) : launch_dense_t<PolMixed, false>(a, shape, st);
+    return model ? launch_dense_t<Pol64, true>(a, shape, st) : launch_dense_t<Pol64, false>(a, shape, st);
+}
+
+}  // namespace kep
+
+namespace kep {
+
+static int grad_grid(int64_t n_sys, int block, int per_cu)
+{
+    int64_t need = (n_sys + block - 1) / block;
+    int64_t cap = (int64_t)device_cu_count() * (per_cu > 0 ? per_cu : 8);
+    return (int)(need < cap ? (need > 0 ? need : 1) : cap);
+}
+
+hipError_t launch_dense_grad(DenseArgs a, Prec prec, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0) return hipSuccess;
+    const int block = shape.block > 0 ? shape.block : 256;
+    const int grid = grad_grid(a.n_sys, block, shape.blocks_per_cu);
+#define KEP_GRAD_CASE(N)                                                                     \
+    case N:                                                                                  \
+        if (prec == Prec::Mixed) hipLaunchKernelGGL(k_grad_mixed<N>, dim3(grid), dim3(block), 0, st, a); \
+        else hipLaunchKernelGGL(k_grad_f64<N>, dim3(grid), dim3(block), 0, st, a);            \
+        break;
+    switch (a.n_pl) {
+        KEP_GRAD_CASE(1)
+        KEP_GRAD_CASE(2)
+        KEP_GRAD_CASE(3)
+        KEP_GRAD_CASE(4)
+        KEP_GRAD_CASE(5)
+        KEP_GRAD_CASE(6)
+        KEP_GRAD_CASE(7)
+        KEP_GRAD_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef KEP_GRAD_CASE
+    return hipGetLastError();
+}
+
+static size_t ragged_lds(int block, int sb)
+{
+    const int wpb = block / 64;
+    return (size_t)wpb * sb * kMaxPl * sizeof(RecMixed) + (size_t)wpb * sb * 2 * sizeof(int);
+}
+
+int ragged_max_grid(LaunchShape shape, int sb)
+{
+    const int block = shape.block > 0 ? shape.block : 256;
+    int per_cu = shape.blocks_per_cu;
+    if (per_cu <= 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_ragged_mixed, block, ragged_lds(block, sb)) != hipSuccess ||
+            occ <= 0)
+            occ = 1;
+        per_cu = occ;
+    }
+    return device_cu_count() * per_cu;
+}
+
+hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st)
+{
+    const int block = shape.block > 0 ? shape.block : 256;
+    hipLaunchKernelGGL(k_ragged_mixed, dim3(grid > 0 ? grid : 1), dim3(block), ragged_lds(block, a.sb), st, a);
+    return hipGetLastError();
+}
+
+}  // namespace kep

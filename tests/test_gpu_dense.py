@@ -1,0 +1,203 @@
+"""GPU parity of the dense entry points (kepler_solve, rv_model, rv_chisq) with the
+CPU oracle, called through the C ABI on seeded inputs.
+
+Tolerances (north star / derivation in the design notes):
+  binary64 path: |dE| <= 1e-12 rad, chi2 relative (to max(chi2, 1)) <= 1e-12,
+                 model velocity |dv| <= 1e-9 m/s
+  mixed path:    model velocity |dv| <= 1e-3 m/s, chi2 relative <= 1e-5,
+                 Kepler |dE| within the binary32 bound of kepler_tol_mixed
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0812_2976_amd as kp
+import synth
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _report(name, x):
+    print(f"[{name}] max = {np.nanmax(x):.3e}", flush=True)
+
+
+# ------------------------------------------------------------------ kepler_solve
+@pytest.mark.parametrize("n", [1, 255, 100003])
+def test_kepler_solve_fp64_uniform(dev, n):
+    M, e = synth.kepler_pairs(n)
+    E = kp.kepler_solve(torch.from_numpy(M).to(dev), torch.from_numpy(e).to(dev), prec="fp64").cpu().numpy()
+    err = np.abs(E - oracle.kepler(M, e))
+    _report(f"kepler fp64 n={n}", err)
+    assert err.max() <= 1e-12
+
+
+def test_kepler_solve_fp64_stress_and_branches(dev):
+    M, e = synth.kepler_pairs(200000, stress=True)
+    M = np.concatenate([M, [-50.0, -3.0, 0.0, np.pi, 2 * np.pi, 1000.25, 7e3]])
+    e = np.concatenate([e, [0.5, 0.9, 0.99, 0.3, 0.7, 0.95, 0.6]])
+    E = kp.kepler_solve(torch.from_numpy(M).to(dev), torch.from_numpy(e).to(dev), prec="fp64").cpu().numpy()
+    err = np.abs(E - oracle.kepler(M, e))
+    _report("kepler fp64 stress", err)
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("stress", [False, True])
+def test_kepler_solve_mixed(dev, stress):
+    M, e = synth.kepler_pairs(300001, stress=stress)
+    E = kp.kepler_solve(torch.from_numpy(M).to(dev), torch.from_numpy(e).to(dev), prec="mixed").cpu().numpy()
+    ref = oracle.kepler(M, e)
+    err = np.abs(E - ref)
+    tol = W.kepler_tol_mixed(M, e, ref)
+    _report(f"kepler mixed stress={stress} |dE|", err)
+    _report(f"kepler mixed stress={stress} |dE|/tol", err / tol)
+    assert np.all(err <= tol)
+
+
+def test_kepler_solve_domain_and_empty(dev):
+    M = torch.tensor([1.0, 1.0, float("nan"), 2.0, 0.5], dtype=torch.float64, device=dev)
+    e = torch.tensor([1.0, -0.2, 0.3, float("inf"), 0.0], dtype=torch.float64, device=dev)
+    for prec in ("fp64", "mixed"):
+        E = kp.kepler_solve(M, e, prec=prec).cpu().numpy()
+        assert np.all(np.isnan(E[:4])) and E[4] == 0.5
+    empty = torch.empty(0, dtype=torch.float64, device=dev)
+    assert kp.kepler_solve(empty, empty).numel() == 0
+
+
+# ------------------------------------------------------------------ rv_chisq FP64
+@pytest.mark.parametrize("case", [
+    dict(name="c0", n_sys=None),                        # the full 1024 x 1 x 64 configuration
+    dict(name="c1", n_sys=1200, n_obs=256),             # paper shape, several setup batches
+    dict(name="c1", n_sys=333, n_obs=97, n_pl=3),       # ragged tail of the observation chunks
+    dict(name="c1", n_sys=130, n_obs=600, n_pl=8),      # more than 8 chunks: grouped observations
+    dict(name="c1", n_sys=77, n_obs=1, n_pl=2),
+])
+def test_chisq_fp64_matches_oracle(dev, case):
+    wl = W.dense(case["name"], n_sys=case.get("n_sys"), n_obs=case.get("n_obs"), n_pl=case.get("n_pl"))
+    g = W.to_gpu(wl, dev)
+    chi2 = kp.rv_chisq(**g, prec="fp64").cpu().numpy()
+    ref = W.oracle_par(oracle.chisq, W.oracle_dense(wl), wl.n_sys)
+    err = W.rel_err_chi2(chi2, ref)
+    _report(f"chi2 fp64 {case}", err)
+    assert err.max() <= 1e-12
+
+
+def test_model_fp64_matches_oracle(dev):
+    wl = W.dense("c1", n_sys=96, n_obs=130, n_pl=4)
+    wl.offset = np.linspace(-5, 5, wl.n_sys)
+    g = W.to_gpu(wl, dev)
+    vm = kp.rv_model(g["t"], g["P"], g["K"], g["e"], g["omega"], g["M0"], g["offset"], prec="fp64").cpu().numpy()
+    ref = oracle.rv_model(W.oracle_dense(wl))
+    err = np.abs(vm - ref)
+    _report("model fp64 |dv|", err)
+    assert err.max() <= 1e-9
+
+
+# ------------------------------------------------------------------ rv_chisq mixed
+@pytest.mark.parametrize("case", [
+    dict(name="c2", n_sys=4096),
+    dict(name="c2", n_sys=2048, stress=True),            # e in [0.9, 0.99], one observation near periapsis
+    dict(name="c1", n_sys=500, n_obs=70, n_pl=7),
+    dict(name="c1", n_sys=64, n_obs=1000, n_pl=2),
+    dict(name="c4", n_sys=777, jitter=True),             # offsets and jitter
+])
+def test_chisq_mixed_matches_oracle(dev, case):
+    wl = W.dense(case["name"], n_sys=case.get("n_sys"), n_obs=case.get("n_obs"), n_pl=case.get("n_pl"),
+                 stress=case.get("stress", False), jitter=case.get("jitter", False))
+    g = W.to_gpu(wl, dev)
+    chi2 = kp.rv_chisq(**g, prec="mixed").cpu().numpy()
+    ref = W.oracle_par(oracle.chisq, W.oracle_dense(wl), wl.n_sys)
+    err = W.rel_err_chi2(chi2, ref)
+    _report(f"chi2 mixed {case}", err)
+    assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("stress", [False, True])
+def test_model_mixed_matches_oracle(dev, stress):
+    wl = W.dense("c2", n_sys=512, stress=stress)
+    g = W.to_gpu(wl, dev)
+    vm = kp.rv_model(g["t"], g["P"], g["K"], g["e"], g["omega"], g["M0"], prec="mixed").cpu().numpy()
+    ref = oracle.rv_model(W.oracle_dense(wl))
+    err = np.abs(vm - ref)
+    _report(f"model mixed stress={stress} |dv| m/s", err)
+    assert err.max() <= 1e-3
+
+
+def test_chisq_fp64_early_exit_variant(dev):
+    """The early-exit binary64 variant (fixed_iter < 0) reaches the same root."""
+    wl = W.dense("c1", n_sys=300)
+    g = W.to_gpu(wl, dev)
+    chi2 = kp.rv_chisq(**g, prec="fp64", opts=dict(fixed_iter=-1)).cpu().numpy()
+    ref = W.oracle_par(oracle.chisq, W.oracle_dense(wl), wl.n_sys)
+    assert W.rel_err_chi2(chi2, ref).max() <= 1e-12
+
+
+# ------------------------------------------------------------------ properties
+def test_domain_errors_are_nan_and_isolated(dev):
+    wl = W.dense("c1", n_sys=40, n_obs=64, n_pl=2)
+    wl.e[1, 3] = 1.0
+    wl.e[0, 4] = -0.01
+    wl.P[1, 5] = 0.0
+    wl.M0[0, 6] = np.inf
+    wl.K[0, 7] = np.nan
+    g = W.to_gpu(wl, dev)
+    ref = W.oracle_par(oracle.chisq, W.oracle_dense(wl), wl.n_sys)
+    assert np.all(np.isnan(ref[3:8]))
+    for prec in ("fp64", "mixed"):
+        chi2 = kp.rv_chisq(**g, prec=prec).cpu().numpy()
+        assert np.all(np.isnan(chi2[3:8])), prec
+        ok = np.r_[0:3, 8:40]
+        assert np.all(np.isfinite(chi2[ok]))
+        assert W.rel_err_chi2(chi2[ok], ref[ok]).max() <= (1e-12 if prec == "fp64" else 1e-5)
+    # a bad observation poisons every system without jitter
+    wl.sigma[5] = -1.0
+    g = W.to_gpu(wl, dev)
+    assert np.all(np.isnan(kp.rv_chisq(**g, prec="mixed").cpu().numpy()))
+
+
+def test_empty_and_zero_obs(dev):
+    wl = W.dense("c1", n_sys=10, n_obs=16, n_pl=1)
+    g = W.to_gpu(wl, dev)
+    for prec in ("fp64", "mixed"):
+        z = {k: (v[:, :0] if k in ("P", "K", "e", "omega", "M0") else v) for k, v in g.items()}
+        assert kp.rv_chisq(**z, prec=prec).numel() == 0
+        e0 = dict(g)
+        for k in ("t", "v", "sigma"):
+            e0[k] = g[k][:0]
+        chi2 = kp.rv_chisq(**e0, prec=prec).cpu().numpy()
+        assert np.array_equal(chi2, np.zeros(10))
+
+
+def test_deterministic(dev):
+    wl = W.dense("c2", n_sys=20000)
+    g = W.to_gpu(wl, dev)
+    a = kp.rv_chisq(**g, prec="mixed").cpu().numpy()
+    b = kp.rv_chisq(**g, prec="mixed").cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_launch_shapes_agree(dev):
+    """Every launch shape gives results within tolerance of the oracle."""
+    wl = W.dense("c1", n_sys=700)
+    g = W.to_gpu(wl, dev)
+    ref = W.oracle_par(oracle.chisq, W.oracle_dense(wl), wl.n_sys)
+    for block in (64, 128, 192, 256):
+        for per_cu in (0, 1, 3):
+            chi2 = kp.rv_chisq(**g, prec="mixed", opts=dict(block_threads=block, blocks_per_cu=per_cu)).cpu().numpy()
+            assert W.rel_err_chi2(chi2, ref).max() <= 1e-5, (block, per_cu)
+
+
+def test_full_size_c2_sampled(dev):
+    """The full 1,048,576 x 4 x 256 batch in the launch configuration the benchmark
+    times; 96 systems spread over the batch are checked against the oracle."""
+    wl = W.dense("c2")
+    g = W.to_gpu(wl, dev)
+    chi2 = kp.rv_chisq(**g, prec="mixed").cpu().numpy()
+    assert np.all(np.isfinite(chi2))
+    idx = np.unique(np.r_[0, 1, np.linspace(0, wl.n_sys - 1, 94).astype(int)])
+    d = W.oracle_dense(wl)
+    ref = np.array([oracle.chisq(d, int(i), int(i) + 1)[i] for i in idx])
+    err = W.rel_err_chi2(chi2[idx], ref)
+    _report("chi2 mixed full c2 sampled", err)
+    assert err.max() <= 1e-5

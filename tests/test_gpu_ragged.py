@@ -1,0 +1,133 @@
+"""GPU parity of the ragged (CSR) persistent kernel, its HIP-graph replay and its
+autotuned launch shape, against the oracle.  Mixed precision: chi2 relative
+error <= 1e-5 (relative to max(chi2, 1))."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0812_2976_amd as kp
+import synth
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _ragged(n_sys, seed=None, n_obs_range=(16, 1024), uniform=None, offsets=False, jitter=False):
+    rw = synth.ragged(n_sys=n_sys, seed=seed, n_obs_range=n_obs_range, uniform=uniform)
+    synth.ragged_with_observations(rw, W.oracle_truth_model)
+    rng = np.random.default_rng(7)
+    if offsets:
+        rw.offset = rng.uniform(-10, 10, rw.n_sys)
+    if jitter:
+        rw.jitter = rng.uniform(0, 3, rw.n_sys)
+    return rw
+
+
+def _plan(rw, dev, opts=None):
+    g = lambda x: None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    return kp.RaggedPlan(g(rw.t), g(rw.v), g(rw.sigma), g(rw.obs_off), g(rw.P), g(rw.K), g(rw.e), g(rw.w),
+                         g(rw.M0), g(rw.pl_off), g(rw.offset), g(rw.jitter), rw.t0, "mixed", opts)
+
+
+def _oracle(rw):
+    d = oracle.Ragged(rw.t, rw.v, rw.sigma, rw.obs_off, rw.P, rw.K, rw.e, rw.w, rw.M0, rw.pl_off, rw.offset,
+                      rw.jitter, rw.t0)
+    return W.oracle_par(oracle.chisq_ragged, d, rw.n_sys)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n_sys=3000),
+    dict(n_sys=1500, n_obs_range=(1, 70), offsets=True, jitter=True),
+    dict(n_sys=97, n_obs_range=(200, 1024)),
+])
+def test_ragged_matches_oracle(dev, case):
+    rw = _ragged(case["n_sys"], n_obs_range=case.get("n_obs_range", (16, 1024)),
+                 offsets=case.get("offsets", False), jitter=case.get("jitter", False))
+    plan = _plan(rw, dev)
+    chi2 = plan().cpu().numpy()
+    ref = _oracle(rw)
+    err = W.rel_err_chi2(chi2, ref)
+    print(f"[ragged {case}] max rel {err.max():.3e} info {plan.info()}", flush=True)
+    assert err.max() <= 1e-5
+
+
+def test_ragged_graph_replay_equals_direct(dev):
+    """Several graph replays, with eager work and synchronisation between them,
+    each equal the direct launch bit for bit."""
+    rw = _ragged(2000, seed=11)
+    plan = _plan(rw, dev)
+    direct = plan.direct().cpu().numpy()
+    out = torch.empty(rw.n_sys, dtype=torch.float64, device=dev)
+    for rep in range(4):
+        out.fill_(-1.0)
+        plan(out)
+        torch.cuda.synchronize()
+        x = torch.randn(1000, device=dev).sum()        # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), direct), rep
+    # a new output buffer re-targets the recorded graph
+    other = plan(torch.empty(rw.n_sys, dtype=torch.float64, device=dev)).cpu().numpy()
+    assert np.array_equal(other, direct)
+    assert x.isfinite()
+
+
+def test_ragged_uniform_equals_dense(dev):
+    """A ragged batch whose systems all have the same size matches the dense kernel
+    on the same systems (within the mixed tolerance; lane grouping may differ)."""
+    n_sys, n_pl, n_obs = 300, 4, 256
+    wl = W.dense("c1", n_sys=n_sys)
+    rw = synth.ragged(n_sys=n_sys, uniform=(n_pl, n_obs))
+    rw.t = np.tile(wl.t, n_sys)
+    rw.v = np.tile(wl.v, n_sys)
+    rw.sigma = np.tile(wl.sigma, n_sys)
+    rw.P, rw.K, rw.e, rw.w, rw.M0 = (np.ascontiguousarray(x.T.ravel()) for x in (wl.P, wl.K, wl.e, wl.w, wl.M0))
+    plan = _plan(rw, dev)
+    ragged = plan().cpu().numpy()
+    dense = kp.rv_chisq(**W.to_gpu(wl, dev), prec="mixed").cpu().numpy()
+    assert W.rel_err_chi2(ragged, dense).max() <= 2e-5
+
+
+def test_ragged_launch_shapes_and_fixed_options(dev):
+    rw = _ragged(800, seed=3)
+    ref = _oracle(rw)
+    for block in (64, 128, 256):
+        plan = _plan(rw, dev, opts=dict(block_threads=block))
+        chi2 = plan().cpu().numpy()
+        assert W.rel_err_chi2(chi2, ref).max() <= 1e-5, block
+
+
+def test_ragged_domain_nan_and_edge_sizes(dev):
+    rw = _ragged(60, seed=5, n_obs_range=(1, 300))
+    rw.e[rw.pl_off[10]] = 1.0
+    rw.P[rw.pl_off[20]] = -1.0
+    rw.sigma[rw.obs_off[30]] = np.nan
+    chi2 = _plan(rw, dev)().cpu().numpy()
+    ref = _oracle(rw)
+    bad = np.isnan(ref)
+    assert set(np.nonzero(bad)[0]) == {10, 20, 30}
+    assert np.array_equal(np.isnan(chi2), bad)
+    assert W.rel_err_chi2(chi2[~bad], ref[~bad]).max() <= 1e-5
+
+
+def test_ragged_rejects_bad_offsets(dev):
+    rw = _ragged(10, seed=2)
+    rw.pl_off = rw.pl_off.copy()
+    rw.pl_off[3] = rw.pl_off[2]          # a system with no planet
+    with pytest.raises(kp.KeplerError):
+        _plan(rw, dev)
+
+
+def test_ragged_c3_full_size_sampled(dev):
+    """The full 262,144-system ragged batch as the benchmark runs it; 64 systems
+    spread over the batch are checked against the oracle."""
+    rw = _ragged(262144)
+    plan = _plan(rw, dev)
+    chi2 = plan().cpu().numpy()
+    assert np.all(np.isfinite(chi2))
+    idx = np.unique(np.linspace(0, rw.n_sys - 1, 64).astype(int))
+    d = oracle.Ragged(rw.t, rw.v, rw.sigma, rw.obs_off, rw.P, rw.K, rw.e, rw.w, rw.M0, rw.pl_off, t0=rw.t0)
+    ref = np.array([oracle.chisq_ragged(d, int(i), int(i) + 1)[i] for i in idx])
+    err = W.rel_err_chi2(chi2[idx], ref)
+    print(f"[ragged c3 full] max rel {err.max():.3e} info {plan.info()}", flush=True)
+    assert err.max() <= 1e-5
