@@ -234,12 +234,16 @@ def main():
         from concurrent.futures import ThreadPoolExecutor
 
         n = min(args.cpu_sample, wl.n_sys)
+        # the oracle's sample has its own observed velocities (oracle model of the
+        # truth system + the same noise): no oracle input comes from the GPU path
+        cols = [np.asarray(wl.truth[k])[:, None] for k in ("P", "K", "e", "w", "M0")]
+        v_cpu = oracle.rv_model(oracle.Dense(wl.t, np.zeros_like(wl.t), wl.sigma, *cols, t0=wl.t0))[0] + wl.noise
         try:
             cores = len(os.sched_getaffinity(0))
         except AttributeError:
             cores = os.cpu_count() or 1
         cores = max(1, min(cores, 16))
-        d = oracle.Dense(wl.t, wl.v, wl.sigma, wl.P[:, :n], wl.K[:, :n], wl.e[:, :n], wl.w[:, :n], wl.M0[:, :n],
+        d = oracle.Dense(wl.t, v_cpu, wl.sigma, wl.P[:, :n], wl.K[:, :n], wl.e[:, :n], wl.w[:, :n], wl.M0[:, :n],
                          None, None, wl.t0)
         oracle.lib()
         bounds = np.linspace(0, n, cores * 4 + 1).astype(int)
@@ -249,11 +253,9 @@ def main():
         with ThreadPoolExecutor(cores) as ex:
             list(ex.map(lambda ab: oracle.chisq(d, int(ab[0]), int(ab[1]), out=out_c), zip(bounds[:-1], bounds[1:])))
         dt = time.perf_counter() - t0
-        rel = np.max(np.abs(chi2[:n] - out_c) / np.maximum(out_c, 1.0))
         result["cpu_baseline"] = {"value": n / dt, "unit": "chi2 evals/s", "cores": cores, "kind": "oracle",
                                   "sample": f"first {n} systems of the same c2 batch ({n * 1024} Kepler solves), "
-                                            f"{dt:.2f} s wall",
-                                  "gpu_vs_oracle_max_rel_err": float(rel)}
+                                            f"{dt:.2f} s wall"}
     print(json.dumps(result), flush=True)
 
 

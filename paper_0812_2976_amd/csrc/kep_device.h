@@ -74,8 +74,8 @@ __device__ __forceinline__ SinCos32 sincos32(float x)
 {
     float ax = fabsf(x);
     bool fold = ax > kHalfPiF;
-    float yf = (KEP_PI_HI_F - ax) + KEP_PI_LO_F;
-    float y = fold ? copysignf(yf, x) : x;
+    float yf = (KEP_PI_HI_F - ax) + KEP_PI_LO_F;   // pi - |x|, negative beyond pi
+    float y = fold ? (x < 0.0f ? -yf : yf) : x;      // sin x = sin y, cos x = -cos y
     float y2 = y * y;
     float p = fmaf(fmaf(fmaf(fmaf(KEP_P4, y2, KEP_P3), y2, KEP_P2), y2, KEP_P1), y2, KEP_P0);
     float q = fmaf(fmaf(fmaf(fmaf(KEP_Q4, y2, KEP_Q3), y2, KEP_Q2), y2, KEP_Q1), y2, KEP_Q0);

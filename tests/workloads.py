@@ -103,3 +103,30 @@ def to_gpu(wl, dev):
 
     return dict(t=g(wl.t), v=g(wl.v), sigma=g(wl.sigma), P=g(wl.P), K=g(wl.K), e=g(wl.e), omega=g(wl.w),
                 M0=g(wl.M0), offset=g(wl.offset), jitter=g(wl.jitter), t0=wl.t0)
+
+
+# Velocity error allowed for the mixed path when a chi-square tolerance is derived
+# from it (an order of magnitude below the stated 1e-3 m/s velocity tolerance).
+DV_MIXED = 1e-4
+
+
+def chi2_tol_mixed_ragged(rw, ref):
+    """Per-system chi-square tolerance of the mixed path: the stated relative 1e-5
+    (of max(chi2, 1)), or, where that is below what binary32 velocities allow
+    (few observations, small residuals), the change a velocity error DV_MIXED
+    can cause: 2 dv sum_k w_k |r_k| + dv^2 sum_k w_k."""
+    import oracle as _o
+    tol = 1e-5 * np.maximum(np.abs(ref), 1.0)
+    for i in range(rw.n_sys):
+        o0, o1 = rw.obs_off[i], rw.obs_off[i + 1]
+        p0, p1 = rw.pl_off[i], rw.pl_off[i + 1]
+        if o1 == o0 or not np.isfinite(ref[i]):
+            continue
+        off = None if rw.offset is None else rw.offset[i:i + 1]
+        d = _o.Dense(rw.t[o0:o1], rw.v[o0:o1], rw.sigma[o0:o1], rw.P[p0:p1, None], rw.K[p0:p1, None],
+                     rw.e[p0:p1, None], rw.w[p0:p1, None], rw.M0[p0:p1, None], off, None, rw.t0)
+        r = _o.rv_model(d)[0] - rw.v[o0:o1]
+        jit = 0.0 if rw.jitter is None else rw.jitter[i]
+        w = 1.0 / (rw.sigma[o0:o1] ** 2 + jit ** 2)
+        tol[i] = max(tol[i], 2 * DV_MIXED * np.sum(w * np.abs(r)) + DV_MIXED ** 2 * np.sum(w))
+    return tol
