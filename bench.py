@@ -36,21 +36,25 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic VALU operations per (system, planet, observation) triple of the
 # mixed-precision formulation (operation count of the method as written, each
-# add/mul/fma/convert/compare/select/reciprocal counted once):
-#   phase in binary64                                   10
-#   bracket and starting guess                           4
-#   one Danby iteration (sin, 1-cos, E-sin E polynomials
-#     22, f and derivatives 6, three corrections 12, update 3)   43
-#   velocity (polynomials 22, 1-e cos E, numerator, reciprocal, product 5),
-#     Kahan planet sum 4                                31
-#   per observation: residual, weight, Kahan chi2 (10) / n_pl
-# The eccentricity schedule takes 2 iterations for e <= 0.8525 and 3 up to
-# 0.975; with e ~ U[0, 0.9] the mean is 2 + (0.9 - 0.8525)/0.9 = 2.0528.
-OPS_PHASE, OPS_START, OPS_ITER, OPS_VEL, OPS_OBS = 10, 4, 43, 31, 10
+# add/mul/fma/convert/compare/select/reciprocal/sine/cosine counted once):
+#   orbital phase in binary64 (quotient with correction, two fractions,
+#     scale, convert)                                              10
+#   bracket [M - e, M + e] and the starting guess                   4
+#   each Danby step before the last (hardware sin/cos, f and three
+#     derivatives, three corrections, clamped update)              22
+#   last Danby step (sin, 1 - cos, E - sin E polynomials 22, f and
+#     derivatives 5, three corrections 12, update 3)               42
+#   sin/1-cos carried to the final E 11, velocity 5, Kahan sum 4   20
+#   per observation: binary64 residual 6, weighted square 2,
+#     Kahan chi-square 4 -> 12 / n_pl
+# The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
+# with e ~ U[0, 0.9] the mean number of steps before the last is
+# 1 + (0.9 - 0.8525)/0.9 = 1.0528.
+OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 10, 4, 22, 42, 20, 12
 
 
-def mixed_ops_per_triple(n_pl, mean_iter):
-    return OPS_PHASE + OPS_START + OPS_ITER * mean_iter + OPS_VEL + OPS_OBS / n_pl
+def mixed_ops_per_triple(n_pl, mean_steps):
+    return OPS_PHASE + OPS_START + OPS_FAST * (mean_steps - 1) + OPS_LAST + OPS_VEL + OPS_OBS / n_pl
 
 
 def mean_iterations(e_max, s2=0.8525, s3=0.975):
@@ -108,6 +112,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rows", default="fp64,grad,ragged,kepler", help="extra paths to time (comma list or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="systems in the CPU oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the systems are independent and the path has no cross-GPU "
@@ -122,6 +128,14 @@ def main():
     dev = torch.device("cuda", 0)
     kp.load_library()
     rows = [] if args.rows == "none" else args.rows.split(",")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)      # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device copies")
+        del src, dst
 
     def gpu(x):
         return None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev)

@@ -105,14 +105,16 @@ __device__ __forceinline__ int sched64(double e)
 // One Danby step (Sec. 4.3, quartic; Danby's third correction) on
 // f(E) = E - e sin E - M written as (1-e) E + e (E - sin E) - M, with
 // f' = (1-e) + e (1 - cos E), f'' = e sin E, f''' = e cos E.  The new iterate
-// is kept in the bracket [M - e, M + e] that holds the root.  Returns the step.
-__device__ __forceinline__ float danby_step32(float &E, float M, float e, float ome, float lo, float hi)
+// is kept in the bracket [M - e, M + e] that holds the root.  Returns the step
+// and leaves sin E, 1 - cos E of the iterate it started from in `sc`.
+__device__ __forceinline__ float danby_step32(float &E, float M, float e, float ome, float lo, float hi,
+                                              SinCos32 &sc)
 {
-    SinCos32 sc = sincos32(E);
+    sc = sincos32(E);
     float f = fmaf(ome, E, fmaf(e, sc.xms, -M));
     float f1 = fmaf(e, sc.omc, ome);
     float f2 = e * sc.s;
-    float f3 = e - e * sc.omc;
+    float f3 = fmaf(-e, sc.omc, e);
     float d1 = -f * rcp32(f1);
     float d2 = -f * rcp32(fmaf(0.5f * d1, f2, f1));
     float den3 = fmaf(d2, fmaf(d2, f3 * (1.0f / 6.0f), 0.5f * f2), f1);
@@ -123,21 +125,70 @@ __device__ __forceinline__ float danby_step32(float &E, float M, float e, float 
     return step;
 }
 
-// Kepler solve in binary32 for a centred mean anomaly M in [-pi, pi].
-// niter > 0: that many steps; niter == 0: schedule-free convergence test
-// (|step| <= 2^-22 max(|E|, 1)) capped at max_iter.
-__device__ __forceinline__ float kepler32(float M, float e, float ome, int niter, int max_iter)
+// A Danby step for the iterations before the last one: sin and cos from the
+// hardware transcendental unit (argument in revolutions) and f in its plain
+// form.  Only the last step fixes the accuracy of the root (each step's error
+// is the fourth power of the previous one, plus its own rounding), so the
+// earlier steps may use cheaper, less accurate arithmetic.
+__device__ __forceinline__ void danby_step32_fast(float &E, float M, float e, float lo, float hi)
+{
+    const float r = E * 0.159154943091895336f;
+    const float s = __builtin_amdgcn_sinf(r);
+    const float c = __builtin_amdgcn_cosf(r);
+    float f = fmaf(-e, s, E - M);
+    float f1 = fmaf(-e, c, 1.0f);
+    float f2 = e * s;
+    float f3 = e * c;
+    float d1 = -f * rcp32(f1);
+    float d2 = -f * rcp32(fmaf(0.5f * d1, f2, f1));
+    float den3 = fmaf(d2, fmaf(d2, f3 * (1.0f / 6.0f), 0.5f * f2), f1);
+    float d3 = -f * rcp32(den3);
+    E = __builtin_amdgcn_fmed3f(E + d3, lo, hi);
+}
+
+// sin and 1 - cos at E + d from their values at E, with sin d and 1 - cos d
+// from their Taylor series to d^3 and d^4 (after the first Kepler step |d| is
+// below 0.05, so the dropped terms are below 1e-9): replaces a fresh
+// evaluation after the last step.
+__device__ __forceinline__ void rotate32(float &s, float &omc, float d)
+{
+    float d2 = d * d;
+    float omcd = d2 * fmaf(d2, -1.0f / 24.0f, 0.5f);  // 1 - cos d
+    float sd = d * fmaf(d2, -1.0f / 6.0f, 1.0f);       // sin d
+    float s_new = fmaf(-s, omcd, fmaf(-omc, sd, s + sd));        // sin E cos d + cos E sin d
+    float omc_new = fmaf(s, sd, fmaf(-omc, omcd, omc + omcd));   // 1 - (cos E cos d - sin E sin d)
+    s = s_new;
+    omc = omc_new;
+}
+
+// Kepler solve in binary32 for a centred mean anomaly M in [-pi, pi], from the
+// paper's starting guess E0 = M + 0.85 e sign(M) (sign(sin M) on [-pi, pi]).
+// niter > 0: that many steps; niter == 0: convergence test
+// (|step| <= 2^-22 max(|E|, 1)) capped at max_iter (>= 1).  Returns E and
+// sin E, 1 - cos E at the returned E.
+__device__ __forceinline__ float kepler32(float M, float e, float ome, int niter, int max_iter, float &sinE,
+                                          float &omcE)
 {
     float lo = M - e, hi = M + e;
     float E = fmaf(copysignf(0.85f, M), e, M);
-    if (niter > 0) {
-        for (int it = 0; it < niter; ++it) danby_step32(E, M, e, ome, lo, hi);
-    } else {
-        for (int it = 0; it < max_iter; ++it) {
-            float st = danby_step32(E, M, e, ome, lo, hi);
-            if (fabsf(st) <= 2.384185791e-7f * fmaxf(fabsf(E), 1.0f)) break;
+    SinCos32 sc;
+    float st = 0.0f;
+    const int n = niter > 0 ? niter : (max_iter > 0 ? max_iter : 1);
+    for (int it = 0; it < n; ++it) {
+        if (niter > 0 && it < n - 1) {
+            danby_step32_fast(E, M, e, lo, hi);
+            continue;
         }
+        st = danby_step32(E, M, e, ome, lo, hi, sc);
+        if (niter == 0 && fabsf(st) <= 2.384185791e-7f * fmaxf(fabsf(E), 1.0f)) break;
     }
+    if (__any(fabsf(st) > 0.0625f)) {   // a large last step (e.g. a single fixed step): evaluate afresh
+        sc = sincos32(E);
+        st = 0.0f;
+    }
+    sinE = sc.s;
+    omcE = sc.omc;
+    rotate32(sinE, omcE, st);
     return E;
 }
 

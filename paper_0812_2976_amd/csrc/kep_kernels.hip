@@ -103,11 +103,13 @@ struct PolMixed {
     static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
                                                       int max_iter, int /*fixed: already in rr.niter*/)
     {
-        const double P = uniform_double(rr.P), rP = uniform_double(rr.rP), m0r = uniform_double(rr.m0r);
-        const float e = uniform_float(rr.e), ome = uniform_float(rr.ome);
-        const float A = uniform_float(rr.A), B = uniform_float(rr.B);
+        // rr comes from an LDS broadcast: every lane holds the same values
+        const double P = rr.P, rP = rr.rP, m0r = rr.m0r;
+        const float e = rr.e, ome = rr.ome, A = rr.A, B = rr.B;
         const int niter = uniform_int(rr.niter);
-        float M[NCH], E[NCH], lo[NCH], hi[NCH];
+        const int n = niter > 0 ? niter : (max_iter > 0 ? max_iter : 1);
+        float M[NCH], E[NCH], lo[NCH], hi[NCH], st[NCH];
+        SinCos32 sc[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             double ph = phase_rev(o[c].tt, P, rP, m0r);
@@ -117,26 +119,36 @@ struct PolMixed {
             E[c] = fmaf(copysignf(0.85f, M[c]), e, M[c]);
         }
         if (niter > 0) {
-            for (int it = 0; it < niter; ++it) {
+            for (int it = 0; it < n - 1; ++it) {   // steps before the last: hardware sin/cos
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) danby_step32(E[c], M[c], e, ome, lo[c], hi[c]);
+                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], e, lo[c], hi[c]);
             }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) st[c] = danby_step32(E[c], M[c], e, ome, lo[c], hi[c], sc[c]);
         } else {
-            for (int it = 0; it < max_iter; ++it) {
+            for (int it = 0; it < n; ++it) {       // convergence-tested (beyond the schedule)
                 bool conv = true;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    float st = danby_step32(E[c], M[c], e, ome, lo[c], hi[c]);
-                    conv = conv && (fabsf(st) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
+                    st[c] = danby_step32(E[c], M[c], e, ome, lo[c], hi[c], sc[c]);
+                    conv = conv && (fabsf(st[c]) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
                 }
                 if (__all(conv)) break;
             }
         }
+        if (n == 1) {   // a single fixed step can be large: evaluate afresh instead of rotating
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                sc[c] = sincos32(E[c]);
+                st[c] = 0.0f;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            SinCos32 sc = sincos32(E[c]);
-            float D = fmaf(e, sc.omc, ome);                  // 1 - e cos E
-            float num = fmaf(B, sc.s, fmaf(-A, sc.omc, A));  // A cos E + B sin E
+            float s = sc[c].s, omc = sc[c].omc;
+            rotate32(s, omc, st[c]);
+            float D = fmaf(e, omc, ome);               // 1 - e cos E
+            float num = fmaf(B, s, fmaf(-A, omc, A));  // A cos E + B sin E
             m[c].k.add(num * rcp32(D));
         }
     }
@@ -149,8 +161,7 @@ struct PolMixed {
     static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
                                                    double jit, bool has_jit)
     {
-        float ck = (float)(o.v - gam);
-        float r = (m.k.s - ck) - m.k.c;
+        float r = (float)(((double)m.k.s - (double)m.k.c + gam) - o.v);   // residual formed in binary64
         float w = o.w;
         bool okw = true;
         if (has_jit) {
@@ -391,7 +402,8 @@ __global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, c
             float e32 = (float)e;
             float ome = (float)(1.0 - e);
             int niter = fixed > 0 ? fixed : sched32(e32);
-            float E32 = kepler32(M32, e32, ome, niter, max_iter);
+            float sE, omcE;
+            float E32 = kepler32(M32, e32, ome, niter, max_iter, sE, omcE);
             E = (double)E32;
         } else {
             E = kepler64(Mr, e, Mr >= 0.0 ? 1.0 : -1.0, fixed, max_iter);
@@ -473,19 +485,19 @@ __device__ __forceinline__ float grad_eval(const GradPlanet<float> &g, double tt
     double q = tt * g.rP;                       // unreduced quotient, only for dM/dP
     double ph = phase_rev(tt, g.P, g.rP, g.m0r);
     float M = (float)(ph * kTwoPi);
-    float E = kepler32(M, g.e, g.ome, g.niter, max_iter);
-    SinCos32 sc = sincos32(E);
-    float D = fmaf(g.e, sc.omc, g.ome);         // 1 - e cos E
+    float sE, omcE;
+    kepler32(M, g.e, g.ome, g.niter, max_iter, sE, omcE);
+    float D = fmaf(g.e, omcE, g.ome);           // 1 - e cos E
     float iD = rcp32(D);
-    float cf = (g.ome - sc.omc) * iD;           // cos f = (cos E - e)/D
-    float sf = g.b * sc.s * iD;                 // sin f = b sin E / D
+    float cf = (g.ome - omcE) * iD;             // cos f = (cos E - e)/D
+    float sf = g.b * sE * iD;                   // sin f = b sin E / D
     float cwf = g.cw * cf - g.sw * sf;          // cos(w + f)
     float swf = g.sw * cf + g.cw * sf;          // sin(w + f)
     float dvdK = cwf + g.e * g.cw;
     float v = g.K * dvdK;
-    float ecE = g.e - g.e * sc.omc;             // e cos E
+    float ecE = g.e - g.e * omcE;               // e cos E
     float dfdM = g.b * iD * iD;
-    float dfde = sc.s * (2.0f - ecE - g.e * g.e) * iD * iD * rcp32(g.b);
+    float dfde = sE * (2.0f - ecE - g.e * g.e) * iD * iD * rcp32(g.b);
     float dvdM0 = -g.K * swf * dfdM;
     d[0] = dvdM0 * (float)(-kTwoPi * q * g.rP);
     d[1] = dvdK;
