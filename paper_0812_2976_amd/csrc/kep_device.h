@@ -89,61 +89,80 @@ __device__ __forceinline__ SinCos32 sincos32(float x)
     return r;
 }
 
-// Number of Danby iterations for eccentricity e in binary32 (offline schedule,
+// Per-planet eccentricity constants of the binary32 Kepler step: e, 1 - e
+// (rounded from binary64, so it keeps its relative precision as e -> 1), e/2
+// and e/6 (the factors of f'' and f''' in Danby's corrections).
+struct Ecc32 {
+    float e, ome, eh, e6;
+};
+
+__device__ __forceinline__ Ecc32 make_ecc32(double e)
+{
+    Ecc32 k;
+    k.e = (float)e;
+    k.ome = (float)(1.0 - e);
+    k.eh = (float)(0.5 * e);
+    k.e6 = (float)(e * (1.0 / 6.0));
+    return k;
+}
+
+// Number of Danby steps for eccentricity e in binary32 (offline schedule,
 // worst error 1e-9 rad); 0 means "run the convergence-tested loop".
 __device__ __forceinline__ int sched32(float e)
 {
-    return e <= (float)KEP_S32_E2 ? 2 : e <= (float)KEP_S32_E3 ? 3 : e <= (float)KEP_S32_E4 ? 4
-         : e <= (float)KEP_S32_E5 ? 5 : 0;
+    return e <= (float)KEP_S32_E1 ? 1 : e <= (float)KEP_S32_E2 ? 2 : e <= (float)KEP_S32_E3 ? 3
+         : e <= (float)KEP_S32_E4 ? 4 : e <= (float)KEP_S32_E5 ? 5 : 0;
 }
 
 __device__ __forceinline__ int sched64(double e)
 {
-    return e <= KEP_S64_E2 ? 2 : e <= KEP_S64_E3 ? 3 : e <= KEP_S64_E4 ? 4 : e <= KEP_S64_E5 ? 5 : 0;
+    return e <= KEP_S64_E1 ? 1 : e <= KEP_S64_E2 ? 2 : e <= KEP_S64_E3 ? 3 : e <= KEP_S64_E4 ? 4
+         : e <= KEP_S64_E5 ? 5 : 0;
 }
 
-// One Danby step (Sec. 4.3, quartic; Danby's third correction) on
-// f(E) = E - e sin E - M written as (1-e) E + e (E - sin E) - M, with
-// f' = (1-e) + e (1 - cos E), f'' = e sin E, f''' = e cos E.  The new iterate
-// is kept in the bracket [M - e, M + e] that holds the root.  Returns the step
-// and leaves sin E, 1 - cos E of the iterate it started from in `sc`.
-__device__ __forceinline__ float danby_step32(float &E, float M, float e, float ome, float lo, float hi,
-                                              SinCos32 &sc)
+// Danby's three corrections (Sec. 4.3: Newton, Halley-like, quartic) from
+// f and its derivatives f' = f1, f''/2 = f2h, f'''/6 = f3s.
+__device__ __forceinline__ float danby_delta(float f, float f1, float f2h, float f3s)
 {
-    sc = sincos32(E);
-    float f = fmaf(ome, E, fmaf(e, sc.xms, -M));
-    float f1 = fmaf(e, sc.omc, ome);
-    float f2 = e * sc.s;
-    float f3 = fmaf(-e, sc.omc, e);
     float d1 = -f * rcp32(f1);
-    float d2 = -f * rcp32(fmaf(0.5f * d1, f2, f1));
-    float den3 = fmaf(d2, fmaf(d2, f3 * (1.0f / 6.0f), 0.5f * f2), f1);
-    float d3 = -f * rcp32(den3);
-    float En = __builtin_amdgcn_fmed3f(E + d3, lo, hi);
-    float step = En - E;
-    E = En;
-    return step;
+    float d2 = -f * rcp32(fmaf(d1, f2h, f1));
+    return -f * rcp32(fmaf(d2, fmaf(d2, f3s, f2h), f1));
 }
 
 // A Danby step for the iterations before the last one: sin and cos from the
 // hardware transcendental unit (argument in revolutions) and f in its plain
 // form.  Only the last step fixes the accuracy of the root (each step's error
-// is the fourth power of the previous one, plus its own rounding), so the
-// earlier steps may use cheaper, less accurate arithmetic.
-__device__ __forceinline__ void danby_step32_fast(float &E, float M, float e, float lo, float hi)
+// is about the fourth power of the previous one, plus its own rounding), so
+// the earlier steps may use cheaper, less accurate arithmetic.  The iterate is
+// kept in the bracket [M - e, M + e] that holds the root.
+__device__ __forceinline__ void danby_step32_fast(float &E, float M, const Ecc32 &k, float lo, float hi)
 {
     const float r = E * 0.159154943091895336f;
     const float s = __builtin_amdgcn_sinf(r);
     const float c = __builtin_amdgcn_cosf(r);
-    float f = fmaf(-e, s, E - M);
-    float f1 = fmaf(-e, c, 1.0f);
-    float f2 = e * s;
-    float f3 = e * c;
-    float d1 = -f * rcp32(f1);
-    float d2 = -f * rcp32(fmaf(0.5f * d1, f2, f1));
-    float den3 = fmaf(d2, fmaf(d2, f3 * (1.0f / 6.0f), 0.5f * f2), f1);
-    float d3 = -f * rcp32(den3);
+    const float f = fmaf(-k.e, s, E - M);
+    const float f1 = fmaf(-k.e, c, 1.0f);
+    const float d3 = danby_delta(f, f1, k.eh * s, k.e6 * c);
     E = __builtin_amdgcn_fmed3f(E + d3, lo, hi);
+}
+
+// The accurate Danby step on f(E) = (1-e) E + e (E - sin E) - M, with
+// f' = (1-e) + e (1 - cos E), f'' = e sin E, f''' = e cos E, all free of
+// cancellation near periapsis.  Returns the step and leaves sin E, 1 - cos E
+// of the iterate it started from in `sc`.  With CLAMP the new iterate is kept
+// in [lo, hi]; the last step of the schedule starts within 0.05 of the root
+// and needs no clamp.
+template <bool CLAMP>
+__device__ __forceinline__ float danby_step32(float &E, float M, const Ecc32 &k, float lo, float hi, SinCos32 &sc)
+{
+    sc = sincos32(E);
+    const float f = fmaf(k.ome, E, fmaf(k.e, sc.xms, -M));
+    const float f1 = fmaf(k.e, sc.omc, k.ome);
+    const float d3 = danby_delta(f, f1, k.eh * sc.s, fmaf(-k.e6, sc.omc, k.e6));
+    const float En = CLAMP ? __builtin_amdgcn_fmed3f(E + d3, lo, hi) : E + d3;
+    const float step = En - E;
+    E = En;
+    return step;
 }
 
 // sin and 1 - cos at E + d from their values at E, with sin d and 1 - cos d
@@ -163,26 +182,31 @@ __device__ __forceinline__ void rotate32(float &s, float &omc, float d)
 
 // Kepler solve in binary32 for a centred mean anomaly M in [-pi, pi], from the
 // paper's starting guess E0 = M + 0.85 e sign(M) (sign(sin M) on [-pi, pi]).
-// niter > 0: that many steps; niter == 0: convergence test
-// (|step| <= 2^-22 max(|E|, 1)) capped at max_iter (>= 1).  Returns E and
-// sin E, 1 - cos E at the returned E.
-__device__ __forceinline__ float kepler32(float M, float e, float ome, int niter, int max_iter, float &sinE,
-                                          float &omcE)
+// niter > 0: that many steps (all but the last one cheap); niter == 0:
+// accurate, clamped steps until |step| <= 2^-22 max(|E|, 1), at most max_iter.
+// check_large: the step count was fixed by the caller rather than the
+// schedule.  Returns E and sin E, 1 - cos E at the returned E.
+__device__ __forceinline__ float kepler32(float M, const Ecc32 &k, int niter, int max_iter, bool check_large,
+                                          float &sinE, float &omcE)
 {
-    float lo = M - e, hi = M + e;
-    float E = fmaf(copysignf(0.85f, M), e, M);
+    const float lo = M - k.e, hi = M + k.e;
+    float E = fmaf(copysignf(0.85f, M), k.e, M);
     SinCos32 sc;
     float st = 0.0f;
-    const int n = niter > 0 ? niter : (max_iter > 0 ? max_iter : 1);
-    for (int it = 0; it < n; ++it) {
-        if (niter > 0 && it < n - 1) {
-            danby_step32_fast(E, M, e, lo, hi);
-            continue;
+    if (niter > 0) {
+        for (int it = 0; it < niter - 1; ++it) danby_step32_fast(E, M, k, lo, hi);
+        st = danby_step32<false>(E, M, k, lo, hi, sc);
+    } else {
+        check_large = true;
+        const int n = max_iter > 0 ? max_iter : 1;
+        for (int it = 0; it < n; ++it) {
+            st = danby_step32<true>(E, M, k, lo, hi, sc);
+            if (fabsf(st) <= 2.384185791e-7f * fmaxf(fabsf(E), 1.0f)) break;
         }
-        st = danby_step32(E, M, e, ome, lo, hi, sc);
-        if (niter == 0 && fabsf(st) <= 2.384185791e-7f * fmaxf(fabsf(E), 1.0f)) break;
     }
-    if (__any(fabsf(st) > 0.0625f)) {   // a large last step (e.g. a single fixed step): evaluate afresh
+    // The schedule guarantees a last step below 0.05; a caller-fixed step count
+    // or an unconverged loop may not: then evaluate afresh instead of rotating.
+    if (check_large && __any(fabsf(st) > 0.0625f)) {
         sc = sincos32(E);
         st = 0.0f;
     }
@@ -192,19 +216,34 @@ __device__ __forceinline__ float kepler32(float M, float e, float ome, int niter
     return E;
 }
 
-// Orbital phase in revolutions, centred on [-1/2, 1/2]:
-// frac((t - t0)/P + M0/(2 pi)) with the quotient formed from a correctly
-// rounded reciprocal and one residual correction (binary64, Sec. 5.1).  The
-// integer part of the quotient is removed before M0 is added, so no bits of
-// the fraction are lost at large epochs.
-__device__ __forceinline__ double phase_rev(double tt, double P, double rP, double m0r)
+// Per-planet constants of the binary64 orbital phase: P, 1/P (correctly
+// rounded) and fract(M0/(2 pi) + 1/2).
+struct Phase64 {
+    double P, rP, m0h;
+};
+
+__device__ __forceinline__ Phase64 make_phase64(double P, double M0)
 {
-    double q0 = tt * rP;
-    double res = fma(-q0, P, tt);
-    double q = fma(res, rP, q0);
-    double fq = q - rint(q);
-    double ph = fq + m0r;
-    return ph - rint(ph);
+    Phase64 p;
+    p.P = P;
+    p.rP = 1.0 / P;
+    p.m0h = __builtin_amdgcn_fract(fma(M0, kInvTwoPi, 0.5));
+    return p;
+}
+
+// Mean anomaly centred on [-pi, pi) (Sec. 4.2, Eq. 6, with the bracket in
+// binary64 as in Sec. 5.1), rounded to binary32 only at the end:
+// M = 2 pi (fract(fract(q) + fract(M0/(2 pi) + 1/2)) - 1/2), q = (t - t0)/P
+// formed from the correctly rounded 1/P with one residual correction.  The
+// integer part of q is removed before M0 is added, so no bits of the phase
+// are lost at large epochs.
+__device__ __forceinline__ float mean_anomaly32(double tt, const Phase64 &p)
+{
+    const double q0 = tt * p.rP;
+    const double res = fma(-q0, p.P, tt);
+    const double q = fma(res, p.rP, q0);
+    const double u = __builtin_amdgcn_fract(q) + p.m0h;
+    return (float)fma(__builtin_amdgcn_fract(u), kTwoPi, -kPi);
 }
 
 // ----------------------------------------------------------------- binary64

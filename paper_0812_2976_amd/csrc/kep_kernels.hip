@@ -31,10 +31,11 @@ __device__ __forceinline__ bool planet_ok(double P, double K, double e, double w
 }
 
 // ------------------------------------------------------------------ mixed
-struct RecMixed {          // 48 bytes, one per (system, planet)
-    double P, rP, m0r;     // period, 1/P, M0 / (2 pi) reduced to [-1/2, 1/2]
-    float e, ome, A, B;    // e, 1 - e (rounded from binary64), K b^2 cos w, -K b sin w
-    int niter, pad;
+struct RecMixed {          // 64 bytes, one per (system, planet)
+    Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
+    Ecc32 k;               // e, 1 - e, e/2, e/6
+    float A, B;            // K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
+    int niter, check;      // Danby steps (0: convergence test); 1 if fixed by the caller
 };
 
 struct ObsMixed {
@@ -57,21 +58,15 @@ struct PolMixed {
     {
         bool ok = planet_ok(P, K, e, w, M0);
         if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
-        r.P = P;
-        r.rP = 1.0 / P;
-        double m0r = M0 * kInvTwoPi;
-        r.m0r = m0r - rint(m0r);
-        double ome = 1.0 - e;
-        double b2 = ome * (1.0 + e);
-        double b = sqrt(b2);
+        r.ph = make_phase64(P, M0);
+        r.k = make_ecc32(e);
+        const double b2 = (1.0 - e) * (1.0 + e);
         double sw, cw;
         sincos(w, &sw, &cw);
-        r.e = (float)e;
-        r.ome = (float)ome;
         r.A = (float)(K * b2 * cw);
-        r.B = (float)(-K * b * sw);
-        r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32((float)e);
-        r.pad = 0;
+        r.B = (float)(-K * sqrt(b2) * sw);
+        r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e);
+        r.check = a.fixed_iter > 0 ? 1 : 0;
         return ok;
     }
 
@@ -104,50 +99,57 @@ struct PolMixed {
                                                       int max_iter, int /*fixed: already in rr.niter*/)
     {
         // rr comes from an LDS broadcast: every lane holds the same values
-        const double P = rr.P, rP = rr.rP, m0r = rr.m0r;
-        const float e = rr.e, ome = rr.ome, A = rr.A, B = rr.B;
+        const Phase64 ph = rr.ph;
+        const Ecc32 k = rr.k;
+        const float A = rr.A, B = rr.B;
         const int niter = uniform_int(rr.niter);
-        const int n = niter > 0 ? niter : (max_iter > 0 ? max_iter : 1);
         float M[NCH], E[NCH], lo[NCH], hi[NCH], st[NCH];
         SinCos32 sc[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            double ph = phase_rev(o[c].tt, P, rP, m0r);
-            M[c] = (float)(ph * kTwoPi);
-            lo[c] = M[c] - e;
-            hi[c] = M[c] + e;
-            E[c] = fmaf(copysignf(0.85f, M[c]), e, M[c]);
+            M[c] = mean_anomaly32(o[c].tt, ph);
+            lo[c] = M[c] - k.e;
+            hi[c] = M[c] + k.e;
+            E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
         }
+        bool check = uniform_int(rr.check) != 0;
         if (niter > 0) {
-            for (int it = 0; it < n - 1; ++it) {   // steps before the last: hardware sin/cos
+            for (int it = 0; it < niter - 1; ++it) {   // steps before the last: hardware sin/cos
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], e, lo[c], hi[c]);
+                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k, lo[c], hi[c]);
             }
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) st[c] = danby_step32(E[c], M[c], e, ome, lo[c], hi[c], sc[c]);
+            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, lo[c], hi[c], sc[c]);
         } else {
-            for (int it = 0; it < n; ++it) {       // convergence-tested (beyond the schedule)
+            check = true;
+            const int n = max_iter > 0 ? max_iter : 1;
+            for (int it = 0; it < n; ++it) {           // convergence-tested (beyond the schedule)
                 bool conv = true;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    st[c] = danby_step32(E[c], M[c], e, ome, lo[c], hi[c], sc[c]);
+                    st[c] = danby_step32<true>(E[c], M[c], k, lo[c], hi[c], sc[c]);
                     conv = conv && (fabsf(st[c]) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
                 }
                 if (__all(conv)) break;
             }
         }
-        if (n == 1) {   // a single fixed step can be large: evaluate afresh instead of rotating
+        if (check) {   // a last step the schedule does not bound: evaluate afresh where it is large
+            bool large = false;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                sc[c] = sincos32(E[c]);
-                st[c] = 0.0f;
+            for (int c = 0; c < NCH; ++c) large = large || fabsf(st[c]) > 0.0625f;
+            if (__any(large)) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    sc[c] = sincos32(E[c]);
+                    st[c] = 0.0f;
+                }
             }
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             float s = sc[c].s, omc = sc[c].omc;
             rotate32(s, omc, st[c]);
-            float D = fmaf(e, omc, ome);               // 1 - e cos E
+            float D = fmaf(k.e, omc, k.ome);           // 1 - e cos E
             float num = fmaf(B, s, fmaf(-A, omc, A));  // A cos E + B sin E
             m[c].k.add(num * rcp32(D));
         }
@@ -319,9 +321,19 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
     };
     if (n_groups <= 1) load_group(0);
 
-    for (int64_t bt = gw; bt < n_batches; bt += n_waves) {
+    // Model velocities need no reduction over observations, so their work items
+    // are (batch, observation group) pairs: a few systems with very many
+    // observations still spread over the whole chip.
+    const int64_t n_items = MODEL ? n_batches * n_groups : n_batches;
+    int64_t prev_bt = -1;
+    for (int64_t item = gw; item < n_items; item += n_waves) {
+        const int64_t bt = MODEL ? item / n_groups : item;
+        const int g_first = MODEL ? (int)(item - bt * n_groups) : 0;
+        const int g_end = MODEL ? g_first + 1 : n_groups;
         const int64_t s0 = bt * a.sb;
         const int nb = (int)min((int64_t)a.sb, a.n_sys - s0);
+        if (bt != prev_bt) {
+        prev_bt = bt;
         wave_sync_lds();
         if (lane < nb) {
             const int64_t sys = s0 + lane;
@@ -337,6 +349,7 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
             sysbad[lane] = ok ? 0 : 1;
         }
         wave_sync_lds();
+        }
 
         for (int s = 0; s < nb; ++s) {
             const int64_t sys = s0 + s;
@@ -346,7 +359,7 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
             typename Pol::ChiAcc chi;
             Pol::chi_init(chi);
             bool bad_obs = false;
-            for (int g = 0; g < n_groups; ++g) {
+            for (int g = g_first; g < g_end; ++g) {
                 if (n_groups > 1) load_group(g);
                 ModelAcc m[NCH];
 #pragma unroll
@@ -398,13 +411,10 @@ __global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, c
         Mr = fma(-kq, kTwoPiLo, Mr);
         double E;
         if (MIXED) {
-            float M32 = (float)Mr;
-            float e32 = (float)e;
-            float ome = (float)(1.0 - e);
-            int niter = fixed > 0 ? fixed : sched32(e32);
-            float sE, omcE;
-            float E32 = kepler32(M32, e32, ome, niter, max_iter, sE, omcE);
-            E = (double)E32;
+            const Ecc32 k = make_ecc32(e);
+            const int niter = fixed > 0 ? fixed : sched32(k.e);
+            float sE, omcE;   // unused here: the standalone solve returns E only
+            E = (double)kepler32((float)Mr, k, niter, max_iter, fixed > 0, sE, omcE);
         } else {
             E = kepler64(Mr, e, Mr >= 0.0 ? 1.0 : -1.0, fixed, max_iter);
         }
@@ -432,9 +442,11 @@ __global__ void k_fill_u32(unsigned int *p, unsigned int value, int64_t n)
 template <class T> struct GradPlanet;
 
 template <> struct GradPlanet<float> {
-    double P, rP, m0r;
-    float e, ome, b, K, cw, sw;
-    int niter;
+    Phase64 ph;                // P, 1/P, fract(M0/(2 pi) + 1/2)
+    Ecc32 k;                   // e, 1 - e, e/2, e/6
+    float b, K, cw, sw;        // sqrt(1 - e^2), K, cos w, sin w
+    float Kecw, c0;            // K e cos w, 2 - e - e^2
+    int niter, check;
 };
 
 template <> struct GradPlanet<double> {
@@ -446,20 +458,18 @@ __device__ __forceinline__ bool grad_setup(double P, double K, double e, double 
 {
     bool ok = planet_ok(P, K, e, w, M0);
     if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
-    g.P = P;
-    g.rP = 1.0 / P;
-    double m0r = M0 * kInvTwoPi;
-    g.m0r = m0r - rint(m0r);
-    double ome = 1.0 - e;
-    g.e = (float)e;
-    g.ome = (float)ome;
-    g.b = (float)sqrt(ome * (1.0 + e));
+    g.ph = make_phase64(P, M0);
+    g.k = make_ecc32(e);
+    g.b = (float)sqrt((1.0 - e) * (1.0 + e));
     g.K = (float)K;
     double sw, cw;
     sincos(w, &sw, &cw);
     g.cw = (float)cw;
     g.sw = (float)sw;
-    g.niter = fixed_iter > 0 ? fixed_iter : sched32((float)e);
+    g.Kecw = (float)(K * e * cw);
+    g.c0 = (float)(2.0 - e - e * e);
+    g.niter = fixed_iter > 0 ? fixed_iter : sched32(g.k.e);
+    g.check = fixed_iter > 0 ? 1 : 0;
     return ok;
 }
 
@@ -478,35 +488,37 @@ __device__ __forceinline__ bool grad_setup(double P, double K, double e, double 
     return ok;
 }
 
-// Velocity of one planet and its five partial derivatives at time tt = t - t0.
-// d[0..4] = dv/d(P, K, e, omega, M0).
-__device__ __forceinline__ float grad_eval(const GradPlanet<float> &g, double tt, int max_iter, float (&d)[5])
+// Velocity of one planet at time tt = t - t0 and the five per-observation
+// terms whose weighted sums give its gradient (the planet's constant factors
+// are applied once per system):
+//   x[0] = sin(w+f) df/dM q      dv/dP  = (2 pi K / P) x[0]
+//   x[1] = cos(w+f)              dv/dK  = x[1] + e cos w
+//   x[2] = sin(w+f) df/de        dv/de  = K cos w - K x[2]
+//   x[3] = sin(w+f)              dv/dw  = -K x[3] - K e sin w
+//   x[4] = sin(w+f) df/dM        dv/dM0 = -K x[4]
+// with q = (t - t0)/P, df/dM = b/D^2, df/de = sin E (2 - e cos E - e^2)/(b D^2).
+__device__ __forceinline__ float grad_terms(const GradPlanet<float> &g, double tt, int max_iter, float (&x)[5])
 {
-    double q = tt * g.rP;                       // unreduced quotient, only for dM/dP
-    double ph = phase_rev(tt, g.P, g.rP, g.m0r);
-    float M = (float)(ph * kTwoPi);
+    const float M = mean_anomaly32(tt, g.ph);
     float sE, omcE;
-    kepler32(M, g.e, g.ome, g.niter, max_iter, sE, omcE);
-    float D = fmaf(g.e, omcE, g.ome);           // 1 - e cos E
-    float iD = rcp32(D);
-    float cf = (g.ome - omcE) * iD;             // cos f = (cos E - e)/D
-    float sf = g.b * sE * iD;                   // sin f = b sin E / D
-    float cwf = g.cw * cf - g.sw * sf;          // cos(w + f)
-    float swf = g.sw * cf + g.cw * sf;          // sin(w + f)
-    float dvdK = cwf + g.e * g.cw;
-    float v = g.K * dvdK;
-    float ecE = g.e - g.e * omcE;               // e cos E
-    float dfdM = g.b * iD * iD;
-    float dfde = sE * (2.0f - ecE - g.e * g.e) * iD * iD * rcp32(g.b);
-    float dvdM0 = -g.K * swf * dfdM;
-    d[0] = dvdM0 * (float)(-kTwoPi * q * g.rP);
-    d[1] = dvdK;
-    d[2] = g.K * g.cw - g.K * swf * dfde;
-    d[3] = -g.K * (swf + g.e * g.sw);
-    d[4] = dvdM0;
-    return v;
+    kepler32(M, g.k, g.niter, max_iter, g.check != 0, sE, omcE);
+    const float iD = rcp32(fmaf(g.k.e, omcE, g.k.ome));   // 1 / (1 - e cos E)
+    const float cf = (g.k.ome - omcE) * iD;                 // cos f = (cos E - e)/D
+    const float sf = g.b * sE * iD;                         // sin f = b sin E / D
+    const float cwf = g.cw * cf - g.sw * sf;                // cos(w + f)
+    const float swf = g.sw * cf + g.cw * sf;                // sin(w + f)
+    const float iD2 = iD * iD;
+    const float a = swf * (g.b * iD2);                      // sin(w+f) df/dM
+    x[0] = a * (float)(tt * g.ph.rP);
+    x[1] = cwf;
+    x[2] = swf * (sE * fmaf(g.k.e, omcE, g.c0) * iD2 * rcp32(g.b));
+    x[3] = swf;
+    x[4] = a;
+    return fmaf(g.K, cwf, g.Kecw);
 }
 
+// binary64 plain path: velocity of one planet and its five partial derivatives
+// d[0..4] = dv/d(P, K, e, omega, M0) at tt = t - t0.
 __device__ __forceinline__ double grad_eval(const GradPlanet<double> &g, double tt, int max_iter, int fixed,
                                             double (&d)[5])
 {
@@ -552,38 +564,53 @@ __global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
         if (a.offset) ok = ok && isfinite(gam);
         if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
         const float jit2 = (float)(jit * jit);
-        Kahan32 chi, gacc[5 * NPL + 1];
+        Kahan32 chi;
         chi.init();
+        double acc[NPL][5], sum_c2 = 0.0;   // binary64 running sums of 2 w r x
 #pragma unroll
-        for (int i = 0; i < 5 * NPL + 1; ++i) gacc[i].init();
+        for (int j = 0; j < NPL; ++j) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) acc[j][i] = 0.0;
+        }
         for (int64_t k = 0; k < a.n_obs; ++k) {
             const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
             ok = ok && isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0;
             const double tt = t - a.t0;
-            float d[NPL][5];
+            float x[NPL][5];
             Kahan32 msum;
             msum.init();
 #pragma unroll
-            for (int j = 0; j < NPL; ++j) msum.add(grad_eval(pl[j], tt, a.max_iter, d[j]));
-            const float ck = (float)(vo - gam);
-            const float r = (msum.s - ck) - msum.c;
+            for (int j = 0; j < NPL; ++j) msum.add(grad_terms(pl[j], tt, a.max_iter, x[j]));
+            const float r = (float)(((double)msum.s - (double)msum.c + gam) - vo);
             const float var = (float)(sg * sg) + jit2;
             ok = ok && var > 0.0f;
-            const float w = rcp32(var);
-            const float wr = w * r;
+            const float wr = rcp32(var) * r;
             chi.add(wr * r);
-            const float c2 = 2.0f * wr;
+            const double c2 = 2.0 * (double)wr;
+            sum_c2 += c2;
 #pragma unroll
             for (int j = 0; j < NPL; ++j) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i) gacc[5 * j + i].add(c2 * d[j][i]);
+                for (int i = 0; i < 5; ++i) acc[j][i] = fma(c2, (double)x[j][i], acc[j][i]);
             }
-            gacc[5 * NPL].add(c2);
         }
         const double nan = __builtin_nan("");
         a.out[sys] = ok ? chi.value() : nan;
 #pragma unroll
-        for (int i = 0; i < 5 * NPL + 1; ++i) a.grad[(int64_t)i * a.n_sys + sys] = ok ? gacc[i].value() : nan;
+        for (int j = 0; j < NPL; ++j) {
+            const int64_t p = (int64_t)j * a.n_sys + sys;
+            const double K = a.K[p], e = a.e[p], P = a.P[p];
+            const double cw = pl[j].cw, sw = pl[j].sw;
+            double gj[5];
+            gj[0] = kTwoPi * K / P * acc[j][0];
+            gj[1] = acc[j][1] + e * cw * sum_c2;
+            gj[2] = K * cw * sum_c2 - K * acc[j][2];
+            gj[3] = -K * acc[j][3] - K * e * sw * sum_c2;
+            gj[4] = -K * acc[j][4];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) a.grad[(int64_t)(5 * j + i) * a.n_sys + sys] = ok ? gj[i] : nan;
+        }
+        a.grad[(int64_t)(5 * NPL) * a.n_sys + sys] = ok ? sum_c2 : nan;
     }
 }
 
@@ -794,10 +821,11 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     size_t lds = rec_bytes * (size_t)sb_cap;
     const int nch_needed = (int)((a.n_obs + 63) / 64);
     void (*kern)(DenseArgs);
-    if (nch_needed <= 1) kern = k_dense<Pol, 1, MODEL>;
-    else if (nch_needed <= 2) kern = k_dense<Pol, 2, MODEL>;
-    else if (nch_needed <= 4) kern = k_dense<Pol, 4, MODEL>;
-    else kern = k_dense<Pol, 8, MODEL>;
+    int nch;
+    if (nch_needed <= 1) { kern = k_dense<Pol, 1, MODEL>; nch = 1; }
+    else if (nch_needed <= 2) { kern = k_dense<Pol, 2, MODEL>; nch = 2; }
+    else if (nch_needed <= 4) { kern = k_dense<Pol, 4, MODEL>; nch = 4; }
+    else { kern = k_dense<Pol, 8, MODEL>; nch = 8; }
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
         int occ = 0;
@@ -810,7 +838,9 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     a.sb = (int)sb;
     lds = rec_bytes * (size_t)sb;
     const int64_t n_batches = (a.n_sys + sb - 1) / sb;
-    int64_t grid = (n_batches + wpb - 1) / wpb;
+    const int64_t n_groups = (a.n_obs + 64 * nch - 1) / (64 * nch);
+    const int64_t n_items = MODEL ? n_batches * (n_groups > 0 ? n_groups : 1) : n_batches;
+    int64_t grid = (n_items + wpb - 1) / wpb;
     const int64_t cap = (int64_t)device_cu_count() * per_cu;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
