@@ -110,14 +110,13 @@ __device__ __forceinline__ Ecc32 make_ecc32(double e)
 // worst error 1e-9 rad); 0 means "run the convergence-tested loop".
 __device__ __forceinline__ int sched32(float e)
 {
-    return e <= (float)KEP_S32_E1 ? 1 : e <= (float)KEP_S32_E2 ? 2 : e <= (float)KEP_S32_E3 ? 3
-         : e <= (float)KEP_S32_E4 ? 4 : e <= (float)KEP_S32_E5 ? 5 : 0;
+    return e <= (float)KEP_S32_E2 ? 2 : e <= (float)KEP_S32_E3 ? 3 : e <= (float)KEP_S32_E4 ? 4
+         : e <= (float)KEP_S32_E5 ? 5 : 0;
 }
 
 __device__ __forceinline__ int sched64(double e)
 {
-    return e <= KEP_S64_E1 ? 1 : e <= KEP_S64_E2 ? 2 : e <= KEP_S64_E3 ? 3 : e <= KEP_S64_E4 ? 4
-         : e <= KEP_S64_E5 ? 5 : 0;
+    return e <= KEP_S64_E2 ? 2 : e <= KEP_S64_E3 ? 3 : e <= KEP_S64_E4 ? 4 : e <= KEP_S64_E5 ? 5 : 0;
 }
 
 // Danby's three corrections (Sec. 4.3: Newton, Halley-like, quartic) from

@@ -55,14 +55,15 @@ def kepler_tol_mixed(M, e, E_ref):
     """Error bound of a binary32 Kepler solve (derivation in the design notes):
     the argument is reduced to [-pi, pi] in binary64 and rounded (u |Mr|), the
     converged iterate leaves |f| <= 8 u (|Mr| + |Er|) of evaluation error,
-    divided by f' = 1 - e cos E, plus the rounding of E itself and the 1e-9 rad
-    of the iteration schedule."""
+    divided by f' = 1 - e cos E, plus the rounding of E itself, the rounding of
+    the last step (a few ulp of a step of at most 0.015 rad after the
+    schedule's earlier steps) and the 1e-9 rad of the iteration schedule."""
     u = 2.0 ** -24
     k = np.rint(M / TWO_PI)
     Mr = M - k * TWO_PI
     Er = E_ref - k * TWO_PI
     fp = 1.0 - e * np.cos(E_ref)
-    return 8 * u * (np.abs(Mr) + np.abs(Er)) / fp + 2 * u * np.abs(Er) + 1e-9 + 4e-16 * np.abs(E_ref)
+    return 8 * u * (np.abs(Mr) + np.abs(Er)) / fp + 2 * u * np.abs(Er) + 4 * u * 0.015 + 1e-9 + 4e-16 * np.abs(E_ref)
 
 
 def n_threads():
