@@ -36,21 +36,21 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic VALU operations per (system, planet, observation) triple of the
 # mixed-precision formulation (operation count of the method as written, each
-# add/mul/fma/convert/compare/select/reciprocal/sine/cosine counted once):
-#   orbital phase in binary64 (quotient with correction, two fractions,
-#     scale, convert)                                              10
-#   bracket [M - e, M + e] and the starting guess                   4
-#   each Danby step before the last (hardware sin/cos, f and three
-#     derivatives, three corrections, clamped update)              22
-#   last Danby step (sin, 1 - cos, E - sin E polynomials 22, f and
-#     derivatives 5, three corrections 12, update 3)               42
-#   sin/1-cos carried to the final E 11, velocity 5, Kahan sum 4   20
+# add/mul/fma/fract/convert/compare/select/reciprocal/sine/cosine counted once):
+#   orbital phase in binary64: quotient and its correction 3, two fractions
+#     and the M0 offset 3, scale to [-pi, pi) 1, convert 1                  8
+#   bracket [M - e, M + e] and the starting guess                          4
+#   each Danby step before the last: scale, hardware sin and cos 3,
+#     f and its three derivatives 5, three corrections 9, clamped update 2 19
+#   last Danby step: sin, 1 - cos, E - sin E with folding 23, f and its
+#     three derivatives 5, three corrections 9, update and step 2         39
+#   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20
 #   per observation: binary64 residual 6, weighted square 2,
 #     Kahan chi-square 4 -> 12 / n_pl
 # The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
 # with e ~ U[0, 0.9] the mean number of steps before the last is
 # 1 + (0.9 - 0.8525)/0.9 = 1.0528.
-OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 10, 4, 22, 42, 20, 12
+OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 8, 4, 19, 39, 20, 12
 
 
 def mixed_ops_per_triple(n_pl, mean_steps):

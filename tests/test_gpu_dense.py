@@ -1,7 +1,7 @@
 """GPU parity of the dense entry points (kepler_solve, rv_model, rv_chisq) with the
 CPU oracle, called through the C ABI on seeded inputs.
 
-Tolerances (north star / derivation in the design notes):
+Tolerances (stated targets, or derived where noted in the design notes):
   binary64 path: |dE| <= 1e-12 rad, chi2 relative (to max(chi2, 1)) <= 1e-12,
                  model velocity |dv| <= 1e-9 m/s
   mixed path:    model velocity |dv| <= 1e-3 m/s, chi2 relative <= 1e-5,
