@@ -132,17 +132,17 @@ __device__ __forceinline__ float danby_delta(float f, float f1, float f2h, float
 // hardware transcendental unit (argument in revolutions) and f in its plain
 // form.  Only the last step fixes the accuracy of the root (each step's error
 // is about the fourth power of the previous one, plus its own rounding), so
-// the earlier steps may use cheaper, less accurate arithmetic.  The iterate is
-// kept in the bracket [M - e, M + e] that holds the root.
-__device__ __forceinline__ void danby_step32_fast(float &E, float M, const Ecc32 &k, float lo, float hi)
+// the earlier steps may use cheaper, less accurate arithmetic.  Within the
+// schedule no clamp to the root's bracket is needed: the worst errors over
+// the scanned (e, M) grid are the same with and without it.
+__device__ __forceinline__ void danby_step32_fast(float &E, float M, const Ecc32 &k)
 {
     const float r = E * 0.159154943091895336f;
     const float s = __builtin_amdgcn_sinf(r);
     const float c = __builtin_amdgcn_cosf(r);
     const float f = fmaf(-k.e, s, E - M);
     const float f1 = fmaf(-k.e, c, 1.0f);
-    const float d3 = danby_delta(f, f1, k.eh * s, k.e6 * c);
-    E = __builtin_amdgcn_fmed3f(E + d3, lo, hi);
+    E += danby_delta(f, f1, k.eh * s, k.e6 * c);
 }
 
 // The accurate Danby step on f(E) = (1-e) E + e (E - sin E) - M, with
@@ -188,15 +188,15 @@ __device__ __forceinline__ void rotate32(float &s, float &omc, float d)
 __device__ __forceinline__ float kepler32(float M, const Ecc32 &k, int niter, int max_iter, bool check_large,
                                           float &sinE, float &omcE)
 {
-    const float lo = M - k.e, hi = M + k.e;
     float E = fmaf(copysignf(0.85f, M), k.e, M);
     SinCos32 sc;
     float st = 0.0f;
     if (niter > 0) {
-        for (int it = 0; it < niter - 1; ++it) danby_step32_fast(E, M, k, lo, hi);
-        st = danby_step32<false>(E, M, k, lo, hi, sc);
+        for (int it = 0; it < niter - 1; ++it) danby_step32_fast(E, M, k);
+        st = danby_step32<false>(E, M, k, 0.0f, 0.0f, sc);
     } else {
         check_large = true;
+        const float lo = M - k.e, hi = M + k.e;
         const int n = max_iter > 0 ? max_iter : 1;
         for (int it = 0; it < n; ++it) {
             st = danby_step32<true>(E, M, k, lo, hi, sc);

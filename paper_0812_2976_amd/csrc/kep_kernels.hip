@@ -103,31 +103,29 @@ struct PolMixed {
         const Ecc32 k = rr.k;
         const float A = rr.A, B = rr.B;
         const int niter = uniform_int(rr.niter);
-        float M[NCH], E[NCH], lo[NCH], hi[NCH], st[NCH];
+        float M[NCH], E[NCH], st[NCH];
         SinCos32 sc[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             M[c] = mean_anomaly32(o[c].tt, ph);
-            lo[c] = M[c] - k.e;
-            hi[c] = M[c] + k.e;
             E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
         }
         bool check = uniform_int(rr.check) != 0;
         if (niter > 0) {
             for (int it = 0; it < niter - 1; ++it) {   // steps before the last: hardware sin/cos
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k, lo[c], hi[c]);
+                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k);
             }
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, lo[c], hi[c], sc[c]);
+            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
         } else {
             check = true;
             const int n = max_iter > 0 ? max_iter : 1;
-            for (int it = 0; it < n; ++it) {           // convergence-tested (beyond the schedule)
-                bool conv = true;
+            for (int it = 0; it < n; ++it) {           // convergence-tested (beyond the schedule),
+                bool conv = true;                      // clamped to the bracket [M - e, M + e]
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    st[c] = danby_step32<true>(E[c], M[c], k, lo[c], hi[c], sc[c]);
+                    st[c] = danby_step32<true>(E[c], M[c], k, M[c] - k.e, M[c] + k.e, sc[c]);
                     conv = conv && (fabsf(st[c]) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
                 }
                 if (__all(conv)) break;
@@ -398,29 +396,50 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
 // M is reduced to [-pi, pi] with 2 pi as a double-double; the root is returned
 // on the input's branch.
 template <bool MIXED>
+__device__ __forceinline__ double kepler_one(double M, double e, int fixed, int max_iter)
+{
+    const bool ok = isfinite(M) && isfinite(e) && e >= 0.0 && e < 1.0;
+    if (!ok) { M = 0.0; e = 0.0; }
+    const double kq = rint(M * kInvTwoPi);
+    double Mr = fma(-kq, kTwoPiHi, M);
+    Mr = fma(-kq, kTwoPiLo, Mr);
+    double E;
+    if (MIXED) {
+        const Ecc32 k = make_ecc32(e);
+        const int niter = fixed > 0 ? fixed : sched32(k.e);
+        float sE, omcE;   // unused here: the standalone solve returns E only
+        E = (double)kepler32((float)Mr, k, niter, max_iter, fixed > 0, sE, omcE);
+    } else {
+        E = kepler64(Mr, e, Mr >= 0.0 ? 1.0 : -1.0, fixed, max_iter);
+    }
+    E = fma(kq, kTwoPiHi, E);
+    E = fma(kq, kTwoPiLo, E);
+    return ok ? E : __builtin_nan("");
+}
+
+// Each thread takes KU pairs per tile (KU x blockDim consecutive pairs per
+// block), issuing all of their loads before solving, so that more memory
+// requests are in flight than one pair per thread would allow.
+template <bool MIXED, int KU>
 __global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, const double *__restrict__ ev,
                                                double *__restrict__ Ev, int64_t n, int fixed, int max_iter)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double M = Mv[i], e = ev[i];
-        bool ok = isfinite(M) && isfinite(e) && e >= 0.0 && e < 1.0;
-        if (!ok) { M = 0.0; e = 0.0; }
-        double kq = rint(M * kInvTwoPi);
-        double Mr = fma(-kq, kTwoPiHi, M);
-        Mr = fma(-kq, kTwoPiLo, Mr);
-        double E;
-        if (MIXED) {
-            const Ecc32 k = make_ecc32(e);
-            const int niter = fixed > 0 ? fixed : sched32(k.e);
-            float sE, omcE;   // unused here: the standalone solve returns E only
-            E = (double)kepler32((float)Mr, k, niter, max_iter, fixed > 0, sE, omcE);
-        } else {
-            E = kepler64(Mr, e, Mr >= 0.0 ? 1.0 : -1.0, fixed, max_iter);
+    const int64_t tile = (int64_t)blockDim.x * KU;
+    const int64_t stride = (int64_t)gridDim.x * tile;
+    for (int64_t base = (int64_t)blockIdx.x * tile + threadIdx.x; base < n; base += stride) {
+        double M[KU], e[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            M[u] = i < n ? Mv[i] : 0.0;
+            e[u] = i < n ? ev[i] : 0.0;
         }
-        E = fma(kq, kTwoPiHi, E);
-        E = fma(kq, kTwoPiLo, E);
-        Ev[i] = ok ? E : __builtin_nan("");
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            const double E = kepler_one<MIXED>(M[u], e[u], fixed, max_iter);
+            if (i < n) Ev[i] = E;
+        }
     }
 }
 
@@ -796,15 +815,16 @@ hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int6
                                int max_iter, LaunchShape shape, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    int block = shape.block > 0 ? shape.block : 256;
-    int per_cu = shape.blocks_per_cu > 0 ? shape.blocks_per_cu : 8;
-    int64_t need = (n + block - 1) / block;
-    int64_t cap = (int64_t)device_cu_count() * per_cu * (256 / block > 0 ? 256 / block : 1) * 4;
-    int grid = (int)(need < cap ? need : cap);
+    const int block = shape.block > 0 ? shape.block : 256;
+    const int per_cu = shape.blocks_per_cu > 0 ? shape.blocks_per_cu : 8 * (256 / block);
+    constexpr int KU = 4;
+    const int64_t need = (n + (int64_t)block * KU - 1) / ((int64_t)block * KU);
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    const int grid = (int)(need < cap ? need : cap);
     if (prec == Prec::Mixed)
-        hipLaunchKernelGGL(k_kepler<true>, dim3(grid), dim3(block), 0, st, M, e, E, n, fixed_iter, max_iter);
+        hipLaunchKernelGGL((k_kepler<true, KU>), dim3(grid), dim3(block), 0, st, M, e, E, n, fixed_iter, max_iter);
     else
-        hipLaunchKernelGGL(k_kepler<false>, dim3(grid), dim3(block), 0, st, M, e, E, n,
+        hipLaunchKernelGGL((k_kepler<false, KU>), dim3(grid), dim3(block), 0, st, M, e, E, n,
                            fixed_iter == 0 ? 30 : (fixed_iter < 0 ? 0 : fixed_iter), max_iter);
     return hipGetLastError();
 }
