@@ -110,7 +110,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--rows", default="fp64,grad,ragged,kepler", help="extra paths to time (comma list or 'none')")
+    ap.add_argument("--rows", default="fp64,separate,grad,ragged,kepler",
+                    help="extra paths to time (comma list or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="systems in the CPU oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (to scale HBM byte counters)")
@@ -199,6 +200,23 @@ def main():
         result["speedup_vs_fp64_gpu"] = value / r64
         result["speedup_vs_fp64_gpu_same_workload"] = (w1.n_sys / (msm1 * 1e-3)) / r64
         del g1, o1
+
+    # ------------------------------------------------------------ separate-function form
+    if "separate" in rows:
+        log("separate-function form on c2 (per-planet velocities to HBM, then chi-square)")
+        g2 = dict(t=gpu(wl.t), v=gpu(wl.v), sigma=gpu(wl.sigma), P=gpu(wl.P), K=gpu(wl.K), e=gpu(wl.e),
+                  omega=gpu(wl.w), M0=gpu(wl.M0))
+        dv = torch.empty((wl.n_pl, wl.n_sys, wl.n_obs), dtype=torch.float32, device=dev)
+        o2 = torch.empty(wl.n_sys, dtype=torch.float64, device=dev)
+        msa, _ = timed(lambda: kp.rv_planet_velocities(g2["t"], g2["P"], g2["K"], g2["e"], g2["omega"], g2["M0"],
+                                                       out=dv), 5, 1, torch)
+        msb, _ = timed(lambda: kp.rv_chisq_from_velocities(g2["t"], g2["v"], g2["sigma"], dv, out=o2), 10, 2, torch)
+        dv_bytes = dv.numel() * 4
+        result["separate_c2"] = {"chi2_per_s": wl.n_sys / ((msa + msb) * 1e-3), "velocities_ms": msa,
+                                 "chisq_ms": msb, "intermediate_GB": dv_bytes / 1e9,
+                                 "chisq_hbm_GBps": (dv_bytes + wl.n_sys * 8) / (msb * 1e-3) / 1e9,
+                                 "time_vs_fused": (msa + msb) / ms}
+        del g2, dv, o2
 
     # ------------------------------------------------------------ gradient
     if "grad" in rows:

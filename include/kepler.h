@@ -136,6 +136,23 @@ kep_status rv_chisq(const kep_obs *obs, const kep_params *par, double *chi2,
 kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2, double *grad,
                          kep_prec prec, const kep_options *opts, void *stream);
 
+/* The paper's separate-function form (Sec. 4.4, first of its two
+   implementations; Sec. 5.3 measures it against the fused one): one call
+   writes the velocity of every planet at every observation, a second forms
+   the planet sums and the chi-square from them.  Binary32 velocities, mixed
+   precision arithmetic as KEP_MIXED.
+   rv_planet_velocities: dv[(j * n_sys + i) * n_obs + k] = v_ijk (Eq. 3), a
+   caller-owned device array of n_pl * n_sys * n_obs floats (observations
+   contiguous, so each (planet, system) row is written and read coalesced);
+   obs->v and obs->sigma are not read.  A system outside the domain gets NaN
+   velocities.
+   rv_chisq_from_velocities: chi2[i] (Eq. 5) from dv; par supplies n_sys, n_pl,
+   offset and jitter (the planes are not read and may be NULL).  n_obs <= 1024. */
+kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float *dv,
+                                const kep_options *opts, void *stream);
+kep_status rv_chisq_from_velocities(const kep_obs *obs, const kep_params *par, const float *dv, double *chi2,
+                                    const kep_options *opts, void *stream);
+
 /* ---- ragged batches (systems of uneven n_pl and n_obs, CSR-packed) ----
    System i owns observations obs_off[i] .. obs_off[i+1]-1 of t, v, sigma and
    planets pl_off[i] .. pl_off[i+1]-1 of P, K, e, omega, M0 (flat arrays of

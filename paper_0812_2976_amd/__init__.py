@@ -11,6 +11,7 @@ Functions keep the C names:
   rv_model(t, P, K, e, omega, M0, ...)     model velocities (Eq. 2, 3)
   rv_chisq(t, v, sigma, P, K, e, ...)      chi-square (Eq. 5)
   rv_chisq_grad(...)                       chi-square and its gradient
+  rv_planet_velocities / rv_chisq_from_velocities   the separate-function form
   RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
   RVChiSq.apply(...)                       torch.autograd.Function over rv_chisq_grad
 Parameter planes are float64 CUDA tensors shaped (n_pl, n_sys) (system index
@@ -71,8 +72,9 @@ class KeplerError(RuntimeError):
 
 _LIB = None
 
-EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "kep_plan_ragged", "rv_chisq_ragged",
-           "rv_chisq_ragged_direct", "kep_plan_get_info", "kep_plan_destroy", "kep_last_error", "kep_abi_version")
+EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_planet_velocities",
+           "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
+           "kep_plan_get_info", "kep_plan_destroy", "kep_last_error", "kep_abi_version")
 
 
 def load_library(path: str = LIB_PATH):
@@ -89,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     for name in ("rv_model", "rv_chisq"):
         getattr(L, name).argtypes = [P(KepObs), P(KepParams), _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_chisq_grad.argtypes = [P(KepObs), P(KepParams), _D, _D, ctypes.c_int, P(KepOptions), _D]
+    L.rv_planet_velocities.argtypes = [P(KepObs), P(KepParams), _D, P(KepOptions), _D]
+    L.rv_chisq_from_velocities.argtypes = [P(KepObs), P(KepParams), _D, _D, P(KepOptions), _D]
     L.kep_plan_ragged.argtypes = [P(KepObsCSR), P(KepParamsCSR), ctypes.c_int, P(KepOptions), _D, P(_D)]
     L.rv_chisq_ragged.argtypes = [_D, _D, _D]
     L.rv_chisq_ragged_direct.argtypes = [_D, _D, _D]
@@ -98,8 +102,9 @@ def load_library(path: str = LIB_PATH):
     L.kep_last_error.restype = ctypes.c_char_p
     L.kep_last_error.argtypes = []
     L.kep_abi_version.restype = ctypes.c_int
-    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "kep_plan_ragged", "rv_chisq_ragged",
-                 "rv_chisq_ragged_direct", "kep_plan_get_info"):
+    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_planet_velocities",
+                 "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
+                 "kep_plan_get_info"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -231,6 +236,37 @@ def rv_chisq_grad(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=
     _check(L.rv_chisq_grad(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), grad.data_ptr(), _prec(prec),
                            _opts(opts), _stream(dev)))
     return out, grad
+
+
+def rv_planet_velocities(t, P, K, e, omega, M0, t0=0.0, out=None, opts=None):
+    """Every planet's velocity (n_pl, n_sys, n_obs) in binary32, mixed precision
+    (first kernel of the paper's separate-function form)."""
+    obs, par, keep, dev = _obs_params(t, None, None, P, K, e, omega, M0, None, None, t0)
+    if out is None:
+        out = torch.empty((par.n_pl, par.n_sys, obs.n_obs), dtype=torch.float32, device=dev)
+    out = _dev(out, "out", 3, torch.float32)
+    _check(load_library().rv_planet_velocities(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _opts(opts),
+                                               _stream(dev)))
+    return out
+
+
+def rv_chisq_from_velocities(t, v, sigma, dv, offset=None, jitter=None, t0=0.0, out=None, opts=None):
+    """chi-square per system from per-planet velocities dv (n_pl, n_sys, n_obs) binary32
+    (second kernel of the separate-function form)."""
+    dv = _dev(dv, "dv", 3, torch.float32)
+    n_pl, n_sys, n_obs = dv.shape
+    t, v, sigma = (_dev(x, n, 1) for x, n in ((t, "t"), (v, "v"), (sigma, "sigma")))
+    if t.numel() != n_obs or v.numel() != n_obs or sigma.numel() != n_obs:
+        raise ValueError("t, v, sigma must have n_obs elements")
+    offset = _opt_dev(offset, "offset", n_sys)
+    jitter = _opt_dev(jitter, "jitter", n_sys)
+    obs = KepObs(t.data_ptr(), v.data_ptr(), sigma.data_ptr(), n_obs, float(t0))
+    par = KepParams(None, None, None, None, None, _ptr(offset), _ptr(jitter), n_sys, n_pl)
+    if out is None:
+        out = torch.empty(n_sys, dtype=torch.float64, device=dv.device)
+    _check(load_library().rv_chisq_from_velocities(ctypes.byref(obs), ctypes.byref(par), dv.data_ptr(),
+                                                   out.data_ptr(), _opts(opts), _stream(dv.device)))
+    return out
 
 
 class RaggedPlan:

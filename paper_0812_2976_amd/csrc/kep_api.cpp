@@ -116,6 +116,7 @@ kep::DenseArgs make_dense(const kep_obs *obs, const kep_params *par, const Opts 
     a.sb = 1;
     a.out = out;
     a.grad = grad;
+    a.dv = nullptr;
     a.fixed_iter = o.fixed_iter;
     a.max_iter = o.max_iter;
     return a;
@@ -191,6 +192,45 @@ kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2
     if (kep_status s = check_device(fn)) return s;
     kep::DenseArgs a = make_dense(obs, par, o, chi2, grad);
     return launch_status(kep::launch_dense_grad(a, to_prec(prec), o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float *dv, const kep_options *opts,
+                                void *stream)
+{
+    static const char *fn = "rv_planet_velocities";
+    if (kep_status s = check_dense(obs, par, false, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0 || obs->n_obs == 0) return KEP_OK;
+    if (!dv) return fail(KEP_ERR_ARG, "%s: dv is NULL", fn);
+    if (mul_overflows(par->n_sys * par->n_pl, obs->n_obs)) return fail(KEP_ERR_SHAPE, "%s: n_pl x n_sys x n_obs overflows", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, nullptr, nullptr);
+    a.dv = dv;
+    return launch_status(kep::launch_planet_velocities(a, o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status rv_chisq_from_velocities(const kep_obs *obs, const kep_params *par, const float *dv, double *chi2,
+                                    const kep_options *opts, void *stream)
+{
+    static const char *fn = "rv_chisq_from_velocities";
+    if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
+    if (obs->n_obs < 0 || par->n_sys < 0) return fail(KEP_ERR_ARG, "%s: negative size", fn);
+    if (par->n_pl < 1 || par->n_pl > KEP_MAX_PL)
+        return fail(KEP_ERR_SHAPE, "%s: n_pl = %lld outside [1, %d]", fn, (long long)par->n_pl, KEP_MAX_PL);
+    if (obs->n_obs > 1024)
+        return fail(KEP_ERR_UNSUPPORTED, "%s: n_obs = %lld above 1024", fn, (long long)obs->n_obs);
+    if (mul_overflows(par->n_sys * par->n_pl, obs->n_obs)) return fail(KEP_ERR_SHAPE, "%s: sizes overflow", fn);
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0) return KEP_OK;
+    if (obs->n_obs > 0 && (!obs->t || !obs->v || !obs->sigma || !dv))
+        return fail(KEP_ERR_ARG, "%s: t, v, sigma and dv must not be NULL", fn);
+    if (!chi2) return fail(KEP_ERR_ARG, "%s: chi2 is NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, chi2, nullptr);
+    a.dv = const_cast<float *>(dv);
+    return launch_status(kep::launch_chisq_from_velocities(a, o.shape, (hipStream_t)stream), fn);
 }
 
 }  // extern "C"

@@ -287,8 +287,13 @@ __device__ __forceinline__ void pol_add_planet(const typename Pol::Rec &r, const
     Pol::template add_planet<NCH>(r, o, m, a.max_iter, fixed64(a.fixed_iter));
 }
 
-// Dense kernel: chi-square (MODEL = false) or model velocities (MODEL = true).
-template <class Pol, int NCH, bool MODEL>
+// Dense kernel.  MODE kChi2: chi-square per system; kModel: model velocities
+// [n_sys][n_obs]; kPlanets: every planet's velocity [n_pl][n_sys][n_obs] in
+// binary32 (the paper's separate-function form, Sec. 4.4, first implementation).
+enum { kChi2 = 0, kModel = 1, kPlanets = 2 };
+
+template <class Pol, int NCH, int MODE>
+
 __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
 {
     using Rec = typename Pol::Rec;
@@ -313,15 +318,16 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
-            if (MODEL) Pol::load_obs_model(a, k, o[c]);
+            if (MODE != kChi2) Pol::load_obs_model(a, k, o[c]);
             else Pol::load_obs(a, k, o[c]);
         }
     };
     if (n_groups <= 1) load_group(0);
 
-    // Model velocities need no reduction over observations, so their work items
-    // are (batch, observation group) pairs: a few systems with very many
+    // Velocities need no reduction over observations, so their work items are
+    // (batch, observation group) pairs: a few systems with very many
     // observations still spread over the whole chip.
+    constexpr bool MODEL = MODE != kChi2;
     const int64_t n_items = MODEL ? n_batches * n_groups : n_batches;
     int64_t prev_bt = -1;
     for (int64_t item = gw; item < n_items; item += n_waves) {
@@ -360,6 +366,22 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
             for (int g = g_first; g < g_end; ++g) {
                 if (n_groups > 1) load_group(g);
                 ModelAcc m[NCH];
+                if (MODE == kPlanets) {
+                    for (int j = 0; j < a.n_pl; ++j) {
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) Pol::model_init(m[c]);
+                        pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a);
+                        float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            if (o[c].in) {
+                                const int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
+                                row[k] = (sbad || !o[c].ok) ? __builtin_nanf("") : (float)Pol::model_value(m[c]);
+                            }
+                        }
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) Pol::model_init(m[c]);
                 for (int j = 0; j < a.n_pl; ++j) pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a);
@@ -388,6 +410,47 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
                 if (lane == 0) a.out[sys] = bad ? __builtin_nan("") : tot;
             }
         }
+    }
+}
+
+// Second kernel of the separate-function form: planet sums (Kahan), residuals
+// and the compensated chi-square from the velocities written by kPlanets.
+template <int NCH>
+__global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
+{
+    const int lane = __lane_id();
+    const int wpb = blockDim.x >> 6;
+    const int64_t gw = (int64_t)blockIdx.x * wpb + uniform_int(threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    const bool has_jit = a.jitter != nullptr;
+    ObsMixed o[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) PolMixed::load_obs(a, c * 64 + lane, o[c]);
+    for (int64_t sys = gw; sys < a.n_sys; sys += n_waves) {
+        const double gam = a.offset ? a.offset[sys] : 0.0;
+        const double jit = a.jitter ? a.jitter[sys] : 0.0;
+        bool bad = !isfinite(a.t0) || (a.offset && !isfinite(gam)) || (has_jit && !(isfinite(jit) && jit >= 0.0));
+        PolMixed::ModelAcc m[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) PolMixed::model_init(m[c]);
+        for (int j = 0; j < a.n_pl; ++j) {
+            const float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) m[c].k.add(o[c].in ? row[c * 64 + lane] : 0.0f);
+        }
+        Kahan32 chi;
+        chi.init();
+        bool bad_obs = false;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (o[c].in) {
+                bool okw = PolMixed::chi_add(chi, m[c], o[c], gam, jit, has_jit);
+                bad_obs = bad_obs || !okw || !o[c].ok;
+            }
+        }
+        const double tot = wave_sum(chi.value());
+        bad = bad || __any(bad_obs);
+        if (lane == 0) a.out[sys] = bad ? __builtin_nan("") : tot;
     }
 }
 
@@ -829,7 +892,7 @@ hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int6
     return hipGetLastError();
 }
 
-template <class Pol, bool MODEL>
+template <class Pol, int MODE>
 static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
 {
     const int block = shape.block > 0 ? shape.block : 256;
@@ -842,10 +905,10 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     const int nch_needed = (int)((a.n_obs + 63) / 64);
     void (*kern)(DenseArgs);
     int nch;
-    if (nch_needed <= 1) { kern = k_dense<Pol, 1, MODEL>; nch = 1; }
-    else if (nch_needed <= 2) { kern = k_dense<Pol, 2, MODEL>; nch = 2; }
-    else if (nch_needed <= 4) { kern = k_dense<Pol, 4, MODEL>; nch = 4; }
-    else { kern = k_dense<Pol, 8, MODEL>; nch = 8; }
+    if (nch_needed <= 1) { kern = k_dense<Pol, 1, MODE>; nch = 1; }
+    else if (nch_needed <= 2) { kern = k_dense<Pol, 2, MODE>; nch = 2; }
+    else if (nch_needed <= 4) { kern = k_dense<Pol, 4, MODE>; nch = 4; }
+    else { kern = k_dense<Pol, 8, MODE>; nch = 8; }
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
         int occ = 0;
@@ -859,7 +922,7 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     lds = rec_bytes * (size_t)sb;
     const int64_t n_batches = (a.n_sys + sb - 1) / sb;
     const int64_t n_groups = (a.n_obs + 64 * nch - 1) / (64 * nch);
-    const int64_t n_items = MODEL ? n_batches * (n_groups > 0 ? n_groups : 1) : n_batches;
+    const int64_t n_items = MODE != kChi2 ? n_batches * (n_groups > 0 ? n_groups : 1) : n_batches;
     int64_t grid = (n_items + wpb - 1) / wpb;
     const int64_t cap = (int64_t)device_cu_count() * per_cu;
     if (grid > cap) grid = cap;
@@ -873,8 +936,35 @@ hipError_t launch_dense(DenseArgs a, Prec prec, bool model, LaunchShape shape, h
     if (a.n_sys <= 0) return hipSuccess;
     if (model && a.n_obs <= 0) return hipSuccess;
     if (prec == Prec::Mixed)
-        return model ? launch_dense_t<PolMixed, true>(a, shape, st) : launch_dense_t<PolMixed, false>(a, shape, st);
-    return model ? launch_dense_t<Pol64, true>(a, shape, st) : launch_dense_t<Pol64, false>(a, shape, st);
+        return model ? launch_dense_t<PolMixed, kModel>(a, shape, st) : launch_dense_t<PolMixed, kChi2>(a, shape, st);
+    return model ? launch_dense_t<Pol64, kModel>(a, shape, st) : launch_dense_t<Pol64, kChi2>(a, shape, st);
+}
+
+hipError_t launch_planet_velocities(DenseArgs a, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0 || a.n_obs <= 0) return hipSuccess;
+    return launch_dense_t<PolMixed, kPlanets>(a, shape, st);
+}
+
+hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0) return hipSuccess;
+    const int block = shape.block > 0 ? shape.block : 256;
+    const int wpb = block / 64;
+    const int nch_needed = (int)((a.n_obs + 63) / 64);
+    void (*kern)(DenseArgs);
+    if (nch_needed <= 1) kern = k_chisq_from_dv<1>;
+    else if (nch_needed <= 2) kern = k_chisq_from_dv<2>;
+    else if (nch_needed <= 4) kern = k_chisq_from_dv<4>;
+    else if (nch_needed <= 8) kern = k_chisq_from_dv<8>;
+    else if (nch_needed <= 16) kern = k_chisq_from_dv<16>;
+    else return hipErrorInvalidValue;
+    const int per_cu = shape.blocks_per_cu > 0 ? shape.blocks_per_cu : 8;
+    int64_t grid = (a.n_sys + wpb - 1) / wpb;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace kep
