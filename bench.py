@@ -242,7 +242,7 @@ def main():
         info = plan.info()
         result["ragged_c3"] = {"chi2_per_s": rw.n_sys / (msr * 1e-3), "launch_ms": msr,
                                "kepler_solves_per_s": info["triples"] / (msr * 1e-3), "triples": info["triples"],
-                               "plan": {k: info[k] for k in ("block_threads", "blocks", "sys_per_batch", "tuned")}}
+                               "plan": {k: info[k] for k in ("block_threads", "blocks", "sys_per_batch", "group_chunks", "tuned")}}
         plan.close()
         del o3
 

@@ -177,9 +177,11 @@ typedef struct kep_plan kep_plan;   /* opaque; owned by the library */
 
 /* Build a plan for one ragged batch: copies the CSR offsets to the host,
    checks them, orders the systems by work (n_pl * n_obs, largest first),
-   picks the launch shape (the autotuner times candidates on this batch unless
-   opts fixes block_threads), and records {queue reset, persistent kernel} as a
-   HIP graph.  May allocate and synchronises `stream`.  The plan keeps the
+   picks the launch shape (the autotuner times block size x systems per work
+   item x observation group size on this batch unless opts fixes
+   block_threads; results are cached per device and shape class, and kept in
+   the text file named by the environment variable KEP_TUNE_CACHE if set), and
+   records {queue reset, persistent kernel} as a HIP graph.  May allocate and synchronises `stream`.  The plan keeps the
    input pointers: their contents may change between calls, their addresses
    and sizes may not.  Only KEP_MIXED is implemented for ragged batches
    (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */
@@ -198,6 +200,8 @@ typedef struct kep_plan_info {
     int64_t n_sys, n_obs_total, n_pl_total, triples;
     int32_t block_threads, blocks, sys_per_batch, tuned;
     double tuned_ms;          /* best candidate's time during tuning, 0 if not tuned */
+    int32_t group_chunks;     /* largest observation group, in 64-lane chunks */
+    int32_t reserved;
 } kep_plan_info;
 
 kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info);

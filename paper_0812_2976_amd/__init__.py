@@ -61,7 +61,8 @@ class KepParamsCSR(ctypes.Structure):
 class KepPlanInfo(ctypes.Structure):
     _fields_ = [("n_sys", ctypes.c_int64), ("n_obs_total", ctypes.c_int64), ("n_pl_total", ctypes.c_int64),
                 ("triples", ctypes.c_int64), ("block_threads", ctypes.c_int32), ("blocks", ctypes.c_int32),
-                ("sys_per_batch", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tuned_ms", ctypes.c_double)]
+                ("sys_per_batch", ctypes.c_int32), ("tuned", ctypes.c_int32), ("tuned_ms", ctypes.c_double),
+                ("group_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KeplerError(RuntimeError):

@@ -255,7 +255,7 @@ namespace {
 
 struct TuneEntry {
     std::string key;
-    int block, sb;
+    int block, sb, gmax;
     double ms;
 };
 std::mutex g_tune_mu;
@@ -282,7 +282,7 @@ std::string tune_key(int64_t n_sys, double mean_work)
     return buf;
 }
 
-// Optional persistence: KEP_TUNE_CACHE names a text file of "key block sb ms" lines.
+// Optional persistence: KEP_TUNE_CACHE names a text file of "key block sb gmax ms" lines.
 void tune_load_locked()
 {
     if (g_tune_loaded) return;
@@ -292,9 +292,13 @@ void tune_load_locked()
     FILE *f = fopen(path, "r");
     if (!f) return;
     char key[200];
-    int block, sb;
+    int block, sb, gmax;
     double ms;
-    while (fscanf(f, "%199s %d %d %lf", key, &block, &sb, &ms) == 4) g_tune.push_back({key, block, sb, ms});
+    while (fscanf(f, "%199s %d %d %d %lf", key, &block, &sb, &gmax, &ms) == 5) {
+        const bool valid = (block == 64 || block == 128 || block == 192 || block == 256) && sb >= 1 &&
+                           sb <= kep::kMaxSB && (gmax == 2 || gmax == 4);
+        if (valid) g_tune.push_back({key, block, sb, gmax, ms});
+    }
     fclose(f);
 }
 
@@ -308,7 +312,7 @@ save:
     if (!path) return;
     FILE *f = fopen(path, "w");
     if (!f) return;
-    for (auto &x : g_tune) fprintf(f, "%s %d %d %.6f\n", x.key.c_str(), x.block, x.sb, x.ms);
+    for (auto &x : g_tune) fprintf(f, "%s %d %d %d %.6f\n", x.key.c_str(), x.block, x.sb, x.gmax, x.ms);
     fclose(f);
 }
 
@@ -472,27 +476,34 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     a.fixed_iter = o.fixed_iter;
     a.max_iter = o.max_iter;
 
-    auto configure = [&](int block, int sb) {
+    auto configure = [&](int block, int sb, int gmax) {
         p->shape.block = block;
         p->shape.blocks_per_cu = o.shape.blocks_per_cu;
         a.sb = sb;
+        a.gmax = gmax;
         a.n_items = (n_sys + sb - 1) / sb;
         const int wpb = block / 64;
         int64_t g = (a.n_items + wpb - 1) / wpb;
-        const int cap = kep::ragged_max_grid(p->shape, sb);
+        const int cap = kep::ragged_max_grid(p->shape, sb, gmax);
         p->grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
     };
 
     const double mean_work = n_sys > 0 ? (double)triples / (double)n_sys : 0.0;
     int best_block = o.shape.block > 0 ? o.shape.block : 256;
-    int best_sb = 4;
+    int best_sb = 4, best_gmax = 4;
     if (o.shape.block == 0 && n_sys > 0) {
         const std::string key = tune_key(n_sys, mean_work);
         std::lock_guard<std::mutex> lock(g_tune_mu);
         tune_load_locked();
         bool found = false;
         for (auto &x : g_tune)
-            if (x.key == key) { best_block = x.block; best_sb = x.sb; p->tuned_ms = x.ms; found = true; }
+            if (x.key == key) {
+                best_block = x.block;
+                best_sb = x.sb;
+                best_gmax = x.gmax;
+                p->tuned_ms = x.ms;
+                found = true;
+            }
         if (!found && triples > 0) {
             // autotune: time every (block, systems per item) candidate on this batch
             double *scratch = nullptr;
@@ -504,20 +515,22 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
             double best = 1e30;
             const int blocks[] = {64, 128, 256};
             const int sbs[] = {1, 2, 4, 8, 16, 32};
-            for (int b : blocks)
-                for (int sb : sbs) {
-                    configure(b, sb);
-                    const double ms = time_candidate(p, st, 2);
-                    if (ms < best) { best = ms; best_block = b; best_sb = sb; }
-                }
+            const int gmaxs[] = {2, 4};
+            for (int gm : gmaxs)
+                for (int b : blocks)
+                    for (int sb : sbs) {
+                        configure(b, sb, gm);
+                        const double ms = time_candidate(p, st, 2);
+                        if (ms < best) { best = ms; best_block = b; best_sb = sb; best_gmax = gm; }
+                    }
             (void)hipFree(scratch);
             a.out = nullptr;
             p->tuned_ms = best;
-            tune_store_locked({key, best_block, best_sb, best});
+            tune_store_locked({key, best_block, best_sb, best_gmax, best});
         }
         p->tuned = 1;
     }
-    configure(best_block, best_sb);
+    configure(best_block, best_sb, best_gmax);
     *out = p;
     return KEP_OK;
 }
@@ -584,6 +597,8 @@ kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info)
     info->sys_per_batch = plan->args.sb;
     info->tuned = plan->tuned;
     info->tuned_ms = plan->tuned_ms;
+    info->group_chunks = plan->args.gmax;
+    info->reserved = 0;
     return KEP_OK;
 }
 

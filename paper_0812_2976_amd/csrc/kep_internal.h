@@ -36,6 +36,7 @@ struct RaggedArgs {
     int64_t n_sys;
     int64_t n_items;          // number of work items = ceil(n_sys / sb)
     int sb;                   // systems per work item
+    int gmax;                 // largest observation group, in 64-lane chunks (2 or 4)
     unsigned int *queue;      // work-queue counter (reset before every launch)
     double *out;
     int fixed_iter, max_iter;
@@ -60,7 +61,7 @@ hipError_t launch_planet_velocities(DenseArgs a, LaunchShape shape, hipStream_t 
 hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
-int ragged_max_grid(LaunchShape shape, int sb);
+int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 int device_cu_count();
 
 }  // namespace kep

@@ -788,6 +788,10 @@ __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed
     }
 }
 
+// GMAX: largest observation group in 64-lane chunks (2 or 4): fewer chunks in
+// flight need fewer registers and allow more resident waves; the plan's
+// autotuner picks it.
+template <int GMAX>
 __global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -835,13 +839,13 @@ __global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
             Kahan32 chi;
             chi.init();
             bool bad_obs = false;
-            for (int64_t g = 0; g < n; g += 256) {
+            for (int64_t g = 0; g < n; g += 64 * GMAX) {
                 const int64_t rem = n - g;
                 const RecMixed *rs = recs + s * kMaxPl;
                 if (rem <= 64) ragged_group<1>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
-                else if (rem <= 128) ragged_group<2>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+                else if (GMAX == 2 || rem <= 128) ragged_group<2>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
                 else if (rem <= 192) ragged_group<3>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
-                else ragged_group<4>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+                else ragged_group<GMAX>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
             }
             const double tot = wave_sum(chi.value());
             const bool bad = code <= 0 || __any(bad_obs);
@@ -1009,13 +1013,14 @@ static size_t ragged_lds(int block, int sb)
     return (size_t)wpb * sb * kMaxPl * sizeof(RecMixed) + (size_t)wpb * sb * 2 * sizeof(int);
 }
 
-int ragged_max_grid(LaunchShape shape, int sb)
+int ragged_max_grid(LaunchShape shape, int sb, int gmax)
 {
     const int block = shape.block > 0 ? shape.block : 256;
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_ragged_mixed, block, ragged_lds(block, sb)) != hipSuccess ||
+        void (*kern)(RaggedArgs) = gmax == 2 ? k_ragged_mixed<2> : k_ragged_mixed<4>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, ragged_lds(block, sb)) != hipSuccess ||
             occ <= 0)
             occ = 1;
         per_cu = occ;
@@ -1026,7 +1031,10 @@ int ragged_max_grid(LaunchShape shape, int sb)
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st)
 {
     const int block = shape.block > 0 ? shape.block : 256;
-    hipLaunchKernelGGL(k_ragged_mixed, dim3(grid > 0 ? grid : 1), dim3(block), ragged_lds(block, a.sb), st, a);
+    if (a.gmax == 2)
+        hipLaunchKernelGGL(k_ragged_mixed<2>, dim3(grid > 0 ? grid : 1), dim3(block), ragged_lds(block, a.sb), st, a);
+    else
+        hipLaunchKernelGGL(k_ragged_mixed<4>, dim3(grid > 0 ? grid : 1), dim3(block), ragged_lds(block, a.sb), st, a);
     return hipGetLastError();
 }
 

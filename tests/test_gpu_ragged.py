@@ -142,3 +142,42 @@ def test_ragged_c3_full_size_sampled(dev):
     err = W.rel_err_chi2(chi2[idx], ref)
     print(f"[ragged c3 full] max rel {err.max():.3e} info {plan.info()}", flush=True)
     assert err.max() <= 1e-5
+
+
+_TUNE_SCRIPT = r"""
+import json, sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import paper_0812_2976_amd as kp, synth
+rw = synth.ragged(n_sys=4000, seed=21)
+rw.v = rw.noise
+g = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+plan = kp.RaggedPlan(g(rw.t), g(rw.v), g(rw.sigma), g(rw.obs_off), g(rw.P), g(rw.K), g(rw.e), g(rw.w), g(rw.M0),
+                     g(rw.pl_off))
+print(json.dumps(plan.info()))
+"""
+
+
+def test_autotune_table_persists(dev, tmp_path):
+    """The tuned launch shape is written to KEP_TUNE_CACHE and read back by a
+    second process, which then skips tuning and reuses it."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, KEP_TUNE_CACHE=str(cache))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    infos = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", _TUNE_SCRIPT, root], env=env, capture_output=True, text=True,
+                           timeout=180)
+        assert r.returncode == 0, r.stderr[-2000:]
+        infos.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    lines = cache.read_text().split()
+    assert len(lines) == 5 and "/ragged_mixed/" in lines[0]
+    a, b = infos
+    for k in ("block_threads", "sys_per_batch", "group_chunks"):
+        assert a[k] == b[k]
+    assert b["tuned_ms"] == pytest.approx(float(lines[4]), rel=1e-6)
+    assert int(lines[1]) == a["block_threads"] and int(lines[2]) == a["sys_per_batch"] and int(lines[3]) == a["group_chunks"]
