@@ -221,15 +221,19 @@ def main():
     # ------------------------------------------------------------ gradient
     if "grad" in rows:
         log("gradient on c4 (262,144 x 4 x 256)")
-        w4 = synth.with_observations(synth.dense("c4"), gpu_truth_model)
+        w4 = synth.with_observations(synth.dense("c4", jitter=True), gpu_truth_model)
         g4 = dict(t=gpu(w4.t), v=gpu(w4.v), sigma=gpu(w4.sigma), P=gpu(w4.P), K=gpu(w4.K), e=gpu(w4.e),
                   omega=gpu(w4.w), M0=gpu(w4.M0), offset=gpu(w4.offset), t0=w4.t0)
         o4 = torch.empty(w4.n_sys, dtype=torch.float64, device=dev)
         gr = torch.empty((5 * w4.n_pl + 1, w4.n_sys), dtype=torch.float64, device=dev)
         msg, _ = timed(lambda: kp.rv_chisq_grad(**g4, prec="mixed", out=o4, grad=gr), 10, 2, torch)
+        gn = torch.empty((5 * w4.n_pl + 2, w4.n_sys), dtype=torch.float64, device=dev)
+        jit = gpu(w4.jitter)
+        msn, _ = timed(lambda: kp.rv_nll_grad(**g4, jitter=jit, prec="mixed", out=o4, grad=gn), 10, 2, torch)
         result["gradient_c4"] = {"chi2_grad_per_s": w4.n_sys / (msg * 1e-3), "launch_ms": msg,
-                                 "triples_per_s": w4.n_sys * 1024 / (msg * 1e-3)}
-        del g4, o4, gr
+                                 "triples_per_s": w4.n_sys * 1024 / (msg * 1e-3),
+                                 "nll_grad_launch_ms": msn}
+        del g4, o4, gr, gn, jit
 
     # ------------------------------------------------------------ ragged
     if "ragged" in rows:

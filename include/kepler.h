@@ -136,6 +136,17 @@ kep_status rv_chisq(const kep_obs *obs, const kep_params *par, double *chi2,
 kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2, double *grad,
                          kep_prec prec, const kep_options *opts, void *stream);
 
+/* Gaussian likelihood with jitter and its gradient.  Eq. 5 weights each
+   residual by 1/(sigma_k^2 + s_i^2); with s_i free, the chi-square alone is
+   not the quantity to maximise, and the normalisation of the Gaussian enters:
+   nll[i] = -2 ln L_i - n_obs ln(2 pi) = chi2_i + sum_k ln(sigma_k^2 + s_i^2).
+   grad is [(5 * n_pl + 2)][n_sys]: the rows of rv_chisq_grad (the normalisation
+   does not depend on them), then d nll / d s_i = 2 s_i sum_k (w_k - w_k^2 r_k^2)
+   with w_k = 1/(sigma_k^2 + s_i^2) and r_k the residual.  A NULL jitter means
+   s_i = 0 (the last row is then 0).  Domain and errors as rv_chisq_grad. */
+kep_status rv_nll_grad(const kep_obs *obs, const kep_params *par, double *nll, double *grad,
+                       kep_prec prec, const kep_options *opts, void *stream);
+
 /* The paper's separate-function form (Sec. 4.4, first of its two
    implementations; Sec. 5.3 measures it against the fused one): one call
    writes the velocity of every planet at every observation, a second forms

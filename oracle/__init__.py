@@ -14,6 +14,7 @@ follow the paper (Ford 2008) section by section:
 * ``rv_model``      — planet sum plus offset (Eq. 2)
 * ``chisq``         — Eq. 5 with per-system jitter
 * ``chisq_grad``    — analytic gradient of Eq. 5 (partial derivatives, Sec. 6)
+* ``nll_grad``      — likelihood with jitter (Eq. 5's weights) and its gradient
 * ``chisq_ragged``  — Eq. 5 over CSR-packed systems of uneven size
 """
 import ctypes
@@ -68,6 +69,8 @@ def lib():
             f.argtypes = [ctypes.POINTER(_Dense), _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_grad.restype = None
         L.oracle_chisq_grad.argtypes = [ctypes.POINTER(_Dense), _D, _D, ctypes.c_int64, ctypes.c_int64]
+        L.oracle_nll_grad.restype = None
+        L.oracle_nll_grad.argtypes = [ctypes.POINTER(_Dense), _D, _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_grad_scales.restype = None
         L.oracle_chisq_grad_scales.argtypes = [ctypes.POINTER(_Dense), _D, _D, _D, _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_ragged.restype = None
@@ -150,6 +153,17 @@ def chisq_grad(d: Dense, i0=0, i1=None):
     grad = np.full((5 * d.n_pl + 1, d.n_sys), np.nan)
     lib().oracle_chisq_grad(ctypes.byref(d._s), _ptr(chi2), _ptr(grad), i0, i1)
     return chi2, grad
+
+
+def nll_grad(d: Dense, i0=0, i1=None):
+    """(-2 ln L [n_sys], grad [5*n_pl+2, n_sys]): Gaussian likelihood with jitter,
+    -2 ln L = chi2 + sum_k ln(sigma_k^2 + s^2) (constant omitted); gradient rows
+    as chisq_grad, then d/ds."""
+    i0, i1 = d._range(i0, i1)
+    nll = np.full(d.n_sys, np.nan)
+    grad = np.full((5 * d.n_pl + 2, d.n_sys), np.nan)
+    lib().oracle_nll_grad(ctypes.byref(d._s), _ptr(nll), _ptr(grad), i0, i1)
+    return nll, grad
 
 
 def chisq_grad_scales(d: Dense, i0=0, i1=None):

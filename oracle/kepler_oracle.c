@@ -234,20 +234,24 @@ void oracle_chisq(const oracle_dense *d, double *chi2, int64_t i0, int64_t i1)
 /* the order P, K, e, omega, M0; the last row is the offset.           */
 /* ------------------------------------------------------------------ */
 static void chisq_grad_impl(const oracle_dense *d, double *chi2, double *grad, double *scale_r,
-                            double *scale_1, int64_t i0, int64_t i1)
+                            double *scale_1, int nll, int64_t i0, int64_t i1)
 {
     const int64_t npar = 5 * d->n_pl + 1;
+    const int64_t nrow = npar + (nll ? 1 : 0);
     ld g[5 * 64 + 1], sr[5 * 64 + 1], s1[5 * 64 + 1];
     for (int64_t i = i0; i < i1; ++i) {
         int ok = system_ok(d, i) && d->n_pl <= 64;
         double s = d->jitter ? d->jitter[i] : 0.0;
         for (int64_t a = 0; a < npar; ++a) g[a] = sr[a] = s1[a] = 0.0L;
-        ld acc = 0.0L;
+        ld acc = 0.0L, sum_logvar = 0.0L, sum_w = 0.0L, sum_w2r2 = 0.0L;
         for (int64_t k = 0; ok && k < d->n_obs; ++k) {
             ld wk = weight_l(d->sigma[k], d->v[k], d->t[k], s);
             if (wk == 0.0L) { ok = 0; break; }
             ld r = model_l(d, i, d->t[k]) - (ld)d->v[k];
             acc += wk * r * r;
+            sum_logvar -= logl(wk);
+            sum_w += wk;
+            sum_w2r2 += wk * wk * r * r;
             ld c = 2.0L * wk * r;
             for (int64_t j = 0; j < d->n_pl; ++j) {
                 int64_t p = j * d->n_sys + i;
@@ -278,18 +282,31 @@ static void chisq_grad_impl(const oracle_dense *d, double *chi2, double *grad, d
             sr[npar - 1] += fabsl(c);
             s1[npar - 1] += 2.0L * wk;
         }
-        chi2[i] = ok ? (double)acc : NAN;
+        chi2[i] = ok ? (double)(nll ? acc + sum_logvar : acc) : NAN;
         for (int64_t a = 0; a < npar; ++a) {
             grad[a * d->n_sys + i] = ok ? (double)g[a] : NAN;
             if (scale_r) scale_r[a * d->n_sys + i] = ok ? (double)sr[a] : NAN;
             if (scale_1) scale_1[a * d->n_sys + i] = ok ? (double)s1[a] : NAN;
+        }
+        if (nll) {
+            ld s = d->jitter ? (ld)d->jitter[i] : 0.0L;
+            grad[(nrow - 1) * d->n_sys + i] = ok ? (double)(2.0L * s * (sum_w - sum_w2r2)) : NAN;
         }
     }
 }
 
 void oracle_chisq_grad(const oracle_dense *d, double *chi2, double *grad, int64_t i0, int64_t i1)
 {
-    chisq_grad_impl(d, chi2, grad, NULL, NULL, i0, i1);
+    chisq_grad_impl(d, chi2, grad, NULL, NULL, 0, i0, i1);
+}
+
+/* Gaussian likelihood with jitter (Eq. 5's weights w = 1/(sigma^2 + s^2)):
+   -2 ln L = chi2 + sum_k ln(sigma_k^2 + s^2), the constant n_obs ln(2 pi)
+   omitted, and its gradient: rows as oracle_chisq_grad, then d/ds =
+   2 s (sum_k w_k - sum_k w_k^2 r_k^2).  grad is [(5 n_pl + 2)][n_sys]. */
+void oracle_nll_grad(const oracle_dense *d, double *nll, double *grad, int64_t i0, int64_t i1)
+{
+    chisq_grad_impl(d, nll, grad, NULL, NULL, 1, i0, i1);
 }
 
 /* Error scales of the gradient (for stating tolerances): per component,
@@ -299,7 +316,7 @@ void oracle_chisq_grad(const oracle_dense *d, double *chi2, double *grad, int64_
 void oracle_chisq_grad_scales(const oracle_dense *d, double *chi2, double *grad, double *scale_r,
                               double *scale_1, int64_t i0, int64_t i1)
 {
-    chisq_grad_impl(d, chi2, grad, scale_r, scale_1, i0, i1);
+    chisq_grad_impl(d, chi2, grad, scale_r, scale_1, 0, i0, i1);
 }
 
 /* ------------------------------------------------------------------ */

@@ -11,6 +11,7 @@ Functions keep the C names:
   rv_model(t, P, K, e, omega, M0, ...)     model velocities (Eq. 2, 3)
   rv_chisq(t, v, sigma, P, K, e, ...)      chi-square (Eq. 5)
   rv_chisq_grad(...)                       chi-square and its gradient
+  rv_nll_grad(...)                         likelihood with jitter and its gradient
   rv_planet_velocities / rv_chisq_from_velocities   the separate-function form
   RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
   RVChiSq.apply(...)                       torch.autograd.Function over rv_chisq_grad
@@ -73,7 +74,7 @@ class KeplerError(RuntimeError):
 
 _LIB = None
 
-EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_planet_velocities",
+EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
            "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
            "kep_plan_get_info", "kep_plan_destroy", "kep_last_error", "kep_abi_version")
 
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     for name in ("rv_model", "rv_chisq"):
         getattr(L, name).argtypes = [P(KepObs), P(KepParams), _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_chisq_grad.argtypes = [P(KepObs), P(KepParams), _D, _D, ctypes.c_int, P(KepOptions), _D]
+    L.rv_nll_grad.argtypes = [P(KepObs), P(KepParams), _D, _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_planet_velocities.argtypes = [P(KepObs), P(KepParams), _D, P(KepOptions), _D]
     L.rv_chisq_from_velocities.argtypes = [P(KepObs), P(KepParams), _D, _D, P(KepOptions), _D]
     L.kep_plan_ragged.argtypes = [P(KepObsCSR), P(KepParamsCSR), ctypes.c_int, P(KepOptions), _D, P(_D)]
@@ -103,7 +105,7 @@ def load_library(path: str = LIB_PATH):
     L.kep_last_error.restype = ctypes.c_char_p
     L.kep_last_error.argtypes = []
     L.kep_abi_version.restype = ctypes.c_int
-    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_planet_velocities",
+    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
                  "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
                  "kep_plan_get_info"):
         getattr(L, name).restype = ctypes.c_int
@@ -156,6 +158,22 @@ def _opt_dev(x, name, n):
     return x
 
 
+def _out(x, name, shape, device, dtype=torch.float64):
+    """A result tensor: allocated when None, else checked to be a contiguous GPU
+    tensor of exactly `shape` (the kernels write through its pointer)."""
+    shape = tuple(int(n) for n in shape)
+    if x is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if x.dtype != dtype or tuple(x.shape) != shape or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {shape} "
+                         f"(got {x.dtype} {tuple(x.shape)})")
+    if x.device != torch.device(device):
+        raise ValueError(f"{name} must be on {device} (got {x.device})")
+    return x
+
+
 def _ptr(x):
     return None if x is None else x.data_ptr()
 
@@ -179,8 +197,7 @@ def kepler_solve(M, e, prec="mixed", out=None, opts=None):
     e = _dev(e, "e")
     if M.shape != e.shape:
         raise ValueError("M and e must have the same shape")
-    if out is None:
-        out = torch.empty_like(M)
+    out = _out(out, "out", M.shape, M.device)
     L = load_library()
     _check(L.kepler_solve(M.data_ptr(), e.data_ptr(), out.data_ptr(), M.numel(), _prec(prec), _opts(opts),
                           _stream(M.device)))
@@ -208,8 +225,7 @@ def _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0):
 def rv_model(t, P, K, e, omega, M0, offset=None, t0=0.0, prec="mixed", out=None, opts=None):
     """Model velocities (n_sys, n_obs): sum over planets of the Keplerian velocity plus offset."""
     obs, par, keep, dev = _obs_params(t, None, None, P, K, e, omega, M0, offset, None, t0)
-    if out is None:
-        out = torch.empty((par.n_sys, obs.n_obs), dtype=torch.float64, device=dev)
+    out = _out(out, "out", (par.n_sys, obs.n_obs), dev)
     L = load_library()
     _check(L.rv_model(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec), _opts(opts), _stream(dev)))
     return out
@@ -218,8 +234,7 @@ def rv_model(t, P, K, e, omega, M0, offset=None, t0=0.0, prec="mixed", out=None,
 def rv_chisq(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.0, prec="mixed", out=None, opts=None):
     """chi-square per system (Eq. 5), shape (n_sys,)."""
     obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
-    if out is None:
-        out = torch.empty(par.n_sys, dtype=torch.float64, device=dev)
+    out = _out(out, "out", (par.n_sys,), dev)
     L = load_library()
     _check(L.rv_chisq(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec), _opts(opts), _stream(dev)))
     return out
@@ -229,13 +244,25 @@ def rv_chisq_grad(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=
                   out=None, grad=None, opts=None):
     """(chi2 (n_sys,), grad (5 n_pl + 1, n_sys)); rows P, K, e, omega, M0 per planet, then offset."""
     obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
-    if out is None:
-        out = torch.empty(par.n_sys, dtype=torch.float64, device=dev)
-    if grad is None:
-        grad = torch.empty((5 * par.n_pl + 1, par.n_sys), dtype=torch.float64, device=dev)
+    out = _out(out, "out", (par.n_sys,), dev)
+    grad = _out(grad, "grad", (5 * par.n_pl + 1, par.n_sys), dev)
     L = load_library()
     _check(L.rv_chisq_grad(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), grad.data_ptr(), _prec(prec),
                            _opts(opts), _stream(dev)))
+    return out, grad
+
+
+def rv_nll_grad(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.0, prec="mixed",
+                out=None, grad=None, opts=None):
+    """(nll (n_sys,), grad (5 n_pl + 2, n_sys)): nll = chi2 + sum_k ln(sigma_k^2 + s^2)
+    (= -2 ln L without the n_obs ln 2 pi constant); rows P, K, e, omega, M0 per
+    planet, then offset, then jitter."""
+    obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
+    out = _out(out, "out", (par.n_sys,), dev)
+    grad = _out(grad, "grad", (5 * par.n_pl + 2, par.n_sys), dev)
+    L = load_library()
+    _check(L.rv_nll_grad(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), grad.data_ptr(), _prec(prec),
+                         _opts(opts), _stream(dev)))
     return out, grad
 
 
@@ -243,9 +270,7 @@ def rv_planet_velocities(t, P, K, e, omega, M0, t0=0.0, out=None, opts=None):
     """Every planet's velocity (n_pl, n_sys, n_obs) in binary32, mixed precision
     (first kernel of the paper's separate-function form)."""
     obs, par, keep, dev = _obs_params(t, None, None, P, K, e, omega, M0, None, None, t0)
-    if out is None:
-        out = torch.empty((par.n_pl, par.n_sys, obs.n_obs), dtype=torch.float32, device=dev)
-    out = _dev(out, "out", 3, torch.float32)
+    out = _out(out, "out", (par.n_pl, par.n_sys, obs.n_obs), dev, torch.float32)
     _check(load_library().rv_planet_velocities(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _opts(opts),
                                                _stream(dev)))
     return out
@@ -263,8 +288,7 @@ def rv_chisq_from_velocities(t, v, sigma, dv, offset=None, jitter=None, t0=0.0, 
     jitter = _opt_dev(jitter, "jitter", n_sys)
     obs = KepObs(t.data_ptr(), v.data_ptr(), sigma.data_ptr(), n_obs, float(t0))
     par = KepParams(None, None, None, None, None, _ptr(offset), _ptr(jitter), n_sys, n_pl)
-    if out is None:
-        out = torch.empty(n_sys, dtype=torch.float64, device=dv.device)
+    out = _out(out, "out", (n_sys,), dv.device)
     _check(load_library().rv_chisq_from_velocities(ctypes.byref(obs), ctypes.byref(par), dv.data_ptr(),
                                                    out.data_ptr(), _opts(opts), _stream(dv.device)))
     return out
@@ -298,15 +322,13 @@ class RaggedPlan:
 
     def __call__(self, out=None):
         """chi-square per system through the plan's HIP graph."""
-        if out is None:
-            out = torch.empty(self.n_sys, dtype=torch.float64, device=self.device)
+        out = _out(out, "out", (self.n_sys,), self.device)
         _check(load_library().rv_chisq_ragged(self._h, out.data_ptr(), _stream(self.device)))
         return out
 
     def direct(self, out=None):
         """Same computation launched directly (no graph)."""
-        if out is None:
-            out = torch.empty(self.n_sys, dtype=torch.float64, device=self.device)
+        out = _out(out, "out", (self.n_sys,), self.device)
         _check(load_library().rv_chisq_ragged_direct(self._h, out.data_ptr(), _stream(self.device)))
         return out
 

@@ -179,19 +179,30 @@ kep_status rv_chisq(const kep_obs *obs, const kep_params *par, double *chi2, kep
     return launch_status(kep::launch_dense(a, to_prec(prec), false, o.shape, (hipStream_t)stream), fn);
 }
 
-kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2, double *grad, kep_prec prec,
-                         const kep_options *opts, void *stream)
+static kep_status dense_grad(const kep_obs *obs, const kep_params *par, double *out, double *grad, kep_prec prec,
+                             const kep_options *opts, void *stream, bool nll, const char *fn)
 {
-    static const char *fn = "rv_chisq_grad";
     if (kep_status s = check_prec(prec, fn)) return s;
     if (kep_status s = check_dense(obs, par, true, fn)) return s;
     Opts o;
     if (kep_status s = parse_opts(opts, fn, o)) return s;
     if (par->n_sys == 0) return KEP_OK;
-    if (!chi2 || !grad) return fail(KEP_ERR_ARG, "%s: chi2 and grad must not be NULL", fn);
+    if (!out || !grad) return fail(KEP_ERR_ARG, "%s: %s and grad must not be NULL", fn, nll ? "nll" : "chi2");
     if (kep_status s = check_device(fn)) return s;
-    kep::DenseArgs a = make_dense(obs, par, o, chi2, grad);
-    return launch_status(kep::launch_dense_grad(a, to_prec(prec), o.shape, (hipStream_t)stream), fn);
+    kep::DenseArgs a = make_dense(obs, par, o, out, grad);
+    return launch_status(kep::launch_dense_grad(a, to_prec(prec), nll, o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2, double *grad, kep_prec prec,
+                         const kep_options *opts, void *stream)
+{
+    return dense_grad(obs, par, chi2, grad, prec, opts, stream, false, "rv_chisq_grad");
+}
+
+kep_status rv_nll_grad(const kep_obs *obs, const kep_params *par, double *nll, double *grad, kep_prec prec,
+                       const kep_options *opts, void *stream)
+{
+    return dense_grad(obs, par, nll, grad, prec, opts, stream, true, "rv_nll_grad");
 }
 
 kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float *dv, const kep_options *opts,

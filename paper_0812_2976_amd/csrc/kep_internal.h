@@ -18,7 +18,7 @@ struct DenseArgs {
     int n_pl;
     int sb;            // systems per setup batch of one wavefront (1..kMaxSB)
     double *out;       // chi2 [n_sys] or model [n_sys][n_obs]
-    double *grad;      // gradient [(5 n_pl + 1)][n_sys] (gradient kernel only)
+    double *grad;      // gradient [(5 n_pl + 1 (+1 for the likelihood))][n_sys] (gradient kernels only)
     float *dv;         // per-planet velocities [n_pl][n_sys][n_obs] (separate-function form)
     int fixed_iter;    // > 0: fixed Danby count; <= 0: eccentricity schedule
     int max_iter;      // cap of the convergence-tested loop
@@ -56,7 +56,7 @@ struct LaunchShape {
 hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int64_t n, Prec prec,
                                int fixed_iter, int max_iter, LaunchShape shape, hipStream_t st);
 hipError_t launch_dense(DenseArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
-hipError_t launch_dense_grad(DenseArgs a, Prec prec, LaunchShape shape, hipStream_t st);
+hipError_t launch_dense_grad(DenseArgs a, Prec prec, bool nll, LaunchShape shape, hipStream_t st);
 hipError_t launch_planet_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);

@@ -628,7 +628,10 @@ __device__ __forceinline__ double grad_eval(const GradPlanet<double> &g, double 
     return g.K * dvdK;
 }
 
-template <int NPL>
+// NLL = true: the Gaussian likelihood with jitter, -2 ln L = chi2 +
+// sum_k ln(sigma_k^2 + s^2) (constant dropped), and one more gradient row,
+// d/ds = 2 s (sum_k w_k - sum_k w_k^2 r_k^2).
+template <int NPL, bool NLL>
 __global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -649,6 +652,7 @@ __global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
         Kahan32 chi;
         chi.init();
         double acc[NPL][5], sum_c2 = 0.0;   // binary64 running sums of 2 w r x
+        double sum_lv = 0.0, sum_w = 0.0, sum_wr2 = 0.0;
 #pragma unroll
         for (int j = 0; j < NPL; ++j) {
 #pragma unroll
@@ -666,8 +670,14 @@ __global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
             const float r = (float)(((double)msum.s - (double)msum.c + gam) - vo);
             const float var = (float)(sg * sg) + jit2;
             ok = ok && var > 0.0f;
-            const float wr = rcp32(var) * r;
+            const float w = rcp32(var);
+            const float wr = w * r;
             chi.add(wr * r);
+            if (NLL) {
+                sum_lv += (double)logf(var);
+                sum_w += (double)w;
+                sum_wr2 = fma((double)wr, (double)wr, sum_wr2);
+            }
             const double c2 = 2.0 * (double)wr;
             sum_c2 += c2;
 #pragma unroll
@@ -677,7 +687,8 @@ __global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
             }
         }
         const double nan = __builtin_nan("");
-        a.out[sys] = ok ? chi.value() : nan;
+        a.out[sys] = ok ? chi.value() + sum_lv : nan;
+        if (NLL) a.grad[(int64_t)(5 * NPL + 1) * a.n_sys + sys] = ok ? 2.0 * jit * (sum_w - sum_wr2) : nan;
 #pragma unroll
         for (int j = 0; j < NPL; ++j) {
             const int64_t p = (int64_t)j * a.n_sys + sys;
@@ -696,7 +707,7 @@ __global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
     }
 }
 
-template <int NPL>
+template <int NPL, bool NLL>
 __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -715,6 +726,7 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
         if (a.offset) ok = ok && isfinite(gam);
         if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
         double chi = 0.0, gacc[5 * NPL + 1];
+        double sum_lv = 0.0, sum_w = 0.0, sum_wr2 = 0.0;
 #pragma unroll
         for (int i = 0; i < 5 * NPL + 1; ++i) gacc[i] = 0.0;
         for (int64_t k = 0; k < a.n_obs; ++k) {
@@ -730,6 +742,11 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
             ok = ok && var > 0.0;
             const double w = 1.0 / var;
             chi = fma(w * r, r, chi);
+            if (NLL) {
+                sum_lv += log(var);
+                sum_w += w;
+                sum_wr2 = fma(w * r, w * r, sum_wr2);
+            }
             const double c2 = 2.0 * w * r;
 #pragma unroll
             for (int j = 0; j < NPL; ++j) {
@@ -739,9 +756,10 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
             gacc[5 * NPL] += c2;
         }
         const double nan = __builtin_nan("");
-        a.out[sys] = ok ? chi : nan;
+        a.out[sys] = ok ? chi + sum_lv : nan;
 #pragma unroll
         for (int i = 0; i < 5 * NPL + 1; ++i) a.grad[(int64_t)i * a.n_sys + sys] = ok ? gacc[i] : nan;
+        if (NLL) a.grad[(int64_t)(5 * NPL + 1) * a.n_sys + sys] = ok ? 2.0 * jit * (sum_w - sum_wr2) : nan;
     }
 }
 
@@ -982,15 +1000,17 @@ static int grad_grid(int64_t n_sys, int block, int per_cu)
     return (int)(need < cap ? (need > 0 ? need : 1) : cap);
 }
 
-hipError_t launch_dense_grad(DenseArgs a, Prec prec, LaunchShape shape, hipStream_t st)
+hipError_t launch_dense_grad(DenseArgs a, Prec prec, bool nll, LaunchShape shape, hipStream_t st)
 {
     if (a.n_sys <= 0) return hipSuccess;
     const int block = shape.block > 0 ? shape.block : 256;
     const int grid = grad_grid(a.n_sys, block, shape.blocks_per_cu);
+#define KEP_GRAD_LAUNCH(N, L)                                                                   \
+    if (prec == Prec::Mixed) hipLaunchKernelGGL((k_grad_mixed<N, L>), dim3(grid), dim3(block), 0, st, a); \
+    else hipLaunchKernelGGL((k_grad_f64<N, L>), dim3(grid), dim3(block), 0, st, a);
 #define KEP_GRAD_CASE(N)                                                                     \
     case N:                                                                                  \
-        if (prec == Prec::Mixed) hipLaunchKernelGGL(k_grad_mixed<N>, dim3(grid), dim3(block), 0, st, a); \
-        else hipLaunchKernelGGL(k_grad_f64<N>, dim3(grid), dim3(block), 0, st, a);            \
+        if (nll) { KEP_GRAD_LAUNCH(N, true) } else { KEP_GRAD_LAUNCH(N, false) }              \
         break;
     switch (a.n_pl) {
         KEP_GRAD_CASE(1)
@@ -1004,6 +1024,7 @@ hipError_t launch_dense_grad(DenseArgs a, Prec prec, LaunchShape shape, hipStrea
         default: return hipErrorInvalidValue;
     }
 #undef KEP_GRAD_CASE
+#undef KEP_GRAD_LAUNCH
     return hipGetLastError();
 }
 

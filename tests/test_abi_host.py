@@ -29,7 +29,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     fns = _declared_functions()
-    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "kep_plan_ragged", "rv_chisq_ragged",
+    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "kep_plan_ragged",
+                 "rv_chisq_ragged",
                  "kep_plan_destroy", "kep_last_error"):
         assert name in fns
 
@@ -73,6 +74,9 @@ def test_dense_argument_errors(lib):
     obs.n_obs = 0
     par.n_sys = 0
     assert lib.rv_chisq_grad(ctypes.byref(obs), ctypes.byref(par), None, None, 1, None, None) == 0
+    assert lib.rv_nll_grad(ctypes.byref(obs), ctypes.byref(par), None, None, 1, None, None) == 0
+    code, msg = _status(lib.rv_nll_grad(ctypes.byref(obs), ctypes.byref(par), None, None, 3, None, None), lib)
+    assert code == 1 and "rv_nll_grad" in msg
     assert lib.rv_chisq(None, ctypes.byref(par), None, 1, None, None) == 1
 
 

@@ -386,3 +386,45 @@ def test_ragged_equals_per_system_dense():
         d = oracle.Dense(rw.t[o0:o1], rw.v[o0:o1], rw.sigma[o0:o1], rw.P[p0:p1, None], rw.K[p0:p1, None],
                          rw.e[p0:p1, None], rw.w[p0:p1, None], rw.M0[p0:p1, None], rw.offset[i:i + 1])
         assert oracle.chisq(d)[0] == out[i]
+
+
+# ------------------------------------------------- likelihood with jitter (Eq. 5)
+def test_nll_single_observation_closed_form_and_optimal_jitter():
+    """One observation: -2 ln L = r^2/(sigma^2 + s^2) + ln(sigma^2 + s^2), whose
+    derivative in s vanishes at s^2 = r^2 - sigma^2 (the maximum-likelihood jitter)."""
+    t = np.array([2455123.25])
+    p = dict(P=[[11.3]], K=[[40.0]], e=[[0.3]], w=[[1.0]], M0=[[2.0]])
+    v_model = oracle.rv_model(oracle.Dense(t, [0.0], [1.0], *(p[k] for k in ("P", "K", "e", "w", "M0"))))[0, 0]
+    v = np.array([v_model - 7.0])              # residual r = model - v = 7
+    sigma = np.array([3.0])
+    for s in (0.0, 2.0, 5.0):
+        d = oracle.Dense(t, v, sigma, *(p[k] for k in ("P", "K", "e", "w", "M0")), jitter=[s])
+        nll, grad = oracle.nll_grad(d)
+        var = 9.0 + s * s
+        assert nll[0] == pytest.approx(49.0 / var + math.log(var), rel=1e-12)
+        assert grad[-1, 0] == pytest.approx(2 * s / var - 2 * s * 49.0 / var ** 2, abs=1e-12)
+    s_opt = math.sqrt(49.0 - 9.0)
+    d = oracle.Dense(t, v, sigma, *(p[k] for k in ("P", "K", "e", "w", "M0")), jitter=[s_opt])
+    assert abs(oracle.nll_grad(d)[1][-1, 0]) < 1e-12
+
+
+def test_nll_matches_chisq_plus_log_terms_and_fd_in_jitter():
+    """-2 ln L - chi2 = sum ln(sigma^2 + s^2); the planet and offset rows equal the
+    chi-square gradient; d/ds matches central differences."""
+    wl = _small_dense(n_sys=5, n_pl=2, n_obs=30, jitter=True, offset=True)
+    synth.with_observations(wl, _mp_model)
+    d = _dense(wl)
+    nll, grad = oracle.nll_grad(d)
+    chi2, gchi = oracle.chisq_grad(d)
+    for i in range(wl.n_sys):
+        assert nll[i] - chi2[i] == pytest.approx(np.sum(np.log(wl.sigma ** 2 + wl.jitter[i] ** 2)), rel=1e-12)
+    assert np.allclose(grad[:-1], gchi, rtol=1e-14, atol=0)
+    h = 1e-6
+    for i in range(wl.n_sys):
+        vals = []
+        for sgn in (1, -1):
+            jit = wl.jitter.copy()
+            jit[i] += sgn * h
+            dd = oracle.Dense(wl.t, wl.v, wl.sigma, wl.P, wl.K, wl.e, wl.w, wl.M0, wl.offset, jit, wl.t0)
+            vals.append(oracle.nll_grad(dd, i, i + 1)[0][i])
+        assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(grad[-1, i], rel=1e-6, abs=1e-6)
