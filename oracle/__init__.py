@@ -45,6 +45,14 @@ class _Ragged(ctypes.Structure):
                 ("n_sys", ctypes.c_int64)]
 
 
+class _Demc(ctypes.Structure):
+    _fields_ = [("t", _D), ("v", _D), ("sigma", _D), ("n_obs", ctypes.c_int64), ("t0", ctypes.c_double),
+                ("x", _D), ("chi2", _D), ("n_accept", _I64), ("jitter", _D),
+                ("n_half", ctypes.c_int64), ("n_pl", ctypes.c_int64),
+                ("gamma", ctypes.c_double), ("jump_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("eps", _D)]
+
+
 def lib():
     """Load (building first if nothing is built) the oracle shared library."""
     global _LIB
@@ -75,6 +83,11 @@ def lib():
         L.oracle_chisq_grad_scales.argtypes = [ctypes.POINTER(_Dense), _D, _D, _D, _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_ragged.restype = None
         L.oracle_chisq_ragged.argtypes = [ctypes.POINTER(_Ragged), _D, ctypes.c_int64, ctypes.c_int64]
+        _U32 = ctypes.POINTER(ctypes.c_uint32)
+        L.oracle_philox4x32_10.restype = None
+        L.oracle_philox4x32_10.argtypes = [_U32, _U32, _U32]
+        L.oracle_demc_run.restype = None
+        L.oracle_demc_run.argtypes = [ctypes.POINTER(_Demc), ctypes.c_uint64, ctypes.c_int64]
         _LIB = L
     return _LIB
 
@@ -205,3 +218,47 @@ def chisq_ragged(d: Ragged, i0=0, i1=None, out=None):
         out = np.full(d.n_sys, np.nan)
     lib().oracle_chisq_ragged(ctypes.byref(d._s), _ptr(out), i0, i1)
     return out
+
+
+def philox4x32_10(ctr, key):
+    """Philox-4x32-10 block (Salmon et al. 2011): four 32-bit words from a
+    128-bit counter and a 64-bit key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    P32 = ctypes.POINTER(ctypes.c_uint32)
+    lib().oracle_philox4x32_10(c.ctypes.data_as(P32), k.ctypes.data_as(P32), out.ctypes.data_as(P32))
+    return out
+
+
+def demc_init_chisq(t, v, sigma, x, n_pl, jitter=None, t0=0.0):
+    """chi-square [2, n_half] of a population x [2, 5 n_pl + 1, n_half] (Eq. 5);
+    NaN where a chain lies outside the prior support (K < 0 included)."""
+    x = np.asarray(x, dtype=np.float64)
+    nh = x.shape[2]
+    out = np.empty((2, nh))
+    for h in range(2):
+        X = np.ascontiguousarray(x[h])
+        planes = [X[a * n_pl:(a + 1) * n_pl] for a in range(5)]
+        jit = None if jitter is None else np.asarray(jitter, dtype=np.float64)[h]
+        out[h] = chisq(Dense(t, v, sigma, *planes, X[5 * n_pl], jit, t0))
+        out[h][np.any(planes[1] < 0.0, axis=0)] = np.nan
+    return out
+
+
+def demc_run(t, v, sigma, x, chi2, n_pl, eps, seed, gen0, n_gen, jitter=None, t0=0.0, gamma=0.0,
+             jump_every=0, n_accept=None):
+    """Run n_gen DE-MC generations (ter Braak 2006, split population; the
+    sampler named in Sec. 6) on copies of x [2, 5 n_pl + 1, n_half] and
+    chi2 [2, n_half]; returns (x, chi2, n_accept)."""
+    t, v, sigma = _f64(t), _f64(v), _f64(sigma)
+    x = np.array(x, dtype=np.float64, copy=True, order="C")
+    chi2 = np.array(chi2, dtype=np.float64, copy=True, order="C")
+    nh = x.shape[2]
+    acc = np.zeros((2, nh), dtype=np.int64) if n_accept is None else np.array(n_accept, dtype=np.int64, copy=True)
+    jit = None if jitter is None else np.ascontiguousarray(jitter, dtype=np.float64)
+    eps = _f64(eps)
+    s = _Demc(_ptr(t), _ptr(v), _ptr(sigma), t.size, float(t0), _ptr(x), _ptr(chi2), acc.ctypes.data_as(_I64),
+              _ptr(jit), nh, n_pl, float(gamma), int(jump_every), 0, int(seed) & (2 ** 64 - 1), _ptr(eps))
+    lib().oracle_demc_run(ctypes.byref(s), int(gen0), int(n_gen))
+    return x, chi2, acc

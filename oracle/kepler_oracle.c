@@ -356,3 +356,151 @@ void oracle_chisq_ragged(const oracle_ragged *d, double *chi2, int64_t i0, int64
         chi2[i] = ok ? (double)acc : NAN;
     }
 }
+
+/* ================================================================== */
+/* Counter-based random numbers: Philox-4x32-10 (Salmon, Moraes, Dror  */
+/* and Shaw, SC'11, "Parallel random numbers: as easy as 1, 2, 3").    */
+/* One round maps the counter (c0, c1, c2, c3) under key (k0, k1) to   */
+/*   (hi(B c2) ^ c1 ^ k0, lo(B c2), hi(A c0) ^ c3 ^ k1, lo(A c0)),     */
+/* A = 0xD2511F53, B = 0xCD9E8D57 (32 x 32 -> 64-bit products); the    */
+/* key is advanced by (0x9E3779B9, 0xBB67AE85) before every round but  */
+/* the first; ten rounds.                                              */
+/* ================================================================== */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)pb;
+        uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)pa;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform double in (0, 1] from two 32-bit words: the top 27 bits of a and
+   the top 26 bits of b form a 53-bit integer n, u = (n + 1) / 2^53. */
+static double unit53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 1.0) * 0x1p-53;
+}
+
+/* Integer in [0, m) from one 32-bit word: floor(w m / 2^32). */
+static uint32_t below(uint32_t w, uint32_t m)
+{
+    return (uint32_t)(((uint64_t)w * (uint64_t)m) >> 32);
+}
+
+/* ================================================================== */
+/* Population MCMC by differential evolution (DE-MC, ter Braak 2006),  */
+/* the many-chain sampler the paper names as the target application    */
+/* of the batched chi-square (Sec. 6).  Target density exp(-chi2 / 2)  */
+/* with a flat prior on P > 0, K >= 0, 0 <= e < 1 and any finite       */
+/* omega, M0, gamma.                                                   */
+/*                                                                     */
+/* The population is split into two halves of n_half chains.  One      */
+/* generation updates half 0 with differences of half-1 chains, then   */
+/* half 1 with differences of the (updated) half-0 chains, so each     */
+/* chain's proposal depends only on chains that do not move while it   */
+/* is updated.  For chain i of half h at generation g:                 */
+/*   draw 0:  r1, r2 distinct chains of the other half, u in (0, 1]    */
+/*   draws 1..: Box-Muller normals z_r, two per draw                   */
+/*   y_r = x_r[i] + gam (x_r[r1] - x_r[r2]) + eps_r z_r                */
+/*   accept iff 2 ln u < chi2(x) - chi2(y)  (Metropolis, symmetric)    */
+/* gam = 2.38 / sqrt(2 d) by default, 1 on every jump_every-th          */
+/* generation.  Draw j of (h, i, g) is Philox-4x32-10 at counter       */
+/* (i, j, g mod 2^32, floor(g / 2^32) + 2^31 h) under key (seed mod    */
+/* 2^32, floor(seed / 2^32)).                                          */
+/* Parameter rows (d = 5 n_pl + 1): P_0..P_{n-1}, K.., e.., omega..,   */
+/* M0.., gamma, so each half is [d][n_half] in the dense plane layout. */
+/* ================================================================== */
+typedef struct {
+    const double *t, *v, *sigma;
+    int64_t n_obs;
+    double t0;
+    double *x;              /* [2][d][n_half], updated in place */
+    double *chi2;           /* [2][n_half], updated in place */
+    int64_t *n_accept;      /* [2][n_half], incremented; may be NULL */
+    const double *jitter;   /* [2][n_half] or NULL (zero) */
+    int64_t n_half, n_pl;
+    double gamma;           /* <= 0: 2.38 / sqrt(2 d) */
+    int32_t jump_every;     /* > 0: gam = 1 when (g + 1) % jump_every == 0 */
+    int32_t reserved;
+    uint64_t seed;
+    const double *eps;      /* [d] */
+} oracle_demc;
+
+static void demc_draw(const oracle_demc *s, int h, int64_t i, uint32_t j, uint64_t g, uint32_t out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)i, j, (uint32_t)g, (uint32_t)(g >> 32) | ((uint32_t)h << 31)};
+    uint32_t key[2] = {(uint32_t)s->seed, (uint32_t)(s->seed >> 32)};
+    oracle_philox4x32_10(ctr, key, out);
+}
+
+/* chi-square of one parameter vector y[d] (Eq. 5) through the dense oracle. */
+static double demc_chisq(const oracle_demc *s, const double *y, const double *jit)
+{
+    const int64_t n = s->n_pl;
+    for (int64_t j = 0; j < n; ++j)
+        if (!(y[n + j] >= 0.0)) return NAN;            /* K >= 0: prior support */
+    oracle_dense d = {s->t, s->v, s->sigma, s->n_obs, s->t0,
+                      y, y + n, y + 2 * n, y + 3 * n, y + 4 * n, y + 5 * n, jit, 1, n};
+    double c = NAN;
+    oracle_chisq(&d, &c, 0, 1);
+    return c;
+}
+
+static const double TWO_PI_D = 6.28318530717958647692528676655900577;
+
+static void demc_half(const oracle_demc *s, int h, uint64_t g)
+{
+    const int64_t d = 5 * s->n_pl + 1, nh = s->n_half;
+    double *xh = s->x + (int64_t)h * d * nh;
+    const double *xo = s->x + (int64_t)(1 - h) * d * nh;
+    double gam = s->gamma > 0.0 ? s->gamma : 2.38 / sqrt(2.0 * (double)d);
+    if (s->jump_every > 0 && (g + 1) % (uint64_t)s->jump_every == 0) gam = 1.0;
+    double y[5 * 8 + 1], z[5 * 8 + 2];
+    for (int64_t i = 0; i < nh; ++i) {
+        uint32_t w[4];
+        demc_draw(s, h, i, 0, g, w);
+        uint32_t r1 = below(w[0], (uint32_t)nh);
+        uint32_t r2 = below(w[1], (uint32_t)nh - 1u);
+        if (r2 >= r1) r2 += 1u;
+        double u = unit53(w[2], w[3]);
+        for (int64_t r = 0; r < d; r += 2) {
+            demc_draw(s, h, i, (uint32_t)(1 + r / 2), g, w);
+            double u1 = unit53(w[0], w[1]), u2 = unit53(w[2], w[3]);
+            double rho = sqrt(-2.0 * log(u1));
+            z[r] = rho * cos(TWO_PI_D * u2);
+            z[r + 1] = rho * sin(TWO_PI_D * u2);
+        }
+        for (int64_t r = 0; r < d; ++r)
+            y[r] = xh[r * nh + i] + gam * (xo[r * nh + r1] - xo[r * nh + r2]) + s->eps[r] * z[r];
+        const double *jit = s->jitter ? s->jitter + (int64_t)h * nh + i : NULL;
+        double c_new = demc_chisq(s, y, jit);
+        double c_old = s->chi2[(int64_t)h * nh + i];
+        if (2.0 * log(u) < c_old - c_new) {            /* false for NaN */
+            for (int64_t r = 0; r < d; ++r) xh[r * nh + i] = y[r];
+            s->chi2[(int64_t)h * nh + i] = c_new;
+            if (s->n_accept) s->n_accept[(int64_t)h * nh + i] += 1;
+        }
+    }
+}
+
+/* Run generations gen0 .. gen0 + n_gen - 1.  n_half >= 2, 1 <= n_pl <= 8. */
+void oracle_demc_run(const oracle_demc *s, uint64_t gen0, int64_t n_gen)
+{
+    if (s->n_half < 2 || s->n_pl < 1 || s->n_pl > 8) return;
+    for (int64_t k = 0; k < n_gen; ++k) {
+        demc_half(s, 0, gen0 + (uint64_t)k);
+        demc_half(s, 1, gen0 + (uint64_t)k);
+    }
+}

@@ -27,12 +27,24 @@ MUTANTS = {
     "dfdM_power": ("ld dfdM = ecf * ecf / (one_m_e2 * b);", "ld dfdM = ecf * ecf / one_m_e2;"),
     "kepler_wrong_sign": ("ld g = E - e * sinl(E) - M;\n        if (g == 0.0L) return E;", "ld g = E + e * sinl(E) - M;\n        if (g == 0.0L) return E;"),
     "phase_not_binary64": ("double q = dt / P;", "double q = (double)((float)dt / (float)P);"),
+    "nll_log_term_dropped": ("sum_logvar -= logl(wk);", ""),
+    "nll_jitter_grad_sign": ("(2.0L * s * (sum_w - sum_w2r2))", "(2.0L * s * (sum_w2r2 - sum_w))"),
+    # population sampler (pins in test_oracle_demc.py)
+    "demc_acceptance_without_half": ("if (2.0 * log(u) < c_old - c_new)", "if (log(u) < c_old - c_new)", "demc"),
+    "demc_own_half_differences": ("const double *xo = s->x + (int64_t)(1 - h) * d * nh;", "const double *xo = xh;",
+                                  "demc"),
+    "demc_pair_not_distinct": ("if (r2 >= r1) r2 += 1u;", "", "demc"),
+    "demc_no_K_support": ("if (!(y[n + j] >= 0.0)) return NAN;", "if (0) return NAN;", "demc"),
+    "philox_round_order": ("uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;", "uint32_t n0 = (uint32_t)(pa >> 32) ^ c1 ^ k0;",
+                           "demc"),
 }
+PIN_FILES = {None: "test_oracle_pins.py", "demc": "test_oracle_demc.py"}
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_mutant(name, tmp_path):
-    old, new = MUTANTS[name]
+    old, new, *which = MUTANTS[name]
+    pins = PIN_FILES[which[0] if which else None]
     src = open(obuild.SRC).read()
     assert src.count(old) >= 1, name
     mutated = tmp_path / "mutant.c"
@@ -40,6 +52,6 @@ def test_pins_catch_mutant(name, tmp_path):
     lib = obuild.build(src=str(mutated), out=str(tmp_path / "libmutant.so"))
     env = dict(os.environ, KEP_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", pins)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"pins did not catch mutant {name}:\n{r.stdout[-2000:]}"
