@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--rows", default="fp64,separate,grad,ragged,kepler",
+    ap.add_argument("--rows", default="fp64,separate,grad,ragged,demc,kepler",
                     help="extra paths to time (comma list or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="systems in the CPU oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -249,6 +249,42 @@ def main():
                                "plan": {k: info[k] for k in ("block_threads", "blocks", "sys_per_batch", "group_chunks", "tuned")}}
         plan.close()
         del o3
+
+    # ------------------------------------------------------------ DE-MC sampler
+    if "demc" in rows:
+        log("DE-MC sampler on c1 observations (n_obs=256, n_pl=4)")
+        w1 = synth.with_observations(synth.dense("c1", n_sys=2), gpu_truth_model)
+        demc = {}
+        for nh in (2048, 32768):
+            x0, eps = synth.demc_population(w1.truth, nh)
+            s = kp.DEMC(gpu(w1.t), gpu(w1.v), gpu(w1.sigma), gpu(x0), gpu(eps), seed=1, t0=w1.t0,
+                        jump_every=10, prec="mixed")
+            gen = [0]
+
+            def graph_step():
+                s.run(gen[0], 10)
+                gen[0] += 10
+
+            def direct_step():
+                s.generations(gen[0], 10)
+                gen[0] += 10
+
+            ms_g, _ = timed(graph_step, 5, 1, torch)
+            ms_d, _ = timed(direct_step, 5, 1, torch)
+            # the chi-square launch of one half alone, for the share of a generation it takes
+            half = {k: gpu(np.ascontiguousarray(x0[0, a * 4:(a + 1) * 4])) for a, k in
+                    enumerate(("P", "K", "e", "omega", "M0"))}
+            obs = dict(t=gpu(w1.t), v=gpu(w1.v), sigma=gpu(w1.sigma), t0=w1.t0)
+            oh = torch.empty(nh, dtype=torch.float64, device=dev)
+            ms_c, _ = timed(lambda: kp.rv_chisq(**obs, **half, prec="mixed", out=oh), 10, 2, torch)
+            acc = s.n_accept.sum().item() / (2 * nh * gen[0])
+            demc[f"chains_{2 * nh}"] = {
+                "generations_per_s_graph": 10 / (ms_g * 1e-3), "generations_per_s_direct": 10 / (ms_d * 1e-3),
+                "proposals_per_s": 2 * nh * 10 / (ms_g * 1e-3), "generation_ms_graph": ms_g / 10,
+                "chisq_share_of_generation": 2 * ms_c / (ms_g / 10), "acceptance": acc}
+            s.close()
+            del s, half, obs, oh
+        result["demc_c1"] = demc
 
     # ------------------------------------------------------------ Kepler only
     if "kepler" in rows:

@@ -219,6 +219,73 @@ kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info);
 
 void kep_plan_destroy(kep_plan *plan);
 
+/* ---- population sampler: differential-evolution MCMC (DE-MC) ----
+   The many-chain MCMC that the batched chi-square serves (Sec. 6 names
+   population MCMC and DEMCMC with hundreds to thousands of chains): DE-MC of
+   ter Braak (2006) with target exp(-chi2/2) (Eq. 5, jitter fixed per chain)
+   and a flat prior on P > 0, K >= 0, 0 <= e < 1, omega, M0 and gamma finite.
+   The population is two halves of n_half chains; a generation updates half 0
+   using differences of half-1 chains, then half 1 using differences of the
+   updated half 0, so no chain's proposal depends on a chain moving with it:
+     y = x_i + gam (x_r1 - x_r2) + eps z,  r1 != r2 uniform in the other half,
+     z_r standard normal (Box-Muller), accepted iff 2 ln u < chi2(x_i) - chi2(y).
+   gam = options->gamma, or 2.38/sqrt(2 d) when gamma <= 0; gam = 1 on every
+   generation g with (g + 1) % jump_every == 0 (jump_every > 0).  Random
+   numbers: Philox-4x32-10 keyed by the 64-bit seed (low word first), counter
+   (chain, draw, g mod 2^32, (g >> 32) | half << 31); draw 0 gives r1, r2 and
+   u, draws 1.. give two normals each (rows 2j-2, 2j-1).  A proposal is thus a
+   function of (seed, half, chain, generation) only: runs are reproducible and
+   independent of launch shape.
+   State (device, caller-owned, updated in place):
+     x        [2][d][n_half], d = 5 n_pl + 1: each half is a kep_params set of
+              planes P[n_pl][n_half], K, e, omega, M0, then the offset row;
+     chi2     [2][n_half] chi-square of each chain's state (demc_chisq);
+     n_accept [2][n_half] accepted proposals per chain, incremented (or NULL);
+     jitter   [2][n_half] fixed jitter of each chain (or NULL = 0).
+   2 <= n_half < 2^31, 1 <= n_pl <= KEP_MAX_PL.  A chain whose chi2 is NaN
+   (state outside the support) never moves. */
+typedef struct kep_demc_state {
+    double *x;
+    double *chi2;
+    int64_t *n_accept;
+    const double *jitter;
+    int64_t n_half, n_pl;
+} kep_demc_state;
+
+typedef struct kep_demc_options {
+    double gamma;             /* difference scale; <= 0: 2.38 / sqrt(2 d) */
+    int32_t jump_every;       /* > 0: gam = 1 every jump_every-th generation */
+    int32_t reserved;
+    uint64_t seed;            /* Philox key */
+    const double *eps;        /* [d] device: standard deviation of the normal term per row */
+} kep_demc_options;
+
+/* chi2 of every chain of the population (both halves; NaN where a K < 0). */
+kep_status demc_chisq(const kep_obs *obs, const kep_demc_state *state, kep_prec prec,
+                      const kep_options *opts, void *stream);
+
+/* Generations gen0 .. gen0 + n_gen - 1, launched directly (7 launches per
+   generation).  work: device workspace of (d + 1) * n_half doubles (proposals
+   and their chi-square), owned by the caller.  Does not allocate or
+   synchronise.  prec selects the chi-square kernel (the sampler's own
+   arithmetic is binary64 in both). */
+kep_status demc_generations(const kep_obs *obs, const kep_demc_state *state, const kep_demc_options *options,
+                            uint64_t gen0, int64_t n_gen, double *work, kep_prec prec,
+                            const kep_options *opts, void *stream);
+
+/* The same generation recorded once as a HIP graph whose kernels read the
+   generation number from a device counter that the graph's last node
+   advances; demc_run sets the counter to gen0 and launches the graph n_gen
+   times.  Results equal demc_generations bit for bit.  kep_plan_demc
+   allocates (the counter) and keeps every pointer of state, options and work;
+   calls on one plan must not overlap; synchronise before destroying it. */
+typedef struct kep_demc_plan kep_demc_plan;
+kep_status kep_plan_demc(const kep_obs *obs, const kep_demc_state *state, const kep_demc_options *options,
+                         double *work, kep_prec prec, const kep_options *opts, void *stream,
+                         kep_demc_plan **out);
+kep_status demc_run(kep_demc_plan *plan, uint64_t gen0, int64_t n_gen, void *stream);
+void kep_demc_plan_destroy(kep_demc_plan *plan);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *kep_last_error(void);
 

@@ -50,7 +50,7 @@ class _Demc(ctypes.Structure):
                 ("x", _D), ("chi2", _D), ("n_accept", _I64), ("jitter", _D),
                 ("n_half", ctypes.c_int64), ("n_pl", ctypes.c_int64),
                 ("gamma", ctypes.c_double), ("jump_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("eps", _D)]
+                ("seed", ctypes.c_uint64), ("eps", _D), ("margin", _D)]
 
 
 def lib():
@@ -247,10 +247,12 @@ def demc_init_chisq(t, v, sigma, x, n_pl, jitter=None, t0=0.0):
 
 
 def demc_run(t, v, sigma, x, chi2, n_pl, eps, seed, gen0, n_gen, jitter=None, t0=0.0, gamma=0.0,
-             jump_every=0, n_accept=None):
+             jump_every=0, n_accept=None, margin=False):
     """Run n_gen DE-MC generations (ter Braak 2006, split population; the
     sampler named in Sec. 6) on copies of x [2, 5 n_pl + 1, n_half] and
-    chi2 [2, n_half]; returns (x, chi2, n_accept)."""
+    chi2 [2, n_half]; returns (x, chi2, n_accept), plus, with margin=True,
+    the last generation's decision margins (chi2(x) - chi2(y)) - 2 ln u
+    [2, n_half] (a proposal is accepted iff its margin is > 0)."""
     t, v, sigma = _f64(t), _f64(v), _f64(sigma)
     x = np.array(x, dtype=np.float64, copy=True, order="C")
     chi2 = np.array(chi2, dtype=np.float64, copy=True, order="C")
@@ -258,7 +260,8 @@ def demc_run(t, v, sigma, x, chi2, n_pl, eps, seed, gen0, n_gen, jitter=None, t0
     acc = np.zeros((2, nh), dtype=np.int64) if n_accept is None else np.array(n_accept, dtype=np.int64, copy=True)
     jit = None if jitter is None else np.ascontiguousarray(jitter, dtype=np.float64)
     eps = _f64(eps)
+    mg = np.full((2, nh), np.nan) if margin else None
     s = _Demc(_ptr(t), _ptr(v), _ptr(sigma), t.size, float(t0), _ptr(x), _ptr(chi2), acc.ctypes.data_as(_I64),
-              _ptr(jit), nh, n_pl, float(gamma), int(jump_every), 0, int(seed) & (2 ** 64 - 1), _ptr(eps))
+              _ptr(jit), nh, n_pl, float(gamma), int(jump_every), 0, int(seed) & (2 ** 64 - 1), _ptr(eps), _ptr(mg))
     lib().oracle_demc_run(ctypes.byref(s), int(gen0), int(n_gen))
-    return x, chi2, acc
+    return (x, chi2, acc, mg) if margin else (x, chi2, acc)

@@ -436,6 +436,7 @@ typedef struct {
     int32_t reserved;
     uint64_t seed;
     const double *eps;      /* [d] */
+    double *margin;         /* [2][n_half] or NULL: (chi2(x) - chi2(y)) - 2 ln u of the last generation */
 } oracle_demc;
 
 static void demc_draw(const oracle_demc *s, int h, int64_t i, uint32_t j, uint64_t g, uint32_t out[4])
@@ -487,6 +488,7 @@ static void demc_half(const oracle_demc *s, int h, uint64_t g)
         const double *jit = s->jitter ? s->jitter + (int64_t)h * nh + i : NULL;
         double c_new = demc_chisq(s, y, jit);
         double c_old = s->chi2[(int64_t)h * nh + i];
+        if (s->margin) s->margin[(int64_t)h * nh + i] = (c_old - c_new) - 2.0 * log(u);
         if (2.0 * log(u) < c_old - c_new) {            /* false for NaN */
             for (int64_t r = 0; r < d; ++r) xh[r * nh + i] = y[r];
             s->chi2[(int64_t)h * nh + i] = c_new;

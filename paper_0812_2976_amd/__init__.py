@@ -14,6 +14,7 @@ Functions keep the C names:
   rv_nll_grad(...)                         likelihood with jitter and its gradient
   rv_planet_velocities / rv_chisq_from_velocities   the separate-function form
   RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
+  DEMC(...)                                population sampler (DE-MC) on the batched chi-square
   RVChiSq.apply(...)                       torch.autograd.Function over rv_chisq_grad
 Parameter planes are float64 CUDA tensors shaped (n_pl, n_sys) (system index
 fastest); observations are 1-D float64 CUDA tensors.
@@ -66,6 +67,16 @@ class KepPlanInfo(ctypes.Structure):
                 ("group_chunks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class KepDemcState(ctypes.Structure):
+    _fields_ = [("x", _D), ("chi2", _D), ("n_accept", _D), ("jitter", _D), ("n_half", ctypes.c_int64),
+                ("n_pl", ctypes.c_int64)]
+
+
+class KepDemcOptions(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("jump_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("eps", _D)]
+
+
 class KeplerError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -76,7 +87,8 @@ _LIB = None
 
 EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
            "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
-           "kep_plan_get_info", "kep_plan_destroy", "kep_last_error", "kep_abi_version")
+           "kep_plan_get_info", "kep_plan_destroy", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
+           "kep_demc_plan_destroy", "kep_last_error", "kep_abi_version")
 
 
 def load_library(path: str = LIB_PATH):
@@ -102,12 +114,20 @@ def load_library(path: str = LIB_PATH):
     L.kep_plan_get_info.argtypes = [_D, P(KepPlanInfo)]
     L.kep_plan_destroy.argtypes = [_D]
     L.kep_plan_destroy.restype = None
+    L.demc_chisq.argtypes = [P(KepObs), P(KepDemcState), ctypes.c_int, P(KepOptions), _D]
+    L.demc_generations.argtypes = [P(KepObs), P(KepDemcState), P(KepDemcOptions), ctypes.c_uint64, ctypes.c_int64,
+                                   _D, ctypes.c_int, P(KepOptions), _D]
+    L.kep_plan_demc.argtypes = [P(KepObs), P(KepDemcState), P(KepDemcOptions), _D, ctypes.c_int, P(KepOptions), _D,
+                                P(_D)]
+    L.demc_run.argtypes = [_D, ctypes.c_uint64, ctypes.c_int64, _D]
+    L.kep_demc_plan_destroy.argtypes = [_D]
+    L.kep_demc_plan_destroy.restype = None
     L.kep_last_error.restype = ctypes.c_char_p
     L.kep_last_error.argtypes = []
     L.kep_abi_version.restype = ctypes.c_int
     for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
                  "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
-                 "kep_plan_get_info"):
+                 "kep_plan_get_info", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -341,6 +361,82 @@ class RaggedPlan:
         if getattr(self, "_h", None):
             load_library().kep_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DEMC:
+    """Population sampler: differential-evolution MCMC (ter Braak 2006) over
+    exp(-chi2/2), the many-chain application the batched chi-square serves
+    (Sec. 6).  The population x is a float64 GPU tensor (2, 5 n_pl + 1, n_half):
+    two halves, each a set of parameter planes P[n_pl], K, e, omega, M0, then
+    the offset row.  x, chi2 (2, n_half) and n_accept (2, n_half) live on the
+    GPU and are updated in place; generations are reproducible from
+    (seed, generation) and identical whether launched directly
+    (generations) or from the recorded HIP graph (run)."""
+
+    def __init__(self, t, v, sigma, x, eps, seed, t0=0.0, jitter=None, gamma=0.0, jump_every=0, prec="mixed",
+                 opts=None):
+        self.t, self.v, self.sigma = (_dev(a, n, 1) for a, n in ((t, "t"), (v, "v"), (sigma, "sigma")))
+        if not (self.t.numel() == self.v.numel() == self.sigma.numel()):
+            raise ValueError("t, v, sigma must have the same length")
+        self.x = _dev(x, "x", 3)
+        two, d, nh = self.x.shape
+        if two != 2 or d < 6 or (d - 1) % 5 != 0:
+            raise ValueError("x must have shape (2, 5 n_pl + 1, n_half)")
+        self.n_pl, self.n_half, self.d = (d - 1) // 5, nh, d
+        self.device = self.x.device
+        self.eps = _dev(eps, "eps", 1)
+        if self.eps.numel() != d:
+            raise ValueError(f"eps must have d = {d} elements")
+        self.jitter = None if jitter is None else _dev(jitter, "jitter", 2)
+        if self.jitter is not None and tuple(self.jitter.shape) != (2, nh):
+            raise ValueError(f"jitter must have shape (2, {nh})")
+        self.chi2 = torch.empty((2, nh), dtype=torch.float64, device=self.device)
+        self.n_accept = torch.zeros((2, nh), dtype=torch.int64, device=self.device)
+        self.work = torch.empty((d + 1) * nh, dtype=torch.float64, device=self.device)
+        self.prec, self.opts = prec, opts
+        self._obs = KepObs(self.t.data_ptr(), self.v.data_ptr(), self.sigma.data_ptr(), self.t.numel(), float(t0))
+        self._state = KepDemcState(self.x.data_ptr(), self.chi2.data_ptr(), self.n_accept.data_ptr(),
+                                   _ptr(self.jitter), nh, self.n_pl)
+        self._dopt = KepDemcOptions(float(gamma), int(jump_every), 0, int(seed) & (2 ** 64 - 1),
+                                    self.eps.data_ptr())
+        self._plan = None
+        self.chisq()
+
+    def chisq(self):
+        """(Re)compute chi2 of the current population (NaN where a K < 0)."""
+        _check(load_library().demc_chisq(ctypes.byref(self._obs), ctypes.byref(self._state), _prec(self.prec),
+                                         _opts(self.opts), _stream(self.device)))
+        return self.chi2
+
+    def generations(self, gen0, n_gen):
+        """Generations gen0 .. gen0 + n_gen - 1, launched directly."""
+        _check(load_library().demc_generations(ctypes.byref(self._obs), ctypes.byref(self._state),
+                                               ctypes.byref(self._dopt), int(gen0), int(n_gen),
+                                               self.work.data_ptr(), _prec(self.prec), _opts(self.opts),
+                                               _stream(self.device)))
+
+    def run(self, gen0, n_gen):
+        """The same generations replayed from the recorded HIP graph."""
+        L = load_library()
+        if self._plan is None:
+            h = ctypes.c_void_p()
+            _check(L.kep_plan_demc(ctypes.byref(self._obs), ctypes.byref(self._state), ctypes.byref(self._dopt),
+                                   self.work.data_ptr(), _prec(self.prec), _opts(self.opts), _stream(self.device),
+                                   ctypes.byref(h)))
+            self._plan = h
+        _check(L.demc_run(self._plan, int(gen0), int(n_gen), _stream(self.device)))
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            torch.cuda.synchronize(self.device)
+            load_library().kep_demc_plan_destroy(self._plan)
+            self._plan = None
 
     def __del__(self):
         try:

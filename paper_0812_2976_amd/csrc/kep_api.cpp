@@ -616,3 +616,188 @@ kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info)
 void kep_plan_destroy(kep_plan *plan) { plan_free(plan); }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ DE-MC
+struct kep_demc_plan {
+    kep::DemcArgs args;
+    kep::DenseArgs base;
+    kep::Prec prec;
+    kep::LaunchShape shape;
+    uint64_t *d_gen = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+kep_status check_demc(const kep_obs *obs, const kep_demc_state *st, const char *fn)
+{
+    if (!obs || !st) return fail(KEP_ERR_ARG, "%s: obs and state must not be NULL", fn);
+    if (obs->n_obs < 0) return fail(KEP_ERR_ARG, "%s: n_obs = %lld < 0", fn, (long long)obs->n_obs);
+    if (obs->n_obs > 0 && (!obs->t || !obs->v || !obs->sigma))
+        return fail(KEP_ERR_ARG, "%s: obs->t, obs->v and obs->sigma must not be NULL", fn);
+    if (st->n_pl < 1 || st->n_pl > KEP_MAX_PL)
+        return fail(KEP_ERR_SHAPE, "%s: n_pl = %lld outside [1, %d]", fn, (long long)st->n_pl, KEP_MAX_PL);
+    if (st->n_half < 2 || st->n_half > INT32_MAX)
+        return fail(KEP_ERR_SHAPE, "%s: n_half = %lld outside [2, 2^31 - 1]", fn, (long long)st->n_half);
+    if (mul_overflows(st->n_half, 2 * (5 * st->n_pl + 1)) || mul_overflows(st->n_half, obs->n_obs))
+        return fail(KEP_ERR_SHAPE, "%s: population size overflows", fn);
+    if (!st->x || !st->chi2) return fail(KEP_ERR_ARG, "%s: state x and chi2 must not be NULL", fn);
+    return KEP_OK;
+}
+
+kep_status make_demc(const kep_obs *obs, const kep_demc_state *st, const kep_demc_options *d, double *work,
+                     const Opts &o, const char *fn, kep::DemcArgs &a, kep::DenseArgs &base)
+{
+    const int dim = 5 * (int)st->n_pl + 1;
+    a = kep::DemcArgs{};
+    a.x = st->x;
+    a.chi2 = st->chi2;
+    a.n_accept = st->n_accept;
+    a.jitter = st->jitter;
+    a.nh = st->n_half;
+    a.n_pl = (int)st->n_pl;
+    a.d = dim;
+    if (d) {
+        if (!d->eps) return fail(KEP_ERR_ARG, "%s: options->eps must not be NULL", fn);
+        if (!std::isfinite(d->gamma)) return fail(KEP_ERR_ARG, "%s: gamma is not finite", fn);
+        if (d->jump_every < 0) return fail(KEP_ERR_ARG, "%s: jump_every = %d < 0", fn, d->jump_every);
+        if (!work) return fail(KEP_ERR_ARG, "%s: work must not be NULL", fn);
+        a.y = work;
+        a.c_new = work + (int64_t)dim * st->n_half;
+        a.eps = d->eps;
+        a.gamma = d->gamma > 0.0 ? d->gamma : 2.38 / std::sqrt(2.0 * dim);
+        a.jump_every = d->jump_every;
+        a.key0 = (uint32_t)d->seed;
+        a.key1 = (uint32_t)(d->seed >> 32);
+    }
+    base = kep::DenseArgs{};
+    base.t = obs->t;
+    base.v = obs->v;
+    base.sigma = obs->sigma;
+    base.n_obs = obs->n_obs;
+    base.t0 = obs->t0;
+    base.sb = 1;
+    base.fixed_iter = o.fixed_iter;
+    base.max_iter = o.max_iter;
+    return KEP_OK;
+}
+
+void demc_plan_free(kep_demc_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_gen) (void)hipFree(p->d_gen);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+kep_status demc_chisq(const kep_obs *obs, const kep_demc_state *st, kep_prec prec, const kep_options *opts,
+                      void *stream)
+{
+    static const char *fn = "demc_chisq";
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_demc(obs, st, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (kep_status s = check_device(fn)) return s;
+    kep::DemcArgs a;
+    kep::DenseArgs base;
+    if (kep_status s = make_demc(obs, st, nullptr, nullptr, o, fn, a, base)) return s;
+    return launch_status(kep::launch_demc_chisq(a, base, to_prec(prec), o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status demc_generations(const kep_obs *obs, const kep_demc_state *st, const kep_demc_options *dopt,
+                            uint64_t gen0, int64_t n_gen, double *work, kep_prec prec, const kep_options *opts,
+                            void *stream)
+{
+    static const char *fn = "demc_generations";
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_demc(obs, st, fn)) return s;
+    if (!dopt) return fail(KEP_ERR_ARG, "%s: options must not be NULL", fn);
+    if (n_gen < 0) return fail(KEP_ERR_ARG, "%s: n_gen = %lld < 0", fn, (long long)n_gen);
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    kep::DemcArgs a;
+    kep::DenseArgs base;
+    if (kep_status s = make_demc(obs, st, dopt, work, o, fn, a, base)) return s;
+    if (n_gen == 0) return KEP_OK;
+    if (kep_status s = check_device(fn)) return s;
+    for (int64_t k = 0; k < n_gen; ++k) {
+        a.gen = gen0 + (uint64_t)k;
+        if (kep_status s = launch_status(kep::launch_demc_generation(a, base, to_prec(prec), o.shape,
+                                                                     (hipStream_t)stream), fn))
+            return s;
+    }
+    return KEP_OK;
+}
+
+kep_status kep_plan_demc(const kep_obs *obs, const kep_demc_state *st, const kep_demc_options *dopt, double *work,
+                         kep_prec prec, const kep_options *opts, void *stream, kep_demc_plan **out)
+{
+    static const char *fn = "kep_plan_demc";
+    (void)stream;
+    if (!out) return fail(KEP_ERR_ARG, "%s: out must not be NULL", fn);
+    *out = nullptr;
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_demc(obs, st, fn)) return s;
+    if (!dopt) return fail(KEP_ERR_ARG, "%s: options must not be NULL", fn);
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (kep_status s = check_device(fn)) return s;
+    kep_demc_plan *p = new kep_demc_plan();
+    if (kep_status s = make_demc(obs, st, dopt, work, o, fn, p->args, p->base)) {
+        delete p;
+        return s;
+    }
+    p->prec = to_prec(prec);
+    p->shape = o.shape;
+    if (hipMalloc(&p->d_gen, sizeof(uint64_t)) != hipSuccess) {
+        delete p;
+        return fail(KEP_ERR_DEVICE, "%s: hipMalloc of the generation counter failed", fn);
+    }
+    p->args.gen_ptr = p->d_gen;
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        demc_plan_free(p);
+        return fail(KEP_ERR_DEVICE, "%s: hipStreamCreate failed", fn);
+    }
+    hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) err = kep::launch_demc_generation(p->args, p->base, p->prec, p->shape, cap);
+    hipError_t err2 = hipStreamEndCapture(cap, &p->graph);
+    (void)hipStreamDestroy(cap);
+    if (err != hipSuccess || err2 != hipSuccess || !p->graph) {
+        demc_plan_free(p);
+        return fail(KEP_ERR_LAUNCH, "%s: graph capture failed: %s", fn,
+                    hipGetErrorString(err != hipSuccess ? err : err2));
+    }
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
+        demc_plan_free(p);
+        return fail(KEP_ERR_LAUNCH, "%s: graph instantiation failed", fn);
+    }
+    *out = p;
+    return KEP_OK;
+}
+
+kep_status demc_run(kep_demc_plan *plan, uint64_t gen0, int64_t n_gen, void *stream)
+{
+    static const char *fn = "demc_run";
+    if (!plan) return fail(KEP_ERR_ARG, "%s: plan is NULL", fn);
+    if (n_gen < 0) return fail(KEP_ERR_ARG, "%s: n_gen = %lld < 0", fn, (long long)n_gen);
+    if (n_gen == 0) return KEP_OK;
+    if (kep_status s = launch_status(kep::launch_demc_set_gen(plan->d_gen, gen0, (hipStream_t)stream), fn))
+        return s;
+    for (int64_t k = 0; k < n_gen; ++k) {
+        hipError_t err = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+        if (err != hipSuccess) return fail(KEP_ERR_LAUNCH, "%s: graph launch failed: %s", fn, hipGetErrorString(err));
+    }
+    return KEP_OK;
+}
+
+void kep_demc_plan_destroy(kep_demc_plan *plan) { demc_plan_free(plan); }
+
+}  // extern "C"

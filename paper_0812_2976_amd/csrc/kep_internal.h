@@ -42,6 +42,25 @@ struct RaggedArgs {
     int fixed_iter, max_iter;
 };
 
+// Population sampler (DE-MC): two halves of n_half chains, each half laid out
+// [d][nh] with rows P[n_pl], K[n_pl], e[n_pl], omega[n_pl], M0[n_pl], gamma.
+struct DemcArgs {
+    double *x;                // [2][d][nh]
+    double *chi2;             // [2][nh]
+    int64_t *n_accept;        // [2][nh] or null
+    const double *jitter;     // [2][nh] or null
+    double *y;                // proposals [d][nh] (caller's workspace)
+    double *c_new;            // chi-square of the proposals [nh] (workspace)
+    const double *eps;        // [d]
+    int64_t nh;
+    int n_pl, d;
+    double gamma;             // resolved (> 0)
+    int jump_every;
+    uint32_t key0, key1;
+    const uint64_t *gen_ptr;  // generation read from device memory (graphs), or null
+    uint64_t gen;             // generation when gen_ptr is null
+};
+
 constexpr int kMaxSB = 32;
 constexpr int kMaxPl = 8;
 
@@ -62,6 +81,11 @@ hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStrea
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
+// DE-MC: chi-square of the whole population (both halves; NaN where K < 0),
+// one generation (both halves; advances *gen_ptr when set), generation setter.
+hipError_t launch_demc_chisq(DemcArgs a, DenseArgs base, Prec prec, LaunchShape shape, hipStream_t st);
+hipError_t launch_demc_generation(DemcArgs a, DenseArgs base, Prec prec, LaunchShape shape, hipStream_t st);
+hipError_t launch_demc_set_gen(uint64_t *gen, uint64_t value, hipStream_t st);
 int device_cu_count();
 
 }  // namespace kep

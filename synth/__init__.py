@@ -37,7 +37,7 @@ DENSE = {
     "c4": (262144, 4, 256, 0.8, "uniform", True),
 }
 SEEDS = {"c0": 1000, "c1": 1001, "c2": 1002, "c3": 1003, "c4": 1004, "stress": 1102,
-         "kepler": 1200, "kepler_stress": 1201}
+         "kepler": 1200, "kepler_stress": 1201, "demc": 1300}
 
 
 @dataclass
@@ -237,3 +237,25 @@ def kepler_pairs(n: int, seed: Optional[int] = None, stress: bool = False):
         M = np.mod(sgn * mag, TWO_PI)
         e = rng.uniform(0.9, 0.99, size=n)
     return M, e
+
+
+def demc_population(truth: dict, n_half: int, seed: Optional[int] = None, rel_spread: float = 1e-4):
+    """Initial population for the DE-MC sampler, [2, 5 n_pl + 1, n_half]: each
+    half holds parameter planes P, K, e, omega, M0 (planet-major rows) and the
+    offset row, scattered about a truth system by rel_spread (relative, at least
+    0.05 absolute scale for e and the angles), e clipped to [0, 0.95], offset
+    ~ N(0, 0.5 m/s).  Also returns the per-row proposal scale eps [d]
+    (rel_spread / 10 of the same scales)."""
+    rng = np.random.default_rng(SEEDS["demc"] if seed is None else seed)
+    keys = ("P", "K", "e", "w", "M0")
+    tr = {k: np.asarray(truth[k], dtype=np.float64).reshape(-1) for k in keys}
+    n_pl = tr["P"].size
+    x = np.empty((2, 5 * n_pl + 1, n_half))
+    eps = []
+    for a, k in enumerate(keys):
+        scale = np.maximum(np.abs(tr[k]), 0.05)
+        x[:, a * n_pl:(a + 1) * n_pl, :] = tr[k][:, None] + rel_spread * scale[:, None] * rng.normal(size=(2, n_pl, n_half))
+        eps.append(0.1 * rel_spread * scale)
+    x[:, 2 * n_pl:3 * n_pl, :] = np.clip(x[:, 2 * n_pl:3 * n_pl, :], 0.0, 0.95)
+    x[:, 5 * n_pl, :] = rng.normal(scale=0.5, size=(2, n_half))
+    return x, np.concatenate(eps + [np.array([0.1 * rel_spread])])

@@ -97,3 +97,23 @@ def test_python_binding_refuses_cpu_tensors():
     x = torch.zeros(4, dtype=torch.float64)
     with pytest.raises(ValueError, match="GPU"):
         kp.kepler_solve(x, x)
+
+
+def test_demc_argument_errors(lib):
+    obs = kp.KepObs(None, None, None, 0, 0.0)
+    st = kp.KepDemcState(None, None, None, None, 1, 2)
+    code, msg = _status(lib.demc_chisq(ctypes.byref(obs), ctypes.byref(st), 1, None, None), lib)
+    assert code == 2 and "n_half" in msg
+    st.n_half, st.n_pl = 4, 9
+    code, msg = _status(lib.demc_chisq(ctypes.byref(obs), ctypes.byref(st), 1, None, None), lib)
+    assert code == 2 and "n_pl" in msg
+    st.n_pl = 2
+    code, msg = _status(lib.demc_chisq(ctypes.byref(obs), ctypes.byref(st), 1, None, None), lib)
+    assert code == 1 and "x and chi2" in msg
+    code, msg = _status(lib.demc_generations(ctypes.byref(obs), ctypes.byref(st), None, 0, 1, None, 1, None, None), lib)
+    assert code == 1
+    out = ctypes.c_void_p()
+    assert lib.kep_plan_demc(ctypes.byref(obs), ctypes.byref(st), None, None, 1, None, None, None) == 1
+    assert lib.demc_run(None, 0, 1, None) == 1
+    lib.kep_demc_plan_destroy(None)
+    del out

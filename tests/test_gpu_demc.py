@@ -1,0 +1,178 @@
+"""GPU parity of the population sampler (DE-MC over the batched chi-square) with
+the oracle's oracle_demc_run, plus its stationary distribution.
+
+Comparisons:
+  * population chi-square (demc_chisq): binary64 within 1e-12 relative, mixed
+    within 1e-5 max(chi2, 1); NaN where K < 0 on both sides.
+  * generations in binary64: the same accept/reject decision for every chain
+    (the two chi-squares differ by ~1e-13, far inside every margin here), the
+    same acceptance counts, states within 1e-12 of the parameter scale (the
+    proposals are formed in binary64 on both sides; the normal deviates may
+    differ in the last bit through log, sqrt and sin/cos).
+  * mixed precision: decisions equal wherever the oracle's margin
+    (chi2(x) - chi2(y)) - 2 ln u exceeds the chi-square tolerance; a decision
+    inside that band may go either way.
+  * graph replay equals direct launches bit for bit.
+  * the mixed-precision sampler reproduces the Laplace posterior covariance of
+    a high signal-to-noise one-planet problem (as the oracle's pin does).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0812_2976_amd as kp
+from tests import workloads as W
+from tests.test_oracle_demc import _one_planet_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _population(n_pl, nh, n_obs, seed=0, spread=1e-3, jitter=False):
+    """Observations from a truth system (oracle model plus noise) and a population
+    scattered about it."""
+    wl = W.dense("c1", n_sys=4, n_pl=min(n_pl, 4), n_obs=n_obs, seed=seed) if n_obs > 0 else None
+    rng = np.random.default_rng(seed + 100)
+    if wl is None:
+        t = v = sigma = np.empty(0)
+        truth = dict(P=np.full(n_pl, 10.0), K=np.full(n_pl, 20.0), e=np.full(n_pl, 0.3),
+                     w=np.full(n_pl, 1.0), M0=np.full(n_pl, 2.0))
+    else:
+        t, v, sigma = wl.t, wl.v, wl.sigma
+        truth = {k: np.asarray(wl.truth[k], dtype=np.float64).reshape(-1) for k in ("P", "K", "e", "w", "M0")}
+        while truth["P"].size < n_pl:          # more planets than the data's truth: longer periods
+            m = min(truth["P"].size, n_pl - truth["P"].size)
+            for k in truth:
+                extra = truth[k][:m] * (3.1 if k == "P" else 1.0)
+                truth[k] = np.concatenate([truth[k], extra])
+    d = 5 * n_pl + 1
+    x = np.empty((2, d, nh))
+    for a, k in enumerate(("P", "K", "e", "w", "M0")):
+        base = truth[k][:, None]
+        scale = np.maximum(np.abs(base), 0.05)
+        x[:, a * n_pl:(a + 1) * n_pl, :] = base + spread * scale * rng.normal(size=(2, n_pl, nh))
+    x[:, 2 * n_pl:3 * n_pl, :] = np.clip(x[:, 2 * n_pl:3 * n_pl, :], 0.0, 0.95)
+    x[:, 5 * n_pl, :] = rng.normal(scale=0.5, size=(2, nh))
+    eps = np.concatenate([spread * 1e-2 * np.maximum(np.abs(truth[k]), 0.05) for k in ("P", "K", "e", "w", "M0")]
+                         + [[1e-3]])
+    jit = rng.uniform(0.0, 2.0, size=(2, nh)) if jitter else None
+    return t, v, sigma, x, eps, jit
+
+
+def _gpu(a, dev):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _sampler(dev, t, v, sigma, x, eps, jit, seed, prec, **kw):
+    return kp.DEMC(_gpu(t, dev), _gpu(v, dev), _gpu(sigma, dev), _gpu(x, dev), _gpu(eps, dev), seed,
+                   jitter=_gpu(jit, dev), prec=prec, **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_demc_population_chisq(dev, prec):
+    t, v, sigma, x, eps, jit = _population(3, 200, 90, jitter=True)
+    x[1, 3 + 1, 17] = -0.5                                     # one chain with K < 0
+    s = _sampler(dev, t, v, sigma, x, eps, jit, 1, prec)
+    got = s.chi2.cpu().numpy()
+    ref = oracle.demc_init_chisq(t, v, sigma, x, 3, jitter=jit)
+    assert np.isnan(got[1, 17]) and np.isnan(ref[1, 17])
+    ok = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(got), ok)
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert np.max(W.rel_err_chi2(got[ok], ref[ok])) <= tol
+
+
+@pytest.mark.parametrize("case", [
+    dict(n_pl=2, nh=256, n_obs=64, n_gen=8, jump_every=5),
+    dict(n_pl=8, nh=40, n_obs=30, n_gen=3, jump_every=0),        # d = 41: odd row count
+    dict(n_pl=1, nh=2, n_obs=50, n_gen=6, jump_every=2),         # smallest population
+    dict(n_pl=3, nh=64, n_obs=0, n_gen=4, jump_every=0),         # no observations: flat target
+    dict(n_pl=2, nh=300, n_obs=100, n_gen=4, jump_every=0, jitter=True),
+])
+def test_demc_generations_fp64_match_oracle(dev, case):
+    t, v, sigma, x, eps, jit = _population(case["n_pl"], case["nh"], case["n_obs"], seed=case["nh"],
+                                           jitter=case.get("jitter", False))
+    seed = 0x1234_5678_9ABC_DEF0
+    s = _sampler(dev, t, v, sigma, x, eps, jit, seed, "fp64", jump_every=case["jump_every"])
+    chi0 = oracle.demc_init_chisq(t, v, sigma, x, case["n_pl"], jitter=jit)
+    xo, co, ao = oracle.demc_run(t, v, sigma, x, chi0, case["n_pl"], eps, seed, 17, case["n_gen"], jitter=jit,
+                                 jump_every=case["jump_every"])
+    s.generations(17, case["n_gen"])
+    xg, cg, ag = s.x.cpu().numpy(), s.chi2.cpu().numpy(), s.n_accept.cpu().numpy()
+    print(f"[demc fp64 {case}] acceptance {ag.sum() / ag.size / case['n_gen']:.3f}", flush=True)
+    assert np.array_equal(ag, ao)
+    scale = np.max(np.abs(x), axis=(0, 2))[None, :, None] + eps[None, :, None]
+    assert np.max(np.abs(xg - xo) / scale) <= 1e-12
+    assert np.max(W.rel_err_chi2(cg, co)) <= 1e-11
+
+
+def test_demc_mixed_one_generation_matches_oracle(dev):
+    n_pl, nh = 4, 512
+    t, v, sigma, x, eps, jit = _population(n_pl, nh, 256, seed=5, spread=3e-4)
+    seed = 77
+    s = _sampler(dev, t, v, sigma, x, eps, jit, seed, "mixed")
+    chi0 = oracle.demc_init_chisq(t, v, sigma, x, n_pl)
+    xo, co, ao, mg = oracle.demc_run(t, v, sigma, x, chi0, n_pl, eps, seed, 0, 1, margin=True)
+    s.generations(0, 1)
+    ag = s.n_accept.cpu().numpy()
+    # margin error: the tolerances of chi2(x) and of chi2(y) <= chi2(x) + 2 |ln u| (ln u >= -37)
+    band = 1e-5 * (2 * np.maximum(np.abs(chi0), 1.0) + 80.0)
+    sure = np.abs(mg) > band
+    print(f"[demc mixed] acceptance {ag.mean():.3f}; decisions inside the tolerance band: {(~sure).sum()}",
+          flush=True)
+    assert np.array_equal(ag[0][sure[0]], ao[0][sure[0]])
+    if np.all(sure[0]):             # half 1 draws its differences from half 0
+        assert np.array_equal(ag[1][sure[1]], ao[1][sure[1]])
+        xg = s.x.cpu().numpy()
+        same = np.broadcast_to(sure[:, None, :], xg.shape)
+        scale = np.max(np.abs(x), axis=(0, 2))[None, :, None] + eps[None, :, None]
+        assert np.max(np.abs(xg - xo)[same] / np.broadcast_to(scale, xg.shape)[same]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_demc_graph_replay_equals_direct(dev, prec):
+    t, v, sigma, x, eps, jit = _population(2, 1000, 128, seed=9, jitter=True)
+    a = _sampler(dev, t, v, sigma, x, eps, jit, 5, prec, jump_every=3)
+    b = _sampler(dev, t, v, sigma, x, eps, jit, 5, prec, jump_every=3)
+    a.generations(100, 12)
+    b.run(100, 5)
+    torch.cuda.synchronize()
+    b.run(105, 7)                   # a second replay series continues the generation count
+    torch.cuda.synchronize()
+    assert torch.equal(a.x, b.x) and torch.equal(a.chi2, b.chi2) and torch.equal(a.n_accept, b.n_accept)
+    assert a.n_accept.sum().item() > 0
+    b.close()
+
+
+def test_demc_mixed_samples_the_laplace_posterior(dev):
+    rng, t, t0, sigma, theta, v, C = _one_planet_problem()
+    sd = np.sqrt(np.diag(C))
+    nh = 1024
+    x = rng.multivariate_normal(theta, C, size=(2, nh)).transpose(0, 2, 1).copy()
+    s = kp.DEMC(_gpu(t, dev), _gpu(v, dev), _gpu(sigma, dev), _gpu(x, dev), _gpu(1e-3 * sd, dev), 2024, t0=t0,
+                jump_every=10, prec="mixed")
+    samples = []
+    for k in range(60):
+        s.run(5 * k, 5)
+        if k >= 10:
+            samples.append(s.x.transpose(1, 2).reshape(-1, 6).cpu().numpy())
+    S = np.concatenate(samples)
+    ratio = np.var(S, axis=0) / np.diag(C)
+    Cs = np.cov(S.T)
+    R = Cs / np.sqrt(np.outer(np.diag(Cs), np.diag(Cs)))
+    R0 = C / np.outer(sd, sd)
+    rate = s.n_accept.sum().item() / (2 * nh * 300)
+    print(f"[demc posterior] acceptance {rate:.3f}; variance ratios {np.round(ratio, 3)}; "
+          f"max |dcorr| {np.max(np.abs(R - R0)):.3f}", flush=True)
+    assert np.all((ratio > 0.9) & (ratio < 1.1))
+    assert np.max(np.abs(R - R0)) < 0.05
+    assert np.all(np.abs(S.mean(0) - theta) < 0.2 * sd)
+    s.close()
+
+
+def test_demc_argument_errors(dev):
+    t, v, sigma, x, eps, jit = _population(1, 2, 10)
+    with pytest.raises(ValueError):
+        _sampler(dev, t, v, sigma, x, eps[:-1], jit, 1, "mixed")
+    with pytest.raises(kp.KeplerError):
+        _sampler(dev, t, v, sigma, x[:, :, :1], eps, jit, 1, "mixed")

@@ -132,3 +132,15 @@ def test_demc_stays_in_prior_support():
     assert np.all(x1[:, 1, :] >= 0.0) and np.all(x1[:, 2, :] >= 0.0) and np.all(x1[:, 2, :] < 1.0)
     assert np.all(x1[:, 0, :] > 0.0)
     assert 0 < acc.sum() < 2 * nh * 60                      # some rejected, some accepted
+
+
+def test_demc_margin_trace_matches_decisions():
+    """The recorded margin (chi2(x) - chi2(y)) - 2 ln u is positive exactly for
+    the chains that moved."""
+    rng, t, t0, sigma, theta, v, C = _one_planet_problem()
+    x = rng.multivariate_normal(theta, 4 * C, size=(2, 16)).transpose(0, 2, 1).copy()
+    chi = oracle.demc_init_chisq(t, v, sigma, x, 1, t0=t0)
+    x1, _, acc, mg = oracle.demc_run(t, v, sigma, x, chi, 1, 1e-3 * np.sqrt(np.diag(C)), seed=3, gen0=0, n_gen=1,
+                                     t0=t0, margin=True)
+    moved = np.any(x1 != x, axis=1)
+    assert np.array_equal(moved, mg > 0) and np.array_equal(acc == 1, moved)
