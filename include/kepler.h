@@ -264,19 +264,21 @@ typedef struct kep_demc_options {
 kep_status demc_chisq(const kep_obs *obs, const kep_demc_state *state, kep_prec prec,
                       const kep_options *opts, void *stream);
 
-/* Generations gen0 .. gen0 + n_gen - 1, launched directly (7 launches per
-   generation).  work: device workspace of (d + 1) * n_half doubles (proposals
-   and their chi-square), owned by the caller.  Does not allocate or
+/* Generations gen0 .. gen0 + n_gen - 1, launched directly (one fused
+   propose / chi-square / accept kernel per half).  work: device workspace of
+   (d + 1) * n_half doubles, owned by the caller; it receives the last half's
+   proposals [d][n_half] and their chi-square [n_half].  Does not allocate or
    synchronise.  prec selects the chi-square kernel (the sampler's own
    arithmetic is binary64 in both). */
 kep_status demc_generations(const kep_obs *obs, const kep_demc_state *state, const kep_demc_options *options,
                             uint64_t gen0, int64_t n_gen, double *work, kep_prec prec,
                             const kep_options *opts, void *stream);
 
-/* The same generation recorded once as a HIP graph whose kernels read the
-   generation number from a device counter that the graph's last node
-   advances; demc_run sets the counter to gen0 and launches the graph n_gen
-   times.  Results equal demc_generations bit for bit.  kep_plan_demc
+/* The same generations recorded as HIP graphs (one of a single generation,
+   one of eight) whose kernels read the generation number from a device
+   counter that each generation's last node advances; demc_run sets the
+   counter to gen0 and replays the graphs until n_gen generations have run.
+   Results equal demc_generations bit for bit.  kep_plan_demc
    allocates (the counter) and keeps every pointer of state, options and work;
    calls on one plan must not overlap; synchronise before destroying it. */
 typedef struct kep_demc_plan kep_demc_plan;

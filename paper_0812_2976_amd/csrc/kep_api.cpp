@@ -624,9 +624,13 @@ struct kep_demc_plan {
     kep::Prec prec;
     kep::LaunchShape shape;
     uint64_t *d_gen = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr, graph_many = nullptr;
+    hipGraphExec_t exec = nullptr, exec_many = nullptr;   // one generation / kDemcGraphGens generations
 };
+
+// generations recorded in the plan's larger graph (one graph launch per this
+// many generations; the remainder replays the one-generation graph)
+constexpr int kDemcGraphGens = 8;
 
 namespace {
 
@@ -688,6 +692,8 @@ void demc_plan_free(kep_demc_plan *p)
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->exec_many) (void)hipGraphExecDestroy(p->exec_many);
+    if (p->graph_many) (void)hipGraphDestroy(p->graph_many);
     if (p->d_gen) (void)hipFree(p->d_gen);
     delete p;
 }
@@ -761,23 +767,28 @@ kep_status kep_plan_demc(const kep_obs *obs, const kep_demc_state *st, const kep
         return fail(KEP_ERR_DEVICE, "%s: hipMalloc of the generation counter failed", fn);
     }
     p->args.gen_ptr = p->d_gen;
-    hipStream_t cap = nullptr;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
-        demc_plan_free(p);
-        return fail(KEP_ERR_DEVICE, "%s: hipStreamCreate failed", fn);
-    }
-    hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (err == hipSuccess) err = kep::launch_demc_generation(p->args, p->base, p->prec, p->shape, cap);
-    hipError_t err2 = hipStreamEndCapture(cap, &p->graph);
-    (void)hipStreamDestroy(cap);
-    if (err != hipSuccess || err2 != hipSuccess || !p->graph) {
-        demc_plan_free(p);
-        return fail(KEP_ERR_LAUNCH, "%s: graph capture failed: %s", fn,
-                    hipGetErrorString(err != hipSuccess ? err : err2));
-    }
-    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) {
-        demc_plan_free(p);
-        return fail(KEP_ERR_LAUNCH, "%s: graph instantiation failed", fn);
+    for (int many = 0; many < 2; ++many) {
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+            demc_plan_free(p);
+            return fail(KEP_ERR_DEVICE, "%s: hipStreamCreate failed", fn);
+        }
+        hipGraph_t &graph = many ? p->graph_many : p->graph;
+        hipGraphExec_t &exec = many ? p->exec_many : p->exec;
+        hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        for (int k = 0; k < (many ? kDemcGraphGens : 1) && err == hipSuccess; ++k)
+            err = kep::launch_demc_generation(p->args, p->base, p->prec, p->shape, cap);
+        hipError_t err2 = hipStreamEndCapture(cap, &graph);
+        (void)hipStreamDestroy(cap);
+        if (err != hipSuccess || err2 != hipSuccess || !graph) {
+            demc_plan_free(p);
+            return fail(KEP_ERR_LAUNCH, "%s: graph capture failed: %s", fn,
+                        hipGetErrorString(err != hipSuccess ? err : err2));
+        }
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            demc_plan_free(p);
+            return fail(KEP_ERR_LAUNCH, "%s: graph instantiation failed", fn);
+        }
     }
     *out = p;
     return KEP_OK;
@@ -791,9 +802,11 @@ kep_status demc_run(kep_demc_plan *plan, uint64_t gen0, int64_t n_gen, void *str
     if (n_gen == 0) return KEP_OK;
     if (kep_status s = launch_status(kep::launch_demc_set_gen(plan->d_gen, gen0, (hipStream_t)stream), fn))
         return s;
-    for (int64_t k = 0; k < n_gen; ++k) {
-        hipError_t err = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    for (int64_t k = 0; k < n_gen;) {
+        const bool many = n_gen - k >= kDemcGraphGens;
+        hipError_t err = hipGraphLaunch(many ? plan->exec_many : plan->exec, (hipStream_t)stream);
         if (err != hipSuccess) return fail(KEP_ERR_LAUNCH, "%s: graph launch failed: %s", fn, hipGetErrorString(err));
+        k += many ? kDemcGraphGens : 1;
     }
     return KEP_OK;
 }

@@ -86,6 +86,8 @@ int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 hipError_t launch_demc_chisq(DemcArgs a, DenseArgs base, Prec prec, LaunchShape shape, hipStream_t st);
 hipError_t launch_demc_generation(DemcArgs a, DenseArgs base, Prec prec, LaunchShape shape, hipStream_t st);
 hipError_t launch_demc_set_gen(uint64_t *gen, uint64_t value, hipStream_t st);
+// one fused half-step (propose, chi-square, accept) of half h
+hipError_t launch_demc_half(DemcArgs m, DenseArgs base, Prec prec, int h, LaunchShape shape, hipStream_t st);
 int device_cu_count();
 
 }  // namespace kep

@@ -134,10 +134,11 @@ def test_demc_graph_replay_equals_direct(dev, prec):
     t, v, sigma, x, eps, jit = _population(2, 1000, 128, seed=9, jitter=True)
     a = _sampler(dev, t, v, sigma, x, eps, jit, 5, prec, jump_every=3)
     b = _sampler(dev, t, v, sigma, x, eps, jit, 5, prec, jump_every=3)
-    a.generations(100, 12)
+    a.generations(100, 31)
     b.run(100, 5)
     torch.cuda.synchronize()
     b.run(105, 7)                   # a second replay series continues the generation count
+    b.run(112, 19)                  # two replays of the eight-generation graph, three single ones
     torch.cuda.synchronize()
     assert torch.equal(a.x, b.x) and torch.equal(a.chi2, b.chi2) and torch.equal(a.n_accept, b.n_accept)
     assert a.n_accept.sum().item() > 0
