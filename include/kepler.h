@@ -275,9 +275,10 @@ kep_status demc_generations(const kep_obs *obs, const kep_demc_state *state, con
                             const kep_options *opts, void *stream);
 
 /* The same generations recorded as HIP graphs (one of a single generation,
-   one of eight) whose kernels read the generation number from a device
-   counter that each generation's last node advances; demc_run sets the
-   counter to gen0 and replays the graphs until n_gen generations have run.
+   one of eight): generation k of a graph reads its number as a device
+   counter plus k, and the graph's last node advances the counter by the
+   graph's generation count; demc_run sets the counter to gen0 and replays the
+   graphs until n_gen generations have run.
    Results equal demc_generations bit for bit.  kep_plan_demc
    allocates (the counter) and keeps every pointer of state, options and work;
    calls on one plan must not overlap; synchronise before destroying it. */

@@ -775,9 +775,15 @@ kep_status kep_plan_demc(const kep_obs *obs, const kep_demc_state *st, const kep
         }
         hipGraph_t &graph = many ? p->graph_many : p->graph;
         hipGraphExec_t &exec = many ? p->exec_many : p->exec;
+        // generation k of the graph reads counter + k; one node advances the counter
+        const int ng = many ? kDemcGraphGens : 1;
         hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        for (int k = 0; k < (many ? kDemcGraphGens : 1) && err == hipSuccess; ++k)
-            err = kep::launch_demc_generation(p->args, p->base, p->prec, p->shape, cap);
+        for (int k = 0; k < ng && err == hipSuccess; ++k) {
+            kep::DemcArgs a = p->args;
+            a.gen = (uint64_t)k;
+            err = kep::launch_demc_generation(a, p->base, p->prec, p->shape, cap);
+        }
+        if (err == hipSuccess) err = kep::launch_demc_advance(p->d_gen, (uint64_t)ng, cap);
         hipError_t err2 = hipStreamEndCapture(cap, &graph);
         (void)hipStreamDestroy(cap);
         if (err != hipSuccess || err2 != hipSuccess || !graph) {

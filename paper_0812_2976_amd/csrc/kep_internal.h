@@ -57,8 +57,8 @@ struct DemcArgs {
     double gamma;             // resolved (> 0)
     int jump_every;
     uint32_t key0, key1;
-    const uint64_t *gen_ptr;  // generation read from device memory (graphs), or null
-    uint64_t gen;             // generation when gen_ptr is null
+    const uint64_t *gen_ptr;  // generation counter in device memory (graphs), or null
+    uint64_t gen;             // the generation (gen_ptr null) or its offset from *gen_ptr
 };
 
 constexpr int kMaxSB = 32;
@@ -82,10 +82,12 @@ hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipSt
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 // DE-MC: chi-square of the whole population (both halves; NaN where K < 0),
-// one generation (both halves; advances *gen_ptr when set), generation setter.
+// one generation (both halves), the device generation counter's setter and
+// increment.
 hipError_t launch_demc_chisq(DemcArgs a, DenseArgs base, Prec prec, LaunchShape shape, hipStream_t st);
 hipError_t launch_demc_generation(DemcArgs a, DenseArgs base, Prec prec, LaunchShape shape, hipStream_t st);
 hipError_t launch_demc_set_gen(uint64_t *gen, uint64_t value, hipStream_t st);
+hipError_t launch_demc_advance(uint64_t *gen, uint64_t inc, hipStream_t st);
 // one fused half-step (propose, chi-square, accept) of half h
 hipError_t launch_demc_half(DemcArgs m, DenseArgs base, Prec prec, int h, LaunchShape shape, hipStream_t st);
 int device_cu_count();

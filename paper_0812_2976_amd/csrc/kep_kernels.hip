@@ -14,284 +14,9 @@
 
 #include "kep_device.h"
 #include "kep_internal.h"
-#include "kep_philox.h"
+#include "kep_policy.h"
 
 namespace kep {
-
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ bool planet_ok(double P, double K, double e, double w, double M0)
-{
-    return isfinite(P) && P > 0.0 && isfinite(K) && isfinite(e) && e >= 0.0 && e < 1.0 &&
-           isfinite(w) && isfinite(M0);
-}
-
-// ------------------------------------------------------------------ mixed
-struct RecMixed {          // 64 bytes, one per (system, planet)
-    Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
-    Ecc32 k;               // e, 1 - e, e/2, e/6
-    float A, B;            // K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
-    int niter, check;      // Danby steps (0: convergence test); 1 if fixed by the caller
-};
-
-struct ObsMixed {
-    double tt;   // t - t0
-    double v;    // observed velocity
-    float s2;    // sigma^2
-    float w;     // 1 / sigma^2 (no jitter)
-    bool in;     // lane holds a real observation
-    bool ok;     // t, v, sigma finite and sigma >= 0
-};
-
-struct PolMixed {
-    using Rec = RecMixed;
-    using Obs = ObsMixed;
-    struct ModelAcc { Kahan32 k; };
-    using ChiAcc = Kahan32;
-
-    static __device__ __forceinline__ bool setup(const DenseArgs &a, double P, double K, double e, double w,
-                                                 double M0, Rec &r)
-    {
-        bool ok = planet_ok(P, K, e, w, M0);
-        if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
-        r.ph = make_phase64(P, M0);
-        r.k = make_ecc32(e);
-        const double b2 = (1.0 - e) * (1.0 + e);
-        double sw, cw;
-        sincos(w, &sw, &cw);
-        r.A = (float)(K * b2 * cw);
-        r.B = (float)(-K * sqrt(b2) * sw);
-        r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e);
-        r.check = a.fixed_iter > 0 ? 1 : 0;
-        return ok;
-    }
-
-    static __device__ __forceinline__ void load_obs(const DenseArgs &a, int64_t k, Obs &o)
-    {
-        o.in = k < a.n_obs;
-        double t = o.in ? a.t[k] : a.t0;
-        double v = o.in ? a.v[k] : 0.0;
-        double s = o.in ? a.sigma[k] : 1.0;
-        o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
-        o.tt = t - a.t0;
-        o.v = v;
-        o.s2 = (float)(s * s);
-        o.w = (float)(1.0 / (s * s));
-    }
-
-    static __device__ __forceinline__ void load_obs_model(const DenseArgs &a, int64_t k, Obs &o)
-    {
-        o.in = k < a.n_obs;
-        double t = o.in ? a.t[k] : a.t0;
-        o.ok = isfinite(t);
-        o.tt = t - a.t0;
-        o.v = 0.0;
-        o.s2 = 1.0f;
-        o.w = 1.0f;
-    }
-
-    template <int NCH>
-    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
-                                                      int max_iter, int /*fixed: already in rr.niter*/)
-    {
-        // rr comes from an LDS broadcast: every lane holds the same values
-        const Phase64 ph = rr.ph;
-        const Ecc32 k = rr.k;
-        const float A = rr.A, B = rr.B;
-        const int niter = uniform_int(rr.niter);
-        float M[NCH], E[NCH], st[NCH];
-        SinCos32 sc[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            M[c] = mean_anomaly32(o[c].tt, ph);
-            E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
-        }
-        bool check = uniform_int(rr.check) != 0;
-        if (niter > 0) {
-            for (int it = 0; it < niter - 1; ++it) {   // steps before the last: hardware sin/cos
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k);
-            }
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
-        } else {
-            check = true;
-            const int n = max_iter > 0 ? max_iter : 1;
-            for (int it = 0; it < n; ++it) {           // convergence-tested (beyond the schedule),
-                bool conv = true;                      // clamped to the bracket [M - e, M + e]
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    st[c] = danby_step32<true>(E[c], M[c], k, M[c] - k.e, M[c] + k.e, sc[c]);
-                    conv = conv && (fabsf(st[c]) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
-                }
-                if (__all(conv)) break;
-            }
-        }
-        if (check) {   // a last step the schedule does not bound: evaluate afresh where it is large
-            bool large = false;
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) large = large || fabsf(st[c]) > 0.0625f;
-            if (__any(large)) {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    sc[c] = sincos32(E[c]);
-                    st[c] = 0.0f;
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            float s = sc[c].s, omc = sc[c].omc;
-            rotate32(s, omc, st[c]);
-            float D = fmaf(k.e, omc, k.ome);           // 1 - e cos E
-            float num = fmaf(B, s, fmaf(-A, omc, A));  // A cos E + B sin E
-            m[c].k.add(num * rcp32(D));
-        }
-    }
-
-    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.k.init(); }
-    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.k.value(); }
-
-    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x.init(); }
-    // One observation's contribution; returns false if the weight is invalid.
-    static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
-                                                   double jit, bool has_jit)
-    {
-        float r = (float)(((double)m.k.s - (double)m.k.c + gam) - o.v);   // residual formed in binary64
-        float w = o.w;
-        bool okw = true;
-        if (has_jit) {
-            float var = o.s2 + (float)(jit * jit);
-            okw = var > 0.0f;
-            w = rcp32(var);
-        } else {
-            okw = o.s2 > 0.0f;
-        }
-        x.add(w * r * r);
-        return okw;
-    }
-    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x.value(); }
-};
-
-// ------------------------------------------------------------------ binary64
-struct Rec64 {            // 64 bytes
-    double P, M0, e, K, b, cw, sw;
-    int pad0, pad1;
-};
-
-struct Obs64 {
-    double tt, v, s2, w;
-    bool in, ok;
-};
-
-struct Pol64 {
-    using Rec = Rec64;
-    using Obs = Obs64;
-    struct ModelAcc { double s; };
-    using ChiAcc = double;
-
-    static __device__ __forceinline__ bool setup(const DenseArgs &, double P, double K, double e, double w,
-                                                 double M0, Rec &r)
-    {
-        bool ok = planet_ok(P, K, e, w, M0);
-        if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
-        r.P = P;
-        r.M0 = M0;
-        r.e = e;
-        r.K = K;
-        r.b = sqrt((1.0 - e) * (1.0 + e));
-        sincos(w, &r.sw, &r.cw);
-        r.pad0 = r.pad1 = 0;
-        return ok;
-    }
-
-    static __device__ __forceinline__ void load_obs(const DenseArgs &a, int64_t k, Obs &o)
-    {
-        o.in = k < a.n_obs;
-        double t = o.in ? a.t[k] : a.t0;
-        double v = o.in ? a.v[k] : 0.0;
-        double s = o.in ? a.sigma[k] : 1.0;
-        o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
-        o.tt = t - a.t0;
-        o.v = v;
-        o.s2 = s * s;
-        o.w = 1.0 / (s * s);
-    }
-
-    static __device__ __forceinline__ void load_obs_model(const DenseArgs &a, int64_t k, Obs &o)
-    {
-        o.in = k < a.n_obs;
-        double t = o.in ? a.t[k] : a.t0;
-        o.ok = isfinite(t);
-        o.tt = t - a.t0;
-        o.v = 0.0;
-        o.s2 = 1.0;
-        o.w = 1.0;
-    }
-
-    // Plain binary64 (the paper's double-precision variant): IEEE quotient
-    // (t - t0)/P, exact fraction, M = 2 pi frac + M0 in [0, 2 pi), Danby's
-    // iteration, then v = K b (b cos w cos E - sin w sin E) / (1 - e cos E).
-    template <int NCH>
-    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
-                                                      int max_iter, int fixed)
-    {
-        const double P = uniform_double(rr.P), M0 = uniform_double(rr.M0), e = uniform_double(rr.e);
-        const double K = uniform_double(rr.K), b = uniform_double(rr.b);
-        const double cw = uniform_double(rr.cw), sw = uniform_double(rr.sw);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            double q = o[c].tt / P;
-            double phi = q - floor(q);
-            double M = fma(kTwoPi, phi, M0);
-            M = M - kTwoPi * floor(M * kInvTwoPi);
-            double E = kepler64(M, e, M < kPi ? 1.0 : -1.0, fixed, max_iter);
-            double s, cE;
-            sincos(E, &s, &cE);
-            m[c].s += K * b * (b * cw * cE - sw * s) / (1.0 - e * cE);
-        }
-    }
-
-    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.s = 0.0; }
-    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.s; }
-    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x = 0.0; }
-    static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
-                                                   double jit, bool has_jit)
-    {
-        double r = m.s + gam - o.v;
-        double w = o.w;
-        bool okw = o.s2 > 0.0;
-        if (has_jit) {
-            double var = o.s2 + jit * jit;
-            okw = var > 0.0;
-            w = 1.0 / var;
-        }
-        x = fma(w * r, r, x);
-        return okw;
-    }
-    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x; }
-};
-
-// Iteration count of the plain binary64 kernel: fixed_iter > 0 as given,
-// 0 -> the fixed 30 steps of the plain kernel, < 0 -> schedule + convergence test.
-__device__ __forceinline__ int fixed64(int fixed_iter) { return fixed_iter > 0 ? fixed_iter : (fixed_iter == 0 ? 30 : 0); }
-
-template <class Pol, int NCH>
-__device__ __forceinline__ void pol_add_planet(const typename Pol::Rec &r, const typename Pol::Obs (&o)[NCH],
-                                               typename Pol::ModelAcc (&m)[NCH], const DenseArgs &a)
-{
-    Pol::template add_planet<NCH>(r, o, m, a.max_iter, fixed64(a.fixed_iter));
-}
-
-// Dense kernel.  MODE kChi2: chi-square per system; kModel: model velocities
-// [n_sys][n_obs]; kPlanets: every planet's velocity [n_pl][n_sys][n_obs] in
-// binary32 (the paper's separate-function form, Sec. 4.4, first implementation).
-enum { kChi2 = 0, kModel = 1, kPlanets = 2 };
 
 template <class Pol, int NCH, int MODE>
 
@@ -762,229 +487,6 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
         for (int i = 0; i < 5 * NPL + 1; ++i) a.grad[(int64_t)i * a.n_sys + sys] = ok ? gacc[i] : nan;
         if (NLL) a.grad[(int64_t)(5 * NPL + 1) * a.n_sys + sys] = ok ? 2.0 * jit * (sum_w - sum_wr2) : nan;
     }
-}
-
-// ------------------------------------------------------------------ DE-MC
-// One half-step of the population sampler, fused: for a batch of sb chains
-// of half h the wave
-//   A. lanes over chains: draw 0 gives r1 != r2 (other half) and u;
-//   B. lanes over (chain, pair of rows): two normals z and the proposal rows
-//      y_r = x_ir + gam (x_r1,r - x_r2,r) + eps_r z_r;
-//   C. lanes over (chain, planet): the planet records, as the dense kernel's
-//      setup does from parameter planes;
-//   D. lanes over chains: domain and prior-support flags;
-//   then evaluates each proposal's chi-square with the lanes over
-//   observations, exactly as the dense chi-square kernel does, and
-//   E. lanes over chains: accepts iff 2 ln u < chi2(x) - chi2(y) and K >= 0,
-//      copying y into the chain.
-// Everything one lane hands to another goes through the wave's slice of LDS;
-// the half being updated is read and written only by the lane that owns the
-// chain in phase B / E, and the other half is only read.  The proposals and
-// their chi-square are also written to the workspace (m.y, m.c_new).
-__host__ __device__ inline size_t demc_lds_per_wave(int sb, int n_pl, int d, size_t rec_bytes)
-{
-    size_t b = (size_t)sb * n_pl * rec_bytes          // planet records
-               + (size_t)sb * d * sizeof(double)       // proposals
-               + (size_t)sb * 2 * sizeof(double)       // u, chi2 of the proposal
-               + (size_t)sb * 2 * sizeof(uint32_t)     // r1, r2
-               + (size_t)sb * n_pl * sizeof(int)       // per-planet domain flag
-               + (size_t)sb * 2 * sizeof(int);         // per-chain domain and support flags
-    return (b + 15) & ~(size_t)15;
-}
-
-template <class Pol, int NCH>
-__global__ void __launch_bounds__(256) k_demc_half(DenseArgs a, DemcArgs m, int h)
-{
-    using Rec = typename Pol::Rec;
-    using Obs = typename Pol::Obs;
-    using ModelAcc = typename Pol::ModelAcc;
-    extern __shared__ __align__(16) unsigned char smem[];
-
-    const int lane = __lane_id();
-    const int wpb = blockDim.x >> 6;
-    const int wib = uniform_int(threadIdx.x >> 6);
-    const int sb = a.sb, npl = a.n_pl, d = m.d;
-    unsigned char *mine = smem + (size_t)wib * demc_lds_per_wave(sb, npl, d, sizeof(Rec));
-    Rec *recs = reinterpret_cast<Rec *>(mine);
-    double *y_l = reinterpret_cast<double *>(mine + (size_t)sb * npl * sizeof(Rec));
-    double *u_l = y_l + (size_t)sb * d;
-    double *cnew_l = u_l + sb;
-    uint32_t *r12_l = reinterpret_cast<uint32_t *>(cnew_l + sb);
-    int *okpl_l = reinterpret_cast<int *>(r12_l + 2 * sb);
-    int *bad_l = okpl_l + sb * npl;
-    int *supp_l = bad_l + sb;
-
-    const int64_t nh = m.nh;
-    const uint64_t g = m.gen_ptr ? *m.gen_ptr : m.gen;
-    const double gde = (m.jump_every > 0 && (g + 1) % (uint64_t)m.jump_every == 0) ? 1.0 : m.gamma;
-    double *xh = m.x + (int64_t)h * d * nh;
-    const double *xo = m.x + (int64_t)(1 - h) * d * nh;
-    const int ndraw = (d + 1) / 2;
-
-    const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
-    const int64_t n_waves = (int64_t)gridDim.x * wpb;
-    const int64_t n_batches = (nh + sb - 1) / sb;
-    const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
-    const bool has_jit = a.jitter != nullptr;
-
-    Obs o[NCH];
-    auto load_group = [&](int gi) {
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) Pol::load_obs(a, (int64_t)gi * 64 * NCH + c * 64 + lane, o[c]);
-    };
-    if (n_groups <= 1) load_group(0);
-
-    for (int64_t bt = gw; bt < n_batches; bt += n_waves) {
-        const int64_t s0 = bt * sb;
-        const int nb = (int)min((int64_t)sb, nh - s0);
-        wave_sync_lds();
-        for (int c = lane; c < nb; c += 64) {                                   // A
-            const U4 w = demc_draw(m.key0, m.key1, h, (uint32_t)(s0 + c), 0u, g);
-            const uint32_t r1 = below(w.w0, (uint32_t)nh);
-            uint32_t r2 = below(w.w1, (uint32_t)nh - 1u);
-            if (r2 >= r1) r2 += 1u;
-            r12_l[2 * c] = r1;
-            r12_l[2 * c + 1] = r2;
-            u_l[c] = unit53(w.w2, w.w3);
-        }
-        wave_sync_lds();
-        for (int q = lane; q < nb * ndraw; q += 64) {                           // B
-            const int c = q / ndraw, p = q - c * ndraw, r = 2 * p;
-            const int64_t i = s0 + c;
-            const uint32_t r1 = r12_l[2 * c], r2 = r12_l[2 * c + 1];
-            const U4 w = demc_draw(m.key0, m.key1, h, (uint32_t)i, (uint32_t)(1 + p), g);
-            const double rho = sqrt(-2.0 * log(unit53(w.w0, w.w1)));
-            double sn, cs;
-            sincos(kTwoPi * unit53(w.w2, w.w3), &sn, &cs);
-            {
-                // rounded term by term, as written (no contraction)
-#pragma clang fp contract(off)
-                const int64_t o0 = (int64_t)r * nh;
-                const double y0 = xh[o0 + i] + gde * (xo[o0 + r1] - xo[o0 + r2]) + m.eps[r] * (rho * cs);
-                y_l[c * d + r] = y0;
-                m.y[o0 + i] = y0;
-                if (r + 1 < d) {
-                    const int64_t o1 = o0 + nh;
-                    const double y1 = xh[o1 + i] + gde * (xo[o1 + r1] - xo[o1 + r2]) + m.eps[r + 1] * (rho * sn);
-                    y_l[c * d + r + 1] = y1;
-                    m.y[o1 + i] = y1;
-                }
-            }
-        }
-        wave_sync_lds();
-        for (int q = lane; q < nb * npl; q += 64) {                             // C
-            const int c = q / npl, j = q - c * npl;
-            const double *yc = y_l + c * d;
-            Rec rr;
-            okpl_l[q] = Pol::setup(a, yc[j], yc[npl + j], yc[2 * npl + j], yc[3 * npl + j], yc[4 * npl + j], rr)
-                            ? 1 : 0;
-            recs[q] = rr;
-        }
-        wave_sync_lds();
-        for (int c = lane; c < nb; c += 64) {                                   // D
-            const double *yc = y_l + c * d;
-            bool ok = isfinite(a.t0) && isfinite(yc[5 * npl]);
-            bool supp = true;
-            for (int j = 0; j < npl; ++j) {
-                ok = ok && okpl_l[c * npl + j] != 0;
-                supp = supp && yc[npl + j] >= 0.0;
-            }
-            if (has_jit) ok = ok && isfinite(a.jitter[s0 + c]) && a.jitter[s0 + c] >= 0.0;
-            bad_l[c] = ok ? 0 : 1;
-            supp_l[c] = supp ? 1 : 0;
-        }
-        wave_sync_lds();
-
-        for (int s = 0; s < nb; ++s) {
-            const double gam = y_l[s * d + 5 * npl];
-            const double jit = has_jit ? a.jitter[s0 + s] : 0.0;
-            const bool sbad = uniform_int(bad_l[s]) != 0;
-            typename Pol::ChiAcc chi;
-            Pol::chi_init(chi);
-            bool bad_obs = false;
-            for (int gi = 0; gi < n_groups; ++gi) {
-                if (n_groups > 1) load_group(gi);
-                ModelAcc mm[NCH];
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) Pol::model_init(mm[c]);
-                for (int j = 0; j < npl; ++j) pol_add_planet<Pol, NCH>(recs[s * npl + j], o, mm, a);
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) {
-                    if (o[c].in) {
-                        const bool okw = Pol::chi_add(chi, mm[c], o[c], gam, jit, has_jit);
-                        bad_obs = bad_obs || !okw || !o[c].ok;
-                    }
-                }
-            }
-            const double tot = wave_sum(Pol::chi_value(chi));
-            const bool bad = sbad || __any(bad_obs);
-            if (lane == 0) cnew_l[s] = bad ? __builtin_nan("") : tot;
-        }
-        wave_sync_lds();
-
-        for (int c = lane; c < nb; c += 64) {                                   // E
-            const int64_t i = s0 + c;
-            const double c_new = cnew_l[c];
-            double *chi = m.chi2 + (int64_t)h * nh + i;
-            m.c_new[i] = c_new;
-            if (supp_l[c] != 0 && 2.0 * log(u_l[c]) < *chi - c_new) {
-                for (int r = 0; r < d; ++r) xh[(int64_t)r * nh + i] = y_l[c * d + r];
-                *chi = c_new;
-                if (m.n_accept) m.n_accept[(int64_t)h * nh + i] += 1;
-            }
-        }
-    }
-}
-
-template <class Pol>
-static hipError_t launch_demc_half_t(DemcArgs m, DenseArgs a, int h, LaunchShape shape, hipStream_t st)
-{
-    const int block = shape.block > 0 ? shape.block : 256;
-    const int wpb = block / 64;
-    const size_t rec = sizeof(typename Pol::Rec);
-    int sb_cap = kMaxSB;
-    while (sb_cap > 1 && (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec) > 48 * 1024) sb_cap /= 2;
-    const int nch_needed = (int)((a.n_obs + 63) / 64);
-    void (*kern)(DenseArgs, DemcArgs, int);
-    if (nch_needed <= 1) kern = k_demc_half<Pol, 1>;
-    else if (nch_needed <= 2) kern = k_demc_half<Pol, 2>;
-    else if (nch_needed <= 4) kern = k_demc_half<Pol, 4>;
-    else kern = k_demc_half<Pol, 8>;
-    int per_cu = shape.blocks_per_cu;
-    if (per_cu <= 0) {
-        int occ = 0;
-        const size_t lds = (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec);
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess || occ <= 0) occ = 1;
-        per_cu = occ;
-    }
-    const int64_t max_waves = (int64_t)device_cu_count() * per_cu * wpb;
-    // ceil: every wave gets at most one batch when the cap allows it, so no wave
-    // runs a second batch while the others idle
-    const int64_t mw = max_waves > 0 ? max_waves : 1;
-    int64_t sb = (m.nh + mw - 1) / mw;
-    sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
-    a.sb = (int)sb;
-    const size_t lds = (size_t)wpb * demc_lds_per_wave(a.sb, a.n_pl, m.d, rec);
-    const int64_t n_batches = (m.nh + sb - 1) / sb;
-    int64_t grid = (n_batches + wpb - 1) / wpb;
-    const int64_t cap = (int64_t)device_cu_count() * per_cu;
-    if (grid > cap) grid = cap;
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, st, a, m, h);
-    return hipGetLastError();
-}
-
-hipError_t launch_demc_half(DemcArgs m, DenseArgs a, Prec prec, int h, LaunchShape shape, hipStream_t st)
-{
-    if (m.nh <= 0) return hipSuccess;
-    a.n_sys = m.nh;
-    a.n_pl = m.n_pl;
-    a.jitter = m.jitter ? m.jitter + (int64_t)h * m.nh : nullptr;
-    a.out = nullptr;
-    a.grad = nullptr;
-    a.dv = nullptr;
-    return prec == Prec::Mixed ? launch_demc_half_t<PolMixed>(m, a, h, shape, st)
-                               : launch_demc_half_t<Pol64>(m, a, h, shape, st);
 }
 
 // ------------------------------------------------------------------ ragged

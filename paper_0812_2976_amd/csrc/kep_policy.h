@@ -1,0 +1,291 @@
+// Per-precision policies of the dense kernels: the planet record built once
+// per (system, planet), the observation record held in registers, and the
+// arithmetic of one planet's velocity and of the chi-square accumulation, for
+// the mixed-precision path (Sec. 5.1) and the plain binary64 path.  Shared by
+// the dense chi-square kernels and the population sampler's fused half-step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kep_device.h"
+#include "kep_internal.h"
+
+namespace kep {
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool planet_ok(double P, double K, double e, double w, double M0)
+{
+    return isfinite(P) && P > 0.0 && isfinite(K) && isfinite(e) && e >= 0.0 && e < 1.0 &&
+           isfinite(w) && isfinite(M0);
+}
+
+// ------------------------------------------------------------------ mixed
+struct RecMixed {          // 64 bytes, one per (system, planet)
+    Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
+    Ecc32 k;               // e, 1 - e, e/2, e/6
+    float A, B;            // K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
+    int niter, check;      // Danby steps (0: convergence test); 1 if fixed by the caller
+};
+
+struct ObsMixed {
+    double tt;   // t - t0
+    double v;    // observed velocity
+    float s2;    // sigma^2
+    float w;     // 1 / sigma^2 (no jitter)
+    bool in;     // lane holds a real observation
+    bool ok;     // t, v, sigma finite and sigma >= 0
+};
+
+struct PolMixed {
+    using Rec = RecMixed;
+    using Obs = ObsMixed;
+    struct ModelAcc { Kahan32 k; };
+    using ChiAcc = Kahan32;
+
+    static __device__ __forceinline__ bool setup(const DenseArgs &a, double P, double K, double e, double w,
+                                                 double M0, Rec &r)
+    {
+        bool ok = planet_ok(P, K, e, w, M0);
+        if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+        r.ph = make_phase64(P, M0);
+        r.k = make_ecc32(e);
+        const double b2 = (1.0 - e) * (1.0 + e);
+        double sw, cw;
+        sincos(w, &sw, &cw);
+        r.A = (float)(K * b2 * cw);
+        r.B = (float)(-K * sqrt(b2) * sw);
+        r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e);
+        r.check = a.fixed_iter > 0 ? 1 : 0;
+        return ok;
+    }
+
+    static __device__ __forceinline__ void load_obs(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        double v = o.in ? a.v[k] : 0.0;
+        double s = o.in ? a.sigma[k] : 1.0;
+        o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
+        o.tt = t - a.t0;
+        o.v = v;
+        o.s2 = (float)(s * s);
+        o.w = (float)(1.0 / (s * s));
+    }
+
+    static __device__ __forceinline__ void load_obs_model(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        o.ok = isfinite(t);
+        o.tt = t - a.t0;
+        o.v = 0.0;
+        o.s2 = 1.0f;
+        o.w = 1.0f;
+    }
+
+    template <int NCH>
+    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
+                                                      int max_iter, int /*fixed: already in rr.niter*/)
+    {
+        // rr comes from an LDS broadcast: every lane holds the same values
+        const Phase64 ph = rr.ph;
+        const Ecc32 k = rr.k;
+        const float A = rr.A, B = rr.B;
+        const int niter = uniform_int(rr.niter);
+        float M[NCH], E[NCH], st[NCH];
+        SinCos32 sc[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            M[c] = mean_anomaly32(o[c].tt, ph);
+            E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
+        }
+        bool check = uniform_int(rr.check) != 0;
+        if (niter > 0) {
+            for (int it = 0; it < niter - 1; ++it) {   // steps before the last: hardware sin/cos
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k);
+            }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
+        } else {
+            check = true;
+            const int n = max_iter > 0 ? max_iter : 1;
+            for (int it = 0; it < n; ++it) {           // convergence-tested (beyond the schedule),
+                bool conv = true;                      // clamped to the bracket [M - e, M + e]
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    st[c] = danby_step32<true>(E[c], M[c], k, M[c] - k.e, M[c] + k.e, sc[c]);
+                    conv = conv && (fabsf(st[c]) <= 2.384185791e-7f * fmaxf(fabsf(E[c]), 1.0f));
+                }
+                if (__all(conv)) break;
+            }
+        }
+        if (check) {   // a last step the schedule does not bound: evaluate afresh where it is large
+            bool large = false;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) large = large || fabsf(st[c]) > 0.0625f;
+            if (__any(large)) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    sc[c] = sincos32(E[c]);
+                    st[c] = 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            float s = sc[c].s, omc = sc[c].omc;
+            rotate32(s, omc, st[c]);
+            float D = fmaf(k.e, omc, k.ome);           // 1 - e cos E
+            float num = fmaf(B, s, fmaf(-A, omc, A));  // A cos E + B sin E
+            m[c].k.add(num * rcp32(D));
+        }
+    }
+
+    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.k.init(); }
+    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.k.value(); }
+
+    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x.init(); }
+    // One observation's contribution; returns false if the weight is invalid.
+    static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
+                                                   double jit, bool has_jit)
+    {
+        float r = (float)(((double)m.k.s - (double)m.k.c + gam) - o.v);   // residual formed in binary64
+        float w = o.w;
+        bool okw = true;
+        if (has_jit) {
+            float var = o.s2 + (float)(jit * jit);
+            okw = var > 0.0f;
+            w = rcp32(var);
+        } else {
+            okw = o.s2 > 0.0f;
+        }
+        x.add(w * r * r);
+        return okw;
+    }
+    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x.value(); }
+};
+
+// ------------------------------------------------------------------ binary64
+struct Rec64 {            // 64 bytes
+    double P, M0, e, K, b, cw, sw;
+    int pad0, pad1;
+};
+
+struct Obs64 {
+    double tt, v, s2, w;
+    bool in, ok;
+};
+
+struct Pol64 {
+    using Rec = Rec64;
+    using Obs = Obs64;
+    struct ModelAcc { double s; };
+    using ChiAcc = double;
+
+    static __device__ __forceinline__ bool setup(const DenseArgs &, double P, double K, double e, double w,
+                                                 double M0, Rec &r)
+    {
+        bool ok = planet_ok(P, K, e, w, M0);
+        if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+        r.P = P;
+        r.M0 = M0;
+        r.e = e;
+        r.K = K;
+        r.b = sqrt((1.0 - e) * (1.0 + e));
+        sincos(w, &r.sw, &r.cw);
+        r.pad0 = r.pad1 = 0;
+        return ok;
+    }
+
+    static __device__ __forceinline__ void load_obs(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        double v = o.in ? a.v[k] : 0.0;
+        double s = o.in ? a.sigma[k] : 1.0;
+        o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
+        o.tt = t - a.t0;
+        o.v = v;
+        o.s2 = s * s;
+        o.w = 1.0 / (s * s);
+    }
+
+    static __device__ __forceinline__ void load_obs_model(const DenseArgs &a, int64_t k, Obs &o)
+    {
+        o.in = k < a.n_obs;
+        double t = o.in ? a.t[k] : a.t0;
+        o.ok = isfinite(t);
+        o.tt = t - a.t0;
+        o.v = 0.0;
+        o.s2 = 1.0;
+        o.w = 1.0;
+    }
+
+    // Plain binary64 (the paper's double-precision variant): IEEE quotient
+    // (t - t0)/P, exact fraction, M = 2 pi frac + M0 in [0, 2 pi), Danby's
+    // iteration, then v = K b (b cos w cos E - sin w sin E) / (1 - e cos E).
+    template <int NCH>
+    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
+                                                      int max_iter, int fixed)
+    {
+        const double P = uniform_double(rr.P), M0 = uniform_double(rr.M0), e = uniform_double(rr.e);
+        const double K = uniform_double(rr.K), b = uniform_double(rr.b);
+        const double cw = uniform_double(rr.cw), sw = uniform_double(rr.sw);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            double q = o[c].tt / P;
+            double phi = q - floor(q);
+            double M = fma(kTwoPi, phi, M0);
+            M = M - kTwoPi * floor(M * kInvTwoPi);
+            double E = kepler64(M, e, M < kPi ? 1.0 : -1.0, fixed, max_iter);
+            double s, cE;
+            sincos(E, &s, &cE);
+            m[c].s += K * b * (b * cw * cE - sw * s) / (1.0 - e * cE);
+        }
+    }
+
+    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.s = 0.0; }
+    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.s; }
+    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x = 0.0; }
+    static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
+                                                   double jit, bool has_jit)
+    {
+        double r = m.s + gam - o.v;
+        double w = o.w;
+        bool okw = o.s2 > 0.0;
+        if (has_jit) {
+            double var = o.s2 + jit * jit;
+            okw = var > 0.0;
+            w = 1.0 / var;
+        }
+        x = fma(w * r, r, x);
+        return okw;
+    }
+    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x; }
+};
+
+// Iteration count of the plain binary64 kernel: fixed_iter > 0 as given,
+// 0 -> the fixed 30 steps of the plain kernel, < 0 -> schedule + convergence test.
+__device__ __forceinline__ int fixed64(int fixed_iter) { return fixed_iter > 0 ? fixed_iter : (fixed_iter == 0 ? 30 : 0); }
+
+template <class Pol, int NCH>
+__device__ __forceinline__ void pol_add_planet(const typename Pol::Rec &r, const typename Pol::Obs (&o)[NCH],
+                                               typename Pol::ModelAcc (&m)[NCH], const DenseArgs &a)
+{
+    Pol::template add_planet<NCH>(r, o, m, a.max_iter, fixed64(a.fixed_iter));
+}
+
+// Dense kernel.  MODE kChi2: chi-square per system; kModel: model velocities
+// [n_sys][n_obs]; kPlanets: every planet's velocity [n_pl][n_sys][n_obs] in
+// binary32 (the paper's separate-function form, Sec. 4.4, first implementation).
+enum { kChi2 = 0, kModel = 1, kPlanets = 2 };
+
+
+}  // namespace kep
