@@ -53,6 +53,12 @@ class _Demc(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("eps", _D), ("margin", _D)]
 
 
+class _Astro(ctypes.Structure):
+    _fields_ = [("t", _D), ("x", _D), ("y", _D), ("sx", _D), ("sy", _D), ("n_obs", ctypes.c_int64),
+                ("t0", ctypes.c_double), ("P", _D), ("e", _D), ("M0", _D), ("A", _D), ("B", _D), ("F", _D),
+                ("G", _D), ("x0", _D), ("y0", _D), ("n_sys", ctypes.c_int64), ("n_pl", ctypes.c_int64)]
+
+
 def lib():
     """Load (building first if nothing is built) the oracle shared library."""
     global _LIB
@@ -86,6 +92,9 @@ def lib():
         _U32 = ctypes.POINTER(ctypes.c_uint32)
         L.oracle_philox4x32_10.restype = None
         L.oracle_philox4x32_10.argtypes = [_U32, _U32, _U32]
+        for fn in ("oracle_astro_model", "oracle_astro_chisq"):
+            getattr(L, fn).restype = None
+            getattr(L, fn).argtypes = [ctypes.POINTER(_Astro), _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_demc_run.restype = None
         L.oracle_demc_run.argtypes = [ctypes.POINTER(_Demc), ctypes.c_uint64, ctypes.c_int64]
         _LIB = L
@@ -265,3 +274,41 @@ def demc_run(t, v, sigma, x, chi2, n_pl, eps, seed, gen0, n_gen, jitter=None, t0
               _ptr(jit), nh, n_pl, float(gamma), int(jump_every), 0, int(seed) & (2 ** 64 - 1), _ptr(eps), _ptr(mg))
     lib().oracle_demc_run(ctypes.byref(s), int(gen0), int(n_gen))
     return (x, chi2, acc, mg) if margin else (x, chi2, acc)
+
+
+class Astro:
+    """Astrometric batch (Thiele-Innes form): observation epochs t with measured
+    offsets x (RA*cos Dec), y (Dec) and uncertainties sx, sy [n_obs]; planes
+    P, e, M0, A, B, F, G [n_pl, n_sys]; optional offsets x0, y0 [n_sys]."""
+
+    def __init__(self, t, x, y, sx, sy, P, e, M0, A, B, F, G, x0=None, y0=None, t0=0.0):
+        self.t, self.x, self.y, self.sx, self.sy = (_f64(a) for a in (t, x, y, sx, sy))
+        self.P, self.e, self.M0, self.A, self.B, self.F, self.G = (np.atleast_2d(_f64(a))
+                                                                   for a in (P, e, M0, A, B, F, G))
+        self.n_pl, self.n_sys = self.P.shape
+        self.x0 = None if x0 is None else _f64(x0)
+        self.y0 = None if y0 is None else _f64(y0)
+        self.t0 = float(t0)
+        self._s = _Astro(_ptr(self.t), _ptr(self.x), _ptr(self.y), _ptr(self.sx), _ptr(self.sy), self.t.size,
+                         self.t0, _ptr(self.P), _ptr(self.e), _ptr(self.M0), _ptr(self.A), _ptr(self.B),
+                         _ptr(self.F), _ptr(self.G), _ptr(self.x0), _ptr(self.y0), self.n_sys, self.n_pl)
+
+    def _range(self, i0, i1):
+        return int(i0), int(self.n_sys if i1 is None else i1)
+
+
+def astro_model(d: Astro, i0=0, i1=None):
+    """Model offsets [n_sys, 2, n_obs]: row 0 RA*cos Dec = B X + G Y, row 1 Dec = A X + F Y
+    (X = cos E - e, Y = sqrt(1 - e^2) sin E), summed over planets, plus offsets."""
+    i0, i1 = d._range(i0, i1)
+    out = np.full((d.n_sys, 2, d.t.size), np.nan)
+    lib().oracle_astro_model(ctypes.byref(d._s), _ptr(out), i0, i1)
+    return out
+
+
+def astro_chisq(d: Astro, i0=0, i1=None):
+    """chi-square per system of the astrometric model against (x, y)."""
+    i0, i1 = d._range(i0, i1)
+    out = np.full(d.n_sys, np.nan)
+    lib().oracle_astro_chisq(ctypes.byref(d._s), _ptr(out), i0, i1)
+    return out

@@ -506,3 +506,90 @@ void oracle_demc_run(const oracle_demc *s, uint64_t gen0, int64_t n_gen)
         demc_half(s, 1, gen0 + (uint64_t)k);
     }
 }
+
+/* ================================================================== */
+/* Astrometric Keplerian model: the star's reflex position on the sky, */
+/* the larger-dynamic-range application the paper names for the same  */
+/* phase and Kepler core (Sec. 5.1).  Thiele-Innes form: with E the    */
+/* root of Eq. 1 at the mean anomaly of Eq. 4,                         */
+/*   X = cos E - e,  Y = sqrt(1 - e^2) sin E,                          */
+/*   dRA* = B X + G Y,  dDec = A X + F Y  (per planet, summed),        */
+/* plus per-system offsets (x0, y0).  A, B, F, G and the positions are */
+/* in one angular unit (e.g. mas).  chi2 = sum_k (dRA*_k - x_k)^2 /    */
+/* sx_k^2 + (dDec_k - y_k)^2 / sy_k^2.  Planes [n_pl][n_sys] as in the */
+/* dense batch; model output [n_sys][2][n_obs] (RA row, then Dec row). */
+/* ================================================================== */
+typedef struct {
+    const double *t, *x, *y, *sx, *sy;
+    int64_t n_obs;
+    double t0;
+    const double *P, *e, *M0, *A, *B, *F, *G;
+    const double *x0, *y0;
+    int64_t n_sys, n_pl;
+} oracle_astro;
+
+static int astro_system_ok(const oracle_astro *d, int64_t i)
+{
+    if (!finite_d(d->t0)) return 0;
+    for (int64_t j = 0; j < d->n_pl; ++j) {
+        int64_t p = j * d->n_sys + i;
+        if (!(finite_d(d->P[p]) && d->P[p] > 0.0 && finite_d(d->e[p]) && d->e[p] >= 0.0 && d->e[p] < 1.0 &&
+              finite_d(d->M0[p]) && finite_d(d->A[p]) && finite_d(d->B[p]) && finite_d(d->F[p]) &&
+              finite_d(d->G[p])))
+            return 0;
+    }
+    if (d->x0 && !finite_d(d->x0[i])) return 0;
+    if (d->y0 && !finite_d(d->y0[i])) return 0;
+    return 1;
+}
+
+static void astro_xy_l(const oracle_astro *d, int64_t i, double t, ld *ra, ld *dec)
+{
+    ld sra = d->x0 ? (ld)d->x0[i] : 0.0L, sdec = d->y0 ? (ld)d->y0[i] : 0.0L;
+    for (int64_t j = 0; j < d->n_pl; ++j) {
+        int64_t p = j * d->n_sys + i;
+        ld e = (ld)d->e[p];
+        ld E = kepler_root_l(mean_anomaly_l(t, d->t0, d->P[p], d->M0[p]), e);
+        ld X = cosl(E) - e;
+        ld Y = sqrtl((1.0L - e) * (1.0L + e)) * sinl(E);
+        sra += (ld)d->B[p] * X + (ld)d->G[p] * Y;
+        sdec += (ld)d->A[p] * X + (ld)d->F[p] * Y;
+    }
+    *ra = sra;
+    *dec = sdec;
+}
+
+void oracle_astro_model(const oracle_astro *d, double *out, int64_t i0, int64_t i1)
+{
+    for (int64_t i = i0; i < i1; ++i) {
+        int ok = astro_system_ok(d, i);
+        for (int64_t k = 0; k < d->n_obs; ++k) {
+            ld ra = 0.0L, dec = 0.0L;
+            int okk = ok && finite_d(d->t[k]);
+            if (okk) astro_xy_l(d, i, d->t[k], &ra, &dec);
+            out[(i * 2 + 0) * d->n_obs + k] = okk ? (double)ra : NAN;
+            out[(i * 2 + 1) * d->n_obs + k] = okk ? (double)dec : NAN;
+        }
+    }
+}
+
+void oracle_astro_chisq(const oracle_astro *d, double *chi2, int64_t i0, int64_t i1)
+{
+    for (int64_t i = i0; i < i1; ++i) {
+        if (!astro_system_ok(d, i)) { chi2[i] = NAN; continue; }
+        ld acc = 0.0L;
+        int bad = 0;
+        for (int64_t k = 0; k < d->n_obs; ++k) {
+            double t = d->t[k], x = d->x[k], y = d->y[k], sx = d->sx[k], sy = d->sy[k];
+            if (!(finite_d(t) && finite_d(x) && finite_d(y) && finite_d(sx) && finite_d(sy) && sx > 0.0 && sy > 0.0)) {
+                bad = 1;
+                break;
+            }
+            ld ra, dec;
+            astro_xy_l(d, i, t, &ra, &dec);
+            ld rx = ra - (ld)x, ry = dec - (ld)y;
+            acc += rx * rx / ((ld)sx * (ld)sx) + ry * ry / ((ld)sy * (ld)sy);
+        }
+        chi2[i] = bad ? NAN : (double)acc;
+    }
+}

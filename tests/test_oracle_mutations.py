@@ -37,8 +37,15 @@ MUTANTS = {
     "demc_no_K_support": ("if (!(y[n + j] >= 0.0)) return NAN;", "if (0) return NAN;", "demc"),
     "philox_round_order": ("uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;", "uint32_t n0 = (uint32_t)(pa >> 32) ^ c1 ^ k0;",
                            "demc"),
+    # astrometric model (pins in test_oracle_astro.py)
+    "astro_Y_without_b": ("ld Y = sqrtl((1.0L - e) * (1.0L + e)) * sinl(E);", "ld Y = sinl(E);", "astro"),
+    "astro_X_sign_of_e": ("ld X = cosl(E) - e;", "ld X = cosl(E) + e;", "astro"),
+    "astro_ra_uses_A": ("sra += (ld)d->B[p] * X + (ld)d->G[p] * Y;", "sra += (ld)d->A[p] * X + (ld)d->G[p] * Y;",
+                        "astro"),
+    "astro_sigma_not_squared": ("acc += rx * rx / ((ld)sx * (ld)sx) + ry * ry / ((ld)sy * (ld)sy);",
+                                "acc += rx * rx / (ld)sx + ry * ry / ((ld)sy * (ld)sy);", "astro"),
 }
-PIN_FILES = {None: "test_oracle_pins.py", "demc": "test_oracle_demc.py"}
+PIN_FILES = {None: "test_oracle_pins.py", "demc": "test_oracle_demc.py", "astro": "test_oracle_astro.py"}
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
