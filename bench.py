@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--rows", default="fp64,separate,grad,ragged,demc,kepler",
+    ap.add_argument("--rows", default="fp64,separate,grad,ragged,demc,astro,kepler",
                     help="extra paths to time (comma list or 'none')")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="systems in the CPU oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -286,6 +286,31 @@ def main():
             s.close()
             del s, half, obs, oh
         result["demc_c1"] = demc
+
+    # ------------------------------------------------------------ astrometry
+    if "astro" in rows:
+        log("astrometric model (1,048,576 x 2 x 128 epochs)")
+
+        def gpu_astro_truth(t, t0, truth):
+            cols = [gpu(np.asarray(truth[k], dtype=np.float64).reshape(-1, 1)) for k in
+                    ("P", "e", "M0", "A", "B", "F", "G")]
+            return kp.astro_model(gpu(t), *cols, t0=t0, prec="fp64").cpu().numpy()[0]
+
+        wa = synth.with_astro_observations(synth.astro(), gpu_astro_truth)
+        ga = dict(t=gpu(wa.t), x=gpu(wa.x), y=gpu(wa.y), sigma_x=gpu(wa.sx), sigma_y=gpu(wa.sy), P=gpu(wa.P),
+                  e=gpu(wa.e), M0=gpu(wa.M0), A=gpu(wa.A), B=gpu(wa.B), F=gpu(wa.F), G=gpu(wa.G), x0=gpu(wa.x0),
+                  y0=gpu(wa.y0), t0=wa.t0)
+        oa = torch.empty(wa.n_sys, dtype=torch.float64, device=dev)
+        msa, _ = timed(lambda: kp.astro_chisq(**ga, prec="mixed", out=oa), 10, 2, torch)
+        ms64, _ = timed(lambda: kp.astro_chisq(**ga, prec="fp64", out=oa), 3, 1, torch)
+        ms64e, _ = timed(lambda: kp.astro_chisq(**ga, prec="fp64", out=oa, opts={"fixed_iter": -1}), 3, 1, torch)
+        tri = wa.n_sys * wa.n_pl * wa.t.size
+        result["astro"] = {"workload": "1,048,576 systems x 2 planets x 128 two-axis epochs, a ~ logU[1, 100] mas",
+                           "chi2_per_s_mixed": wa.n_sys / (msa * 1e-3), "launch_ms_mixed": msa,
+                           "kepler_solves_per_s_mixed": tri / (msa * 1e-3),
+                           "launch_ms_fp64": ms64, "launch_ms_fp64_early_exit": ms64e,
+                           "speedup_vs_fp64": ms64 / msa, "speedup_vs_fp64_early_exit": ms64e / msa}
+        del ga, oa
 
     # ------------------------------------------------------------ Kepler only
     if "kepler" in rows:

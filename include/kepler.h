@@ -164,6 +164,42 @@ kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float
 kep_status rv_chisq_from_velocities(const kep_obs *obs, const kep_params *par, const float *dv, double *chi2,
                                     const kep_options *opts, void *stream);
 
+/* ---- astrometric Keplerian model (Thiele-Innes form) ----
+   The star's reflex offset on the sky from the same phase (Eq. 4) and Kepler
+   solve (Eq. 1): per planet X = cos E - e, Y = sqrt(1 - e^2) sin E and
+     dRA* = B X + G Y,   dDec = A X + F Y,
+   summed over planets, plus per-system offsets x0 (RA*cos Dec) and y0 (Dec).
+   A, B, F, G are the Thiele-Innes constants of the star's orbit (linear
+   parameters; any angular unit, the same for positions and uncertainties).
+   chi2 = sum_k (dRA*_k - x_k)^2 / sigma_x,k^2 + (dDec_k - y_k)^2 / sigma_y,k^2.
+   This is the larger dynamic range for which Sec. 5.1 notes that binary32 is
+   not enough: KEP_MIXED keeps the binary64 phase and the binary32 Danby
+   iteration and adds one binary64 Newton step against the binary64 mean
+   anomaly (E to ~1e-11 rad), then forms the positions, residuals and sums in
+   binary64.  KEP_FP64 is the plain binary64 path (30 Danby steps by default).
+   Domain: P > 0, 0 <= e < 1, finite parameters, sigma > 0, else NaN for that
+   system.  Planes [n_pl][n_sys] as for kep_params; x0, y0 [n_sys] or NULL. */
+typedef struct kep_astro_obs {
+    const double *t, *x, *y, *sigma_x, *sigma_y;
+    int64_t n_obs;
+    double t0;
+} kep_astro_obs;
+
+typedef struct kep_astro_params {
+    const double *P, *e, *M0, *A, *B, *F, *G;
+    const double *x0, *y0;
+    int64_t n_sys, n_pl;
+} kep_astro_params;
+
+/* Model offsets xy[(i * 2 + 0) * n_obs + k] = dRA*_ik + x0_i and
+   xy[(i * 2 + 1) * n_obs + k] = dDec_ik + y0_i.  x, y and the sigmas are not read. */
+kep_status astro_model(const kep_astro_obs *obs, const kep_astro_params *par, double *xy,
+                       kep_prec prec, const kep_options *opts, void *stream);
+
+/* chi2[i], i < n_sys. */
+kep_status astro_chisq(const kep_astro_obs *obs, const kep_astro_params *par, double *chi2,
+                       kep_prec prec, const kep_options *opts, void *stream);
+
 /* ---- ragged batches (systems of uneven n_pl and n_obs, CSR-packed) ----
    System i owns observations obs_off[i] .. obs_off[i+1]-1 of t, v, sigma and
    planets pl_off[i] .. pl_off[i+1]-1 of P, K, e, omega, M0 (flat arrays of

@@ -15,6 +15,7 @@ Functions keep the C names:
   rv_planet_velocities / rv_chisq_from_velocities   the separate-function form
   RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
   DEMC(...)                                population sampler (DE-MC) on the batched chi-square
+  astro_model / astro_chisq                astrometric Keplerian model (Thiele-Innes form)
   RVChiSq.apply(...)                       torch.autograd.Function over rv_chisq_grad
 Parameter planes are float64 CUDA tensors shaped (n_pl, n_sys) (system index
 fastest); observations are 1-D float64 CUDA tensors.
@@ -77,6 +78,16 @@ class KepDemcOptions(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("eps", _D)]
 
 
+class KepAstroObs(ctypes.Structure):
+    _fields_ = [("t", _D), ("x", _D), ("y", _D), ("sigma_x", _D), ("sigma_y", _D), ("n_obs", ctypes.c_int64),
+                ("t0", ctypes.c_double)]
+
+
+class KepAstroParams(ctypes.Structure):
+    _fields_ = [("P", _D), ("e", _D), ("M0", _D), ("A", _D), ("B", _D), ("F", _D), ("G", _D), ("x0", _D),
+                ("y0", _D), ("n_sys", ctypes.c_int64), ("n_pl", ctypes.c_int64)]
+
+
 class KeplerError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -88,7 +99,7 @@ _LIB = None
 EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
            "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
            "kep_plan_get_info", "kep_plan_destroy", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
-           "kep_demc_plan_destroy", "kep_last_error", "kep_abi_version")
+           "kep_demc_plan_destroy", "astro_model", "astro_chisq", "kep_last_error", "kep_abi_version")
 
 
 def load_library(path: str = LIB_PATH):
@@ -122,12 +133,15 @@ def load_library(path: str = LIB_PATH):
     L.demc_run.argtypes = [_D, ctypes.c_uint64, ctypes.c_int64, _D]
     L.kep_demc_plan_destroy.argtypes = [_D]
     L.kep_demc_plan_destroy.restype = None
+    for name in ("astro_model", "astro_chisq"):
+        getattr(L, name).argtypes = [P(KepAstroObs), P(KepAstroParams), _D, ctypes.c_int, P(KepOptions), _D]
     L.kep_last_error.restype = ctypes.c_char_p
     L.kep_last_error.argtypes = []
     L.kep_abi_version.restype = ctypes.c_int
     for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
                  "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
-                 "kep_plan_get_info", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run"):
+                 "kep_plan_get_info", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
+                 "astro_model", "astro_chisq"):
         getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -311,6 +325,46 @@ def rv_chisq_from_velocities(t, v, sigma, dv, offset=None, jitter=None, t0=0.0, 
     out = _out(out, "out", (n_sys,), dv.device)
     _check(load_library().rv_chisq_from_velocities(ctypes.byref(obs), ctypes.byref(par), dv.data_ptr(),
                                                    out.data_ptr(), _opts(opts), _stream(dv.device)))
+    return out
+
+
+def _astro(t, x, y, sigma_x, sigma_y, P, e, M0, A, B, F, G, x0, y0, t0):
+    planes = [_dev(a, n, 2) for a, n in zip((P, e, M0, A, B, F, G), ("P", "e", "M0", "A", "B", "F", "G"))]
+    shape = planes[0].shape
+    if any(p.shape != shape for p in planes):
+        raise ValueError("P, e, M0, A, B, F, G must share the shape (n_pl, n_sys)")
+    n_pl, n_sys = shape
+    t = _dev(t, "t", 1)
+    obs_arrays = []
+    for arr, nm in ((x, "x"), (y, "y"), (sigma_x, "sigma_x"), (sigma_y, "sigma_y")):
+        arr = None if arr is None else _dev(arr, nm, 1)
+        if arr is not None and arr.numel() != t.numel():
+            raise ValueError(f"{nm} must have n_obs = {t.numel()} elements")
+        obs_arrays.append(arr)
+    x0 = _opt_dev(x0, "x0", n_sys)
+    y0 = _opt_dev(y0, "y0", n_sys)
+    obs = KepAstroObs(t.data_ptr(), *[_ptr(a) for a in obs_arrays], t.numel(), float(t0))
+    par = KepAstroParams(*[p.data_ptr() for p in planes], _ptr(x0), _ptr(y0), n_sys, n_pl)
+    return obs, par, (t, obs_arrays, planes, x0, y0), t.device
+
+
+def astro_model(t, P, e, M0, A, B, F, G, x0=None, y0=None, t0=0.0, prec="mixed", out=None, opts=None):
+    """Astrometric model offsets (n_sys, 2, n_obs): row 0 dRA* = B X + G Y (+ x0), row 1
+    dDec = A X + F Y (+ y0), X = cos E - e, Y = sqrt(1 - e^2) sin E."""
+    obs, par, keep, dev = _astro(t, None, None, None, None, P, e, M0, A, B, F, G, x0, y0, t0)
+    out = _out(out, "out", (par.n_sys, 2, obs.n_obs), dev)
+    _check(load_library().astro_model(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec),
+                                      _opts(opts), _stream(dev)))
+    return out
+
+
+def astro_chisq(t, x, y, sigma_x, sigma_y, P, e, M0, A, B, F, G, x0=None, y0=None, t0=0.0, prec="mixed",
+                out=None, opts=None):
+    """chi-square per system of the astrometric model against offsets (x, y)."""
+    obs, par, keep, dev = _astro(t, x, y, sigma_x, sigma_y, P, e, M0, A, B, F, G, x0, y0, t0)
+    out = _out(out, "out", (par.n_sys,), dev)
+    _check(load_library().astro_chisq(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec),
+                                      _opts(opts), _stream(dev)))
     return out
 
 

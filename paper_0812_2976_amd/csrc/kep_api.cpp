@@ -205,6 +205,65 @@ kep_status rv_nll_grad(const kep_obs *obs, const kep_params *par, double *nll, d
     return dense_grad(obs, par, nll, grad, prec, opts, stream, true, "rv_nll_grad");
 }
 
+static kep_status astro_common(const kep_astro_obs *obs, const kep_astro_params *par, double *out, kep_prec prec,
+                               const kep_options *opts, void *stream, bool model, const char *fn)
+{
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
+    if (obs->n_obs < 0) return fail(KEP_ERR_ARG, "%s: n_obs = %lld < 0", fn, (long long)obs->n_obs);
+    if (par->n_sys < 0) return fail(KEP_ERR_ARG, "%s: n_sys = %lld < 0", fn, (long long)par->n_sys);
+    if (par->n_pl < 1 || par->n_pl > KEP_MAX_PL)
+        return fail(KEP_ERR_SHAPE, "%s: n_pl = %lld outside [1, %d]", fn, (long long)par->n_pl, KEP_MAX_PL);
+    if (mul_overflows(par->n_sys, par->n_pl) || mul_overflows(par->n_sys, 2 * obs->n_obs))
+        return fail(KEP_ERR_SHAPE, "%s: n_sys x n_pl or n_sys x n_obs overflows", fn);
+    if (obs->n_obs > 0 && !obs->t) return fail(KEP_ERR_ARG, "%s: obs->t is NULL", fn);
+    if (!model && obs->n_obs > 0 && (!obs->x || !obs->y || !obs->sigma_x || !obs->sigma_y))
+        return fail(KEP_ERR_ARG, "%s: obs->x, y, sigma_x and sigma_y must not be NULL", fn);
+    if (par->n_sys > 0 && (!par->P || !par->e || !par->M0 || !par->A || !par->B || !par->F || !par->G))
+        return fail(KEP_ERR_ARG, "%s: a parameter plane (P, e, M0, A, B, F, G) is NULL", fn);
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0 || (model && obs->n_obs == 0)) return KEP_OK;
+    if (!out) return fail(KEP_ERR_ARG, "%s: output is NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::AstroArgs a{};
+    a.t = obs->t;
+    a.x = obs->x;
+    a.y = obs->y;
+    a.sx = obs->sigma_x;
+    a.sy = obs->sigma_y;
+    a.n_obs = obs->n_obs;
+    a.t0 = obs->t0;
+    a.P = par->P;
+    a.e = par->e;
+    a.M0 = par->M0;
+    a.A = par->A;
+    a.B = par->B;
+    a.F = par->F;
+    a.G = par->G;
+    a.x0 = par->x0;
+    a.y0 = par->y0;
+    a.n_sys = par->n_sys;
+    a.n_pl = (int)par->n_pl;
+    a.sb = 1;
+    a.out = out;
+    a.fixed_iter = o.fixed_iter;
+    a.max_iter = o.max_iter;
+    return launch_status(kep::launch_astro(a, to_prec(prec), model, o.shape, (hipStream_t)stream), fn);
+}
+
+kep_status astro_model(const kep_astro_obs *obs, const kep_astro_params *par, double *xy, kep_prec prec,
+                       const kep_options *opts, void *stream)
+{
+    return astro_common(obs, par, xy, prec, opts, stream, true, "astro_model");
+}
+
+kep_status astro_chisq(const kep_astro_obs *obs, const kep_astro_params *par, double *chi2, kep_prec prec,
+                       const kep_options *opts, void *stream)
+{
+    return astro_common(obs, par, chi2, prec, opts, stream, false, "astro_chisq");
+}
+
 kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float *dv, const kep_options *opts,
                                 void *stream)
 {

@@ -42,6 +42,22 @@ struct RaggedArgs {
     int fixed_iter, max_iter;
 };
 
+// Astrometric batch (Thiele-Innes form): epochs t with measured offsets x
+// (RA*cos Dec) and y (Dec), uncertainties sx, sy; planes P, e, M0, A, B, F, G
+// [n_pl][n_sys]; offsets x0, y0 [n_sys] or null.
+struct AstroArgs {
+    const double *t, *x, *y, *sx, *sy;
+    int64_t n_obs;
+    double t0;
+    const double *P, *e, *M0, *A, *B, *F, *G;
+    const double *x0, *y0;
+    int64_t n_sys;
+    int n_pl;
+    int sb;
+    double *out;       // chi2 [n_sys] or positions [n_sys][2][n_obs]
+    int fixed_iter, max_iter;
+};
+
 // Population sampler (DE-MC): two halves of n_half chains, each half laid out
 // [d][nh] with rows P[n_pl], K[n_pl], e[n_pl], omega[n_pl], M0[n_pl], gamma.
 struct DemcArgs {
@@ -81,6 +97,7 @@ hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStrea
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
+hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 // DE-MC: chi-square of the whole population (both halves; NaN where K < 0),
 // one generation (both halves), the device generation counter's setter and
 // increment.

@@ -37,7 +37,7 @@ DENSE = {
     "c4": (262144, 4, 256, 0.8, "uniform", True),
 }
 SEEDS = {"c0": 1000, "c1": 1001, "c2": 1002, "c3": 1003, "c4": 1004, "stress": 1102,
-         "kepler": 1200, "kepler_stress": 1201, "demc": 1300}
+         "kepler": 1200, "kepler_stress": 1201, "demc": 1300, "astro": 1400}
 
 
 @dataclass
@@ -259,3 +259,78 @@ def demc_population(truth: dict, n_half: int, seed: Optional[int] = None, rel_sp
     x[:, 2 * n_pl:3 * n_pl, :] = np.clip(x[:, 2 * n_pl:3 * n_pl, :], 0.0, 0.95)
     x[:, 5 * n_pl, :] = rng.normal(scale=0.5, size=(2, n_half))
     return x, np.concatenate(eps + [np.array([0.1 * rel_spread])])
+
+
+@dataclass
+class AstroWorkload:
+    """Astrometric batch: epochs t [n_obs] with offsets x (RA*cos Dec), y (Dec) and
+    uncertainties sx, sy; planes P, e, M0, A, B, F, G [n_pl, n_sys]; offsets x0, y0."""
+    t: np.ndarray
+    sx: np.ndarray
+    sy: np.ndarray
+    P: np.ndarray
+    e: np.ndarray
+    M0: np.ndarray
+    A: np.ndarray
+    B: np.ndarray
+    F: np.ndarray
+    G: np.ndarray
+    x0: np.ndarray
+    y0: np.ndarray
+    noise_x: np.ndarray
+    noise_y: np.ndarray
+    truth: dict
+    t0: float = 0.0
+    x: Optional[np.ndarray] = None
+    y: Optional[np.ndarray] = None
+
+    @property
+    def n_sys(self):
+        return self.P.shape[1]
+
+    @property
+    def n_pl(self):
+        return self.P.shape[0]
+
+
+def astro(n_sys: int = 1048576, n_pl: int = 2, n_obs: int = 128, seed: Optional[int] = None,
+          e_range=(0.0, 0.9)) -> AstroWorkload:
+    """Astrometric workload: n_obs epochs over five years (t ~ U[2457000, 2458826] d,
+    sorted), sigma_x, sigma_y ~ U[0.02, 0.1] mas; per planet P log-uniform [10, 2000] d,
+    e ~ U[e_range], M0 ~ U[0, 2 pi), Thiele-Innes constants a u with a log-uniform
+    [1, 100] mas (a binary-star range: amplitudes up to 5000 times the noise) and
+    u ~ U[-1, 1] for each of A, B, F, G; offsets ~ U[-1, 1] mas.  System 0 is the
+    truth (zero offsets); its noise is drawn here, the observed offsets are formed
+    by with_astro_observations."""
+    rng = np.random.default_rng(SEEDS["astro"] if seed is None else seed)
+    t = np.sort(rng.uniform(2457000.0, 2458826.0, n_obs))
+    sx = rng.uniform(0.02, 0.1, n_obs)
+    sy = rng.uniform(0.02, 0.1, n_obs)
+
+    def planets(n):
+        P = np.sort(np.exp(rng.uniform(np.log(10.0), np.log(2000.0), size=(n_pl, n))), axis=0)
+        e = rng.uniform(e_range[0], e_range[1], size=(n_pl, n))
+        M0 = rng.uniform(0.0, TWO_PI, size=(n_pl, n))
+        a = np.exp(rng.uniform(0.0, np.log(100.0), size=(n_pl, n)))
+        c = [a * rng.uniform(-1.0, 1.0, size=(n_pl, n)) for _ in range(4)]
+        return [P, e, M0] + c
+
+    truth = dict(zip(("P", "e", "M0", "A", "B", "F", "G"), planets(1)))
+    noise_x = rng.normal(size=n_obs) * sx
+    noise_y = rng.normal(size=n_obs) * sy
+    planes = planets(n_sys)
+    x0 = rng.uniform(-1.0, 1.0, n_sys)
+    y0 = rng.uniform(-1.0, 1.0, n_sys)
+    for k, arr in zip(("P", "e", "M0", "A", "B", "F", "G"), planes):
+        arr[:, 0] = truth[k][:, 0]
+    x0[0] = y0[0] = 0.0
+    return AstroWorkload(t, sx, sy, *planes, x0, y0, noise_x, noise_y, truth)
+
+
+def with_astro_observations(wl: AstroWorkload, model_fn: Callable, noise_free: bool = False) -> AstroWorkload:
+    """Observed offsets = model of the truth system (model_fn(t, t0, truth) -> (2, n_obs))
+    plus the drawn noise."""
+    m = np.asarray(model_fn(wl.t, wl.t0, wl.truth))
+    wl.x = m[0] + (0.0 if noise_free else wl.noise_x)
+    wl.y = m[1] + (0.0 if noise_free else wl.noise_y)
+    return wl

@@ -131,3 +131,30 @@ def chi2_tol_mixed_ragged(rw, ref):
         w = 1.0 / (rw.sigma[o0:o1] ** 2 + jit ** 2)
         tol[i] = max(tol[i], 2 * DV_MIXED * np.sum(w * np.abs(r)) + DV_MIXED ** 2 * np.sum(w))
     return tol
+
+
+def oracle_astro_truth(t, t0, truth):
+    """Truth system's astrometric offsets (2, n_obs) by the oracle."""
+    z = np.zeros_like(t)
+    cols = [np.asarray(truth[k], dtype=np.float64).reshape(-1, 1) for k in ("P", "e", "M0", "A", "B", "F", "G")]
+    return oracle.astro_model(oracle.Astro(t, z, z, z + 1, z + 1, *cols, t0=t0))[0]
+
+
+def astro(n_sys, n_pl, n_obs, seed=None, e_range=(0.0, 0.9), noise_free=False):
+    wl = synth.astro(n_sys=n_sys, n_pl=n_pl, n_obs=n_obs, seed=seed, e_range=e_range)
+    return synth.with_astro_observations(wl, oracle_astro_truth, noise_free=noise_free)
+
+
+def oracle_astro(wl):
+    return oracle.Astro(wl.t, wl.x, wl.y, wl.sx, wl.sy, wl.P, wl.e, wl.M0, wl.A, wl.B, wl.F, wl.G, wl.x0, wl.y0,
+                        wl.t0)
+
+
+def astro_to_gpu(wl, dev):
+    import torch
+
+    def g(a):
+        return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    return dict(t=g(wl.t), x=g(wl.x), y=g(wl.y), sigma_x=g(wl.sx), sigma_y=g(wl.sy), P=g(wl.P), e=g(wl.e),
+                M0=g(wl.M0), A=g(wl.A), B=g(wl.B), F=g(wl.F), G=g(wl.G), x0=g(wl.x0), y0=g(wl.y0), t0=wl.t0)
