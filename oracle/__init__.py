@@ -83,6 +83,8 @@ def lib():
             f.argtypes = [ctypes.POINTER(_Dense), _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_grad.restype = None
         L.oracle_chisq_grad.argtypes = [ctypes.POINTER(_Dense), _D, _D, ctypes.c_int64, ctypes.c_int64]
+        L.oracle_gn.restype = None
+        L.oracle_gn.argtypes = [ctypes.POINTER(_Dense), _D, _D, _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_nll_grad.restype = None
         L.oracle_nll_grad.argtypes = [ctypes.POINTER(_Dense), _D, _D, ctypes.c_int64, ctypes.c_int64]
         L.oracle_chisq_grad_scales.restype = None
@@ -186,6 +188,30 @@ def nll_grad(d: Dense, i0=0, i1=None):
     grad = np.full((5 * d.n_pl + 2, d.n_sys), np.nan)
     lib().oracle_nll_grad(ctypes.byref(d._s), _ptr(nll), _ptr(grad), i0, i1)
     return nll, grad
+
+
+def gn(d: Dense, i0=0, i1=None):
+    """Gauss-Newton products: (chi2 [n_sys], jtwr [np, n_sys], jtwj [np (np + 1) / 2, n_sys])
+    with np = 5 n_pl + 1; jtwj packed upper triangle, (a, b), a <= b, at
+    a np - a (a - 1) / 2 + (b - a)."""
+    i0, i1 = d._range(i0, i1)
+    np_ = 5 * d.n_pl + 1
+    chi2 = np.full(d.n_sys, np.nan)
+    jtwr = np.full((np_, d.n_sys), np.nan)
+    jtwj = np.full((np_ * (np_ + 1) // 2, d.n_sys), np.nan)
+    lib().oracle_gn(ctypes.byref(d._s), _ptr(chi2), _ptr(jtwr), _ptr(jtwj), i0, i1)
+    return chi2, jtwr, jtwj
+
+
+def unpack_sym(packed, n):
+    """[n (n + 1) / 2, ...] packed upper triangle -> [n, n, ...] symmetric."""
+    out = np.empty((n, n) + packed.shape[1:])
+    idx = 0
+    for a in range(n):
+        for b in range(a, n):
+            out[a, b] = out[b, a] = packed[idx]
+            idx += 1
+    return out
 
 
 def chisq_grad_scales(d: Dense, i0=0, i1=None):

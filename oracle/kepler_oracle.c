@@ -233,6 +233,34 @@ void oracle_chisq(const oracle_dense *d, double *chi2, int64_t i0, int64_t i1)
 /* grad layout: [(5*n_pl + 1)][n_sys], planet j uses rows 5j..5j+4 in  */
 /* the order P, K, e, omega, M0; the last row is the offset.           */
 /* ------------------------------------------------------------------ */
+/* Partial derivatives of planet j's velocity at time t with respect to
+   (P, K, e, omega, M0) of system i. */
+static void planet_dv_l(const oracle_dense *d, int64_t i, int64_t j, double t, ld dv[5])
+{
+    int64_t p = j * d->n_sys + i;
+    ld P = d->P[p], K = d->K[p], e = d->e[p], om = d->w[p];
+    ld q = (ld)((t - d->t0) / d->P[p]);
+    ld M = mean_anomaly_l(t, d->t0, d->P[p], d->M0[p]);
+    ld E = kepler_root_l(M, e);
+    ld f = true_anomaly_l(E, e);
+    ld one_m_e2 = (1.0L - e) * (1.0L + e);
+    ld b = sqrtl(one_m_e2);
+    ld ecf = 1.0L + e * cosl(f);
+    ld dfdM = ecf * ecf / (one_m_e2 * b);
+    ld dfde = sinl(f) * (2.0L + e * cosl(f)) / one_m_e2;
+    ld swf = sinl(om + f);
+    ld dv_dK = cosl(om + f) + e * cosl(om);
+    ld dv_dw = -K * (swf + e * sinl(om));
+    ld dv_dM0 = -K * swf * dfdM;
+    ld dv_dP = dv_dM0 * (-TWO_PI_L * q / P);
+    ld dv_de = K * cosl(om) - K * swf * dfde;
+    dv[0] = dv_dP;
+    dv[1] = dv_dK;
+    dv[2] = dv_de;
+    dv[3] = dv_dw;
+    dv[4] = dv_dM0;
+}
+
 static void chisq_grad_impl(const oracle_dense *d, double *chi2, double *grad, double *scale_r,
                             double *scale_1, int nll, int64_t i0, int64_t i1)
 {
@@ -254,24 +282,8 @@ static void chisq_grad_impl(const oracle_dense *d, double *chi2, double *grad, d
             sum_w2r2 += wk * wk * r * r;
             ld c = 2.0L * wk * r;
             for (int64_t j = 0; j < d->n_pl; ++j) {
-                int64_t p = j * d->n_sys + i;
-                ld P = d->P[p], K = d->K[p], e = d->e[p], om = d->w[p];
-                ld q = (ld)((d->t[k] - d->t0) / d->P[p]);
-                ld M = mean_anomaly_l(d->t[k], d->t0, d->P[p], d->M0[p]);
-                ld E = kepler_root_l(M, e);
-                ld f = true_anomaly_l(E, e);
-                ld one_m_e2 = (1.0L - e) * (1.0L + e);
-                ld b = sqrtl(one_m_e2);
-                ld ecf = 1.0L + e * cosl(f);
-                ld dfdM = ecf * ecf / (one_m_e2 * b);
-                ld dfde = sinl(f) * (2.0L + e * cosl(f)) / one_m_e2;
-                ld swf = sinl(om + f);
-                ld dv_dK = cosl(om + f) + e * cosl(om);
-                ld dv_dw = -K * (swf + e * sinl(om));
-                ld dv_dM0 = -K * swf * dfdM;
-                ld dv_dP = dv_dM0 * (-TWO_PI_L * q / P);
-                ld dv_de = K * cosl(om) - K * swf * dfde;
-                const ld dv[5] = {dv_dP, dv_dK, dv_de, dv_dw, dv_dM0};
+                ld dv[5];
+                planet_dv_l(d, i, j, d->t[k], dv);
                 for (int a = 0; a < 5; ++a) {
                     g[5 * j + a] += c * dv[a];
                     sr[5 * j + a] += fabsl(c * dv[a]);
@@ -591,5 +603,45 @@ void oracle_astro_chisq(const oracle_astro *d, double *chi2, int64_t i0, int64_t
             acc += rx * rx / ((ld)sx * (ld)sx) + ry * ry / ((ld)sy * (ld)sy);
         }
         chi2[i] = bad ? NAN : (double)acc;
+    }
+}
+
+
+/* ================================================================== */
+/* Gauss-Newton products of the chi-square (for Levenberg-Marquardt    */
+/* and Newton-type optimisers; the paper asks for derivatives to feed  */
+/* optimisers, Sec. 6): with J the Jacobian of the model velocities    */
+/* (rows = observations, columns = the 5 n_pl + 1 parameters in the    */
+/* gradient's order) and W = diag(w_k), w_k = 1/(sigma_k^2 + s^2):     */
+/*   jtwr = J^T W r        (= half the chi-square gradient)            */
+/*   jtwj = J^T W J        packed upper triangle, (a, b) with a <= b   */
+/*          at a np - a (a - 1) / 2 + (b - a), np = 5 n_pl + 1.        */
+/* Layout [row][n_sys] for both.                                       */
+/* ================================================================== */
+void oracle_gn(const oracle_dense *d, double *chi2, double *jtwr, double *jtwj, int64_t i0, int64_t i1)
+{
+    const int64_t np = 5 * d->n_pl + 1, npk = np * (np + 1) / 2;
+    ld Jr[5 * 8 + 1], JJ[(5 * 8 + 1) * (5 * 8 + 2) / 2], row[5 * 8 + 1];
+    for (int64_t i = i0; i < i1; ++i) {
+        int ok = system_ok(d, i) && d->n_pl <= 8;
+        double s = d->jitter ? d->jitter[i] : 0.0;
+        ld acc = 0.0L;
+        for (int64_t a = 0; a < np; ++a) Jr[a] = 0.0L;
+        for (int64_t a = 0; a < npk; ++a) JJ[a] = 0.0L;
+        for (int64_t k = 0; ok && k < d->n_obs; ++k) {
+            ld wk = weight_l(d->sigma[k], d->v[k], d->t[k], s);
+            if (wk == 0.0L) { ok = 0; break; }
+            ld r = model_l(d, i, d->t[k]) - (ld)d->v[k];
+            acc += wk * r * r;
+            for (int64_t j = 0; j < d->n_pl; ++j) planet_dv_l(d, i, j, d->t[k], row + 5 * j);
+            row[np - 1] = 1.0L;
+            for (int64_t a = 0; a < np; ++a) {
+                Jr[a] += wk * row[a] * r;
+                for (int64_t b = a; b < np; ++b) JJ[a * np - a * (a - 1) / 2 + (b - a)] += wk * row[a] * row[b];
+            }
+        }
+        chi2[i] = ok ? (double)acc : NAN;
+        for (int64_t a = 0; a < np; ++a) jtwr[a * d->n_sys + i] = ok ? (double)Jr[a] : NAN;
+        for (int64_t a = 0; a < npk; ++a) jtwj[a * d->n_sys + i] = ok ? (double)JJ[a] : NAN;
     }
 }

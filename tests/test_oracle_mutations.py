@@ -29,6 +29,10 @@ MUTANTS = {
     "phase_not_binary64": ("double q = dt / P;", "double q = (double)((float)dt / (float)P);"),
     "nll_log_term_dropped": ("sum_logvar -= logl(wk);", ""),
     "nll_jitter_grad_sign": ("(2.0L * s * (sum_w - sum_w2r2))", "(2.0L * s * (sum_w2r2 - sum_w))"),
+    "gn_weight_dropped": ("JJ[a * np - a * (a - 1) / 2 + (b - a)] += wk * row[a] * row[b];",
+                          "JJ[a * np - a * (a - 1) / 2 + (b - a)] += row[a] * row[b];"),
+    "gn_jtwr_sign": ("Jr[a] += wk * row[a] * r;", "Jr[a] -= wk * row[a] * r;"),
+    "gn_offset_column": ("row[np - 1] = 1.0L;", "row[np - 1] = 0.0L;"),
     # population sampler (pins in test_oracle_demc.py)
     "demc_acceptance_without_half": ("if (2.0 * log(u) < c_old - c_new)", "if (log(u) < c_old - c_new)", "demc"),
     "demc_own_half_differences": ("const double *xo = s->x + (int64_t)(1 - h) * d * nh;", "const double *xo = xh;",

@@ -428,3 +428,71 @@ def test_nll_matches_chisq_plus_log_terms_and_fd_in_jitter():
             dd = oracle.Dense(wl.t, wl.v, wl.sigma, wl.P, wl.K, wl.e, wl.w, wl.M0, wl.offset, jit, wl.t0)
             vals.append(oracle.nll_grad(dd, i, i + 1)[0][i])
         assert (vals[0] - vals[1]) / (2 * h) == pytest.approx(grad[-1, i], rel=1e-6, abs=1e-6)
+
+
+# ------------------------------------------------- Gauss-Newton products
+def _gn_problem(seed=31, n_obs=60, noise=True):
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(2455000.0, 2455400.0, n_obs))
+    sigma = rng.uniform(1.0, 3.0, n_obs)
+    th = dict(P=[[9.7], [83.0]], K=[[25.0], [12.0]], e=[[0.25], [0.4]], w=[[1.1], [4.0]], M0=[[2.0], [0.7]])
+    t0 = 2455200.0
+    d0 = oracle.Dense(t, np.zeros(n_obs), sigma, *(np.array(th[k]) for k in ("P", "K", "e", "w", "M0")), [0.8],
+                      None, t0)
+    v = oracle.rv_model(d0)[0] + (rng.normal(size=n_obs) * sigma if noise else 0.0)
+    return t, v, sigma, th, t0
+
+
+def _flat(th, gam):
+    return np.array([th[k][j][0] for j in range(2) for k in ("P", "K", "e", "w", "M0")] + [gam])
+
+
+def _dense_from(t, v, sigma, theta, t0):
+    planes = [np.array([[theta[5 * j + a]] for j in range(2)]) for a in range(5)]
+    return oracle.Dense(t, v, sigma, *planes, [theta[-1]], None, t0)
+
+
+def test_gn_products_match_finite_difference_jacobian():
+    """J^T W J from central differences of the oracle's model (an independent route:
+    numerical Jacobian and a numpy product) equals the analytic packed matrix;
+    J^T W r is half the chi-square gradient."""
+    t, v, sigma, th, t0 = _gn_problem()
+    theta = _flat(th, 0.8)
+    d = _dense_from(t, v, sigma, theta, t0)
+    chi2, jtwr, jtwj = oracle.gn(d)
+    n = theta.size
+    J = np.empty((t.size, n))
+    span = np.max(np.abs(t - t0))
+    for a in range(n):
+        h = 1e-6 * theta[a] ** 2 / (2 * np.pi * span) if a % 5 == 0 and a < n - 1 else 1e-6 * max(abs(theta[a]), 1.0)
+        tp, tm = theta.copy(), theta.copy()
+        tp[a] += h
+        tm[a] -= h
+        J[:, a] = (oracle.rv_model(_dense_from(t, v, sigma, tp, t0))[0] -
+                   oracle.rv_model(_dense_from(t, v, sigma, tm, t0))[0]) / (2 * h)
+    W = 1.0 / sigma ** 2
+    ref = J.T @ (W[:, None] * J)
+    scale = np.abs(J).T @ (W[:, None] * np.abs(J))
+    got = oracle.unpack_sym(jtwj[:, 0], n)
+    assert np.max(np.abs(got - ref) / scale) < 1e-6
+    _, grad = oracle.chisq_grad(d)
+    assert np.allclose(jtwr[:, 0], 0.5 * grad[:, 0], rtol=1e-13, atol=0)
+    assert chi2[0] == pytest.approx(oracle.chisq(d)[0], rel=1e-15)
+    ev = np.linalg.eigvalsh(got)
+    assert ev.min() > -1e-12 * ev.max()
+
+
+def test_gn_step_converges_quadratically_on_noise_free_data():
+    """Noise-free data from theta*: a Gauss-Newton step theta - (J^T W J)^-1 J^T W r from a
+    start 1e-4 (relative) away lands within the square of that distance (residuals
+    vanish at the solution, so Gauss-Newton is Newton there)."""
+    t, v, sigma, th, t0 = _gn_problem(noise=False)
+    star = _flat(th, 0.8)
+    rng = np.random.default_rng(5)
+    scale = np.maximum(np.abs(star), 1.0)
+    x0 = star + 1e-4 * scale * rng.normal(size=star.size) * np.where(np.arange(star.size) % 5 == 0, 1e-3, 1.0)
+    _, jtwr, jtwj = oracle.gn(_dense_from(t, v, sigma, x0, t0))
+    x1 = x0 - np.linalg.solve(oracle.unpack_sym(jtwj[:, 0], star.size), jtwr[:, 0])
+    e0 = np.max(np.abs(x0 - star) / scale)
+    e1 = np.max(np.abs(x1 - star) / scale)
+    assert e1 < 100 * e0 ** 2 + 1e-12, (e0, e1)
