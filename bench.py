@@ -63,7 +63,7 @@ def mean_iterations(e_max, s2=0.8525, s3=0.975):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h"):
+    for f in ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_grad.h"):
         with open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -147,6 +147,23 @@ kep_status rv_chisq_grad(const kep_obs *obs, const kep_params *par, double *chi2
 kep_status rv_nll_grad(const kep_obs *obs, const kep_params *par, double *nll, double *grad,
                        kep_prec prec, const kep_options *opts, void *stream);
 
+/* Gauss-Newton products for Levenberg-Marquardt / Newton-type optimisers (the
+   paper asks for derivatives to feed optimisers, Sec. 6).  With J the
+   Jacobian of the model velocities (rows: observations; columns: the
+   np = 5 n_pl + 1 parameters in rv_chisq_grad's order) and
+   W = diag(1/(sigma_k^2 + s_i^2)):
+     chi2[i]                      = r^T W r (Eq. 5),
+     jtwr[a * n_sys + i]          = (J^T W r)_a  (half the chi-square gradient),
+     jtwj[idx(a, b) * n_sys + i]  = (J^T W J)_ab for a <= b, packed upper
+                                    triangle, idx(a, b) = a np - a (a - 1)/2 + (b - a),
+                                    np (np + 1)/2 rows.
+   The jitter is a fixed input.  J is formed from the same implicit-function
+   derivative terms as rv_chisq_grad (binary32 terms in KEP_MIXED, binary64 in
+   KEP_FP64) and the products are accumulated in binary64 on the matrix cores.
+   Domain and errors as rv_chisq_grad. */
+kep_status rv_chisq_gn(const kep_obs *obs, const kep_params *par, double *chi2, double *jtwr, double *jtwj,
+                       kep_prec prec, const kep_options *opts, void *stream);
+
 /* The paper's separate-function form (Sec. 4.4, first of its two
    implementations; Sec. 5.3 measures it against the fused one): one call
    writes the velocity of every planet at every observation, a second forms

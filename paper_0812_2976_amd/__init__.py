@@ -12,6 +12,7 @@ Functions keep the C names:
   rv_chisq(t, v, sigma, P, K, e, ...)      chi-square (Eq. 5)
   rv_chisq_grad(...)                       chi-square and its gradient
   rv_nll_grad(...)                         likelihood with jitter and its gradient
+  rv_chisq_gn(...)                         Gauss-Newton products J^T W r, J^T W J (matrix cores)
   rv_planet_velocities / rv_chisq_from_velocities   the separate-function form
   RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
   DEMC(...)                                population sampler (DE-MC) on the batched chi-square
@@ -96,7 +97,7 @@ class KeplerError(RuntimeError):
 
 _LIB = None
 
-EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
+EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_chisq_gn", "rv_planet_velocities",
            "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
            "kep_plan_get_info", "kep_plan_destroy", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
            "kep_demc_plan_destroy", "astro_model", "astro_chisq", "kep_last_error", "kep_abi_version")
@@ -117,6 +118,7 @@ def load_library(path: str = LIB_PATH):
         getattr(L, name).argtypes = [P(KepObs), P(KepParams), _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_chisq_grad.argtypes = [P(KepObs), P(KepParams), _D, _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_nll_grad.argtypes = [P(KepObs), P(KepParams), _D, _D, ctypes.c_int, P(KepOptions), _D]
+    L.rv_chisq_gn.argtypes = [P(KepObs), P(KepParams), _D, _D, _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_planet_velocities.argtypes = [P(KepObs), P(KepParams), _D, P(KepOptions), _D]
     L.rv_chisq_from_velocities.argtypes = [P(KepObs), P(KepParams), _D, _D, P(KepOptions), _D]
     L.kep_plan_ragged.argtypes = [P(KepObsCSR), P(KepParamsCSR), ctypes.c_int, P(KepOptions), _D, P(_D)]
@@ -138,8 +140,8 @@ def load_library(path: str = LIB_PATH):
     L.kep_last_error.restype = ctypes.c_char_p
     L.kep_last_error.argtypes = []
     L.kep_abi_version.restype = ctypes.c_int
-    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_planet_velocities",
-                 "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
+    for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_chisq_gn",
+                 "rv_planet_velocities", "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
                  "kep_plan_get_info", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
                  "astro_model", "astro_chisq"):
         getattr(L, name).restype = ctypes.c_int
@@ -298,6 +300,21 @@ def rv_nll_grad(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.
     _check(L.rv_nll_grad(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), grad.data_ptr(), _prec(prec),
                          _opts(opts), _stream(dev)))
     return out, grad
+
+
+def rv_chisq_gn(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.0, prec="mixed", out=None,
+                jtwr=None, jtwj=None, opts=None):
+    """Gauss-Newton products: (chi2 (n_sys,), J^T W r (np, n_sys), J^T W J packed upper
+    triangle (np (np + 1) / 2, n_sys)), np = 5 n_pl + 1, entry (a, b), a <= b, at row
+    a np - a (a - 1) / 2 + (b - a)."""
+    obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
+    npar = 5 * par.n_pl + 1
+    out = _out(out, "out", (par.n_sys,), dev)
+    jtwr = _out(jtwr, "jtwr", (npar, par.n_sys), dev)
+    jtwj = _out(jtwj, "jtwj", (npar * (npar + 1) // 2, par.n_sys), dev)
+    _check(load_library().rv_chisq_gn(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), jtwr.data_ptr(),
+                                      jtwj.data_ptr(), _prec(prec), _opts(opts), _stream(dev)))
+    return out, jtwr, jtwj
 
 
 def rv_planet_velocities(t, P, K, e, omega, M0, t0=0.0, out=None, opts=None):

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkepler.so")
-SOURCES = ["kep_kernels.hip", "kep_demc.hip", "kep_astro.hip", "kep_api.cpp"]
+SOURCES = ["kep_kernels.hip", "kep_demc.hip", "kep_astro.hip", "kep_gn.hip", "kep_api.cpp"]
 ARCH = os.environ.get("KEP_OFFLOAD_ARCH", "gfx950")
 
 

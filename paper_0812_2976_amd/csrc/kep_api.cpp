@@ -205,6 +205,22 @@ kep_status rv_nll_grad(const kep_obs *obs, const kep_params *par, double *nll, d
     return dense_grad(obs, par, nll, grad, prec, opts, stream, true, "rv_nll_grad");
 }
 
+kep_status rv_chisq_gn(const kep_obs *obs, const kep_params *par, double *chi2, double *jtwr, double *jtwj,
+                       kep_prec prec, const kep_options *opts, void *stream)
+{
+    static const char *fn = "rv_chisq_gn";
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (kep_status s = check_dense(obs, par, true, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (o.shape.block != 0 && o.shape.block > 256) return fail(KEP_ERR_ARG, "%s: block_threads too large", fn);
+    if (par->n_sys == 0) return KEP_OK;
+    if (!chi2 || !jtwr || !jtwj) return fail(KEP_ERR_ARG, "%s: chi2, jtwr and jtwj must not be NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, chi2, nullptr);
+    return launch_status(kep::launch_gn(a, jtwr, jtwj, to_prec(prec), o.shape, (hipStream_t)stream), fn);
+}
+
 static kep_status astro_common(const kep_astro_obs *obs, const kep_astro_params *par, double *out, kep_prec prec,
                                const kep_options *opts, void *stream, bool model, const char *fn)
 {

@@ -1,0 +1,228 @@
+// Gauss-Newton products of the chi-square on the matrix cores: for each
+// system, with J the Jacobian of the model velocities (one row per
+// observation, one column per parameter P, K, e, omega, M0 of each planet and
+// the offset) and W = diag(1/(sigma^2 + s^2)),
+//   J^T W J (packed upper triangle),  J^T W r,  chi2 = r^T W r.
+// These feed Levenberg-Marquardt and Newton-type optimisers (the paper asks
+// for derivatives for optimisers, Sec. 6).  J^T W J is a dense contraction
+// over the observations, so it runs on MFMA: each lane (one observation)
+// forms its row of the augmented matrix sqrt(w) [J | 1 | r] in binary64 from
+// the implicit-function derivative terms of the adjoint (kep_grad.h) and
+// stores it in the wavefront's slice of LDS; the wavefront then accumulates
+// the upper-triangular 16 x 16 blocks of its Gram matrix with
+// v_mfma_f64_16x16x4_f64, four observations per instruction.  The augmented
+// column gives J^T W r and chi2 from the same products.
+#include <hip/hip_runtime.h>
+
+#include "kep_device.h"
+#include "kep_grad.h"
+#include "kep_internal.h"
+#include "kep_policy.h"
+
+namespace kep {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <bool MIXED> struct GNPlanet;
+template <> struct GNPlanet<true> {
+    GradPlanet<float> g;
+    double cP, ecw, Kcw, K, Kesw;   // 2 pi K / P, e cos w, K cos w, K, K e sin w
+};
+template <> struct GNPlanet<false> {
+    GradPlanet<double> g;
+};
+
+template <int NB>
+__host__ __device__ constexpr int gn_stride() { return 16 * NB + 1; }   // odd row length: staggers LDS banks
+
+template <bool MIXED, int NB>
+__host__ __device__ inline size_t gn_lds_per_wave()
+{
+    const size_t b = (size_t)64 * gn_stride<NB>() * sizeof(double) + (size_t)kMaxPl * sizeof(GNPlanet<MIXED>);
+    return (b + 15) & ~(size_t)15;
+}
+
+template <bool MIXED, int NB>
+__global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *jtwj)
+{
+    constexpr int NCOL = 16 * NB;
+    constexpr int STRIDE = gn_stride<NB>();
+    constexpr int NPAIR = NB * (NB + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = __lane_id();
+    const int wpb = blockDim.x >> 6;
+    const int wib = uniform_int(threadIdx.x >> 6);
+    unsigned char *mine = smem + (size_t)wib * gn_lds_per_wave<MIXED, NB>();
+    double *T = reinterpret_cast<double *>(mine);
+    GNPlanet<MIXED> *pl = reinterpret_cast<GNPlanet<MIXED> *>(mine + (size_t)64 * STRIDE * sizeof(double));
+
+    const int npl = a.n_pl;
+    const int np = 5 * npl + 1;
+    const int fixed = fixed64(a.fixed_iter);
+    const bool has_jit = a.jitter != nullptr;
+    const int n_chunks = (int)((a.n_obs + 63) / 64);
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    const double nan = __builtin_nan("");
+    double *row = T + lane * STRIDE;
+
+    for (int64_t sys = (int64_t)blockIdx.x * wpb + wib; sys < a.n_sys; sys += n_waves) {
+        wave_sync_lds();
+        bool pok = true;
+        if (lane < npl) {
+            const int64_t p = (int64_t)lane * a.n_sys + sys;
+            const double P = a.P[p], K = a.K[p], e = a.e[p], w = a.w[p], M0 = a.M0[p];
+            GNPlanet<MIXED> q;
+            pok = grad_setup(P, K, e, w, M0, a.fixed_iter, q.g);
+            if constexpr (MIXED) {
+                double sw, cw;
+                sincos(w, &sw, &cw);
+                q.cP = kTwoPi * K / P;
+                q.ecw = e * cw;
+                q.Kcw = K * cw;
+                q.K = K;
+                q.Kesw = K * e * sw;
+            }
+            pl[lane] = q;
+        }
+        const double gam = a.offset ? a.offset[sys] : 0.0;
+        const double jit = has_jit ? a.jitter[sys] : 0.0;
+        bool ok = isfinite(a.t0) && !__any(!pok);
+        if (a.offset) ok = ok && isfinite(gam);
+        if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
+        wave_sync_lds();
+
+        d4 acc[NPAIR];
+#pragma unroll
+        for (int p = 0; p < NPAIR; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
+        bool bad_obs = false;
+        for (int ch = 0; ch < n_chunks; ++ch) {
+            const int64_t k = (int64_t)ch * 64 + lane;
+            int c0 = 0;
+            if (k < a.n_obs) {
+                const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
+                const double var = sg * sg + jit * jit;
+                bool ook = isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0 && var > 0.0;
+                const double wgt = ook ? 1.0 / var : 0.0;
+                const double sw = sqrt(wgt);
+                const double tt = t - a.t0;
+                double model;
+                if constexpr (MIXED) {
+                    Kahan32 msum;
+                    msum.init();
+                    for (int j = 0; j < npl; ++j) {
+                        const GNPlanet<true> &q = pl[j];
+                        float x[5];
+                        msum.add(grad_terms(q.g, tt, a.max_iter, x));
+                        row[5 * j + 0] = sw * (q.cP * (double)x[0]);
+                        row[5 * j + 1] = sw * ((double)x[1] + q.ecw);
+                        row[5 * j + 2] = sw * (q.Kcw - q.K * (double)x[2]);
+                        row[5 * j + 3] = sw * (-q.K * (double)x[3] - q.Kesw);
+                        row[5 * j + 4] = sw * (-q.K * (double)x[4]);
+                    }
+                    model = (double)msum.s - (double)msum.c;
+                } else {
+                    model = 0.0;
+                    for (int j = 0; j < npl; ++j) {
+                        const GNPlanet<false> &q = pl[j];
+                        double d[5];
+                        model += grad_eval(q.g, tt, a.max_iter, fixed, d);
+#pragma unroll
+                        for (int i = 0; i < 5; ++i) row[5 * j + i] = sw * d[i];
+                    }
+                }
+                const double r = (model + gam) - vo;
+                row[np - 1] = sw;
+                row[np] = sw * r;
+                bad_obs = bad_obs || !ook;
+                c0 = np + 1;
+            }
+            for (int c = c0; c < NCOL; ++c) row[c] = 0.0;
+            wave_sync_lds();
+            // Gram matrix of the 64 rows: A operand lane l = row (4s + l/16),
+            // column (16 bi + l%16); the B operand reads the same pattern for bj.
+            const double *src = T + (lane >> 4) * STRIDE + (lane & 15);
+#pragma unroll 4
+            for (int s = 0; s < 16; ++s) {
+                double av[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) av[b] = src[4 * s * STRIDE + 16 * b];
+                int p = 0;
+#pragma unroll
+                for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+                    for (int bj = bi; bj < NB; ++bj) {
+                        acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], av[bj], acc[p], 0, 0, 0);
+                        ++p;
+                    }
+                }
+            }
+            wave_sync_lds();
+        }
+        ok = ok && !__any(bad_obs);
+
+        // lane l holds entry (16 bi + 4 (l/16) + q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
+        int p = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+            for (int bj = bi; bj < NB; ++bj) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 16 * bi + 4 * (lane >> 4) + q, j = 16 * bj + (lane & 15);
+                    const double val = ok ? acc[p][q] : nan;
+                    if (i <= j && j < np) jtwj[(int64_t)(i * np - i * (i - 1) / 2 + (j - i)) * a.n_sys + sys] = val;
+                    else if (j == np && i < np) jtwr[(int64_t)i * a.n_sys + sys] = val;
+                    else if (i == np && j == np) a.out[sys] = val;
+                }
+                ++p;
+            }
+        }
+    }
+}
+
+template <bool MIXED, int NB>
+hipError_t launch_gn_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+{
+    const size_t per_wave = gn_lds_per_wave<MIXED, NB>();
+    int wpb = shape.block > 0 ? shape.block / 64 : (int)((64 * 1024) / per_wave);
+    wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+    if ((size_t)wpb * per_wave > 64 * 1024) return hipErrorInvalidValue;
+    const size_t lds = (size_t)wpb * per_wave;
+    int per_cu = shape.blocks_per_cu;
+    if (per_cu <= 0) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gn<MIXED, NB>, wpb * 64, lds) != hipSuccess ||
+            occ <= 0)
+            occ = 1;
+        per_cu = occ;
+    }
+    int64_t grid = (a.n_sys + wpb - 1) / wpb;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    if (grid > cap) grid = cap;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_gn<MIXED, NB>), dim3((unsigned)grid), dim3(wpb * 64), lds, st, a, jtwr, jtwj);
+    return hipGetLastError();
+}
+
+template <bool MIXED>
+hipError_t launch_gn_p(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+{
+    const int ncol = 5 * a.n_pl + 2;   // parameters, offset, residual
+    if (ncol <= 16) return launch_gn_t<MIXED, 1>(a, jtwr, jtwj, shape, st);
+    if (ncol <= 32) return launch_gn_t<MIXED, 2>(a, jtwr, jtwj, shape, st);
+    if (ncol <= 48) return launch_gn_t<MIXED, 3>(a, jtwr, jtwj, shape, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_gn(DenseArgs a, double *jtwr, double *jtwj, Prec prec, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0) return hipSuccess;
+    return prec == Prec::Mixed ? launch_gn_p<true>(a, jtwr, jtwj, shape, st)
+                               : launch_gn_p<false>(a, jtwr, jtwj, shape, st);
+}
+
+}  // namespace kep

@@ -98,6 +98,8 @@ hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipSt
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
+// Gauss-Newton products: chi2 into a.out, J^T W r [np][n_sys], packed J^T W J
+hipError_t launch_gn(DenseArgs a, double *jtwr, double *jtwj, Prec prec, LaunchShape shape, hipStream_t st);
 // DE-MC: chi-square of the whole population (both halves; NaN where K < 0),
 // one generation (both halves), the device generation counter's setter and
 // increment.

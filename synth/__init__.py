@@ -88,10 +88,12 @@ def _planet_params(rng, n_pl, n_sys, e_lo, e_hi):
 
 
 def dense(name: str, n_sys: Optional[int] = None, seed: Optional[int] = None,
-          e_range=None, t0: float = 0.0, jitter: bool = False) -> DenseWorkload:
-    """Dense workload `name` (c0, c1, c2 or c4), optionally with fewer systems.
-    The observed velocities are not filled in: call with_observations()."""
-    n_sys0, n_pl, n_obs, e_max, sig_mode, with_off = DENSE[name]
+          e_range=None, t0: float = 0.0, jitter: bool = False, n_pl: Optional[int] = None) -> DenseWorkload:
+    """Dense workload `name` (c0, c1, c2 or c4), optionally with fewer systems or
+    another planet count (n_pl changes every draw after sigma).  The observed
+    velocities are not filled in: call with_observations()."""
+    n_sys0, n_pl0, n_obs, e_max, sig_mode, with_off = DENSE[name]
+    n_pl = n_pl0 if n_pl is None else int(n_pl)
     n_sys = n_sys0 if n_sys is None else int(n_sys)
     rng = np.random.Generator(np.random.PCG64(SEEDS[name] if seed is None else seed))
     e_lo, e_hi = (0.0, e_max) if e_range is None else e_range

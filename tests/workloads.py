@@ -23,8 +23,10 @@ def oracle_phase(t, t0, P):
 
 def dense(name, n_sys=None, n_obs=None, n_pl=None, seed=None, stress=False, jitter=False, t0=0.0, e_range=None):
     """Dense workload with observed velocities, optionally cut to n_obs / n_pl."""
-    wl = synth.dense(name, n_sys=n_sys, seed=seed, jitter=jitter, t0=t0, e_range=e_range)
-    if n_pl is not None:
+    more = n_pl is not None and n_pl > synth.DENSE[name][1]
+    wl = synth.dense(name, n_sys=n_sys, seed=seed, jitter=jitter, t0=t0, e_range=e_range,
+                     n_pl=n_pl if more else None)
+    if n_pl is not None and not more:
         wl.P, wl.K, wl.e, wl.w, wl.M0 = (np.ascontiguousarray(x[:n_pl]) for x in (wl.P, wl.K, wl.e, wl.w, wl.M0))
         wl.truth = {k: v[:n_pl] for k, v in wl.truth.items()}
     if n_obs is not None:
