@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
         }
         ok = ok && !__any(bad_obs);
 
-        // lane l holds entry (16 bi + 4 (l/16) + q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
+        // lane l holds entry (16 bi + l/16 + 4 q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
+        // (the binary64 16x16x4 product interleaves its output rows by four)
         int p = 0;
 #pragma unroll
         for (int bi = 0; bi < NB; ++bi) {
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
             for (int bj = bi; bj < NB; ++bj) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int i = 16 * bi + 4 * (lane >> 4) + q, j = 16 * bj + (lane & 15);
+                    const int i = 16 * bi + (lane >> 4) + 4 * q, j = 16 * bj + (lane & 15);
                     const double val = ok ? acc[p][q] : nan;
                     if (i <= j && j < np) jtwj[(int64_t)(i * np - i * (i - 1) / 2 + (j - i)) * a.n_sys + sys] = val;
                     else if (j == np && i < np) jtwr[(int64_t)i * a.n_sys + sys] = val;
