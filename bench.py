@@ -230,10 +230,24 @@ def main():
         gn = torch.empty((5 * w4.n_pl + 2, w4.n_sys), dtype=torch.float64, device=dev)
         jit = gpu(w4.jitter)
         msn, _ = timed(lambda: kp.rv_nll_grad(**g4, jitter=jit, prec="mixed", out=o4, grad=gn), 10, 2, torch)
+        npar = 5 * w4.n_pl + 1
+        jr = torch.empty((npar, w4.n_sys), dtype=torch.float64, device=dev)
+        jj = torch.empty((npar * (npar + 1) // 2, w4.n_sys), dtype=torch.float64, device=dev)
+        msgn, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="mixed", out=o4, jtwr=jr, jtwj=jj), 10, 2, torch)
+        msgn64, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="fp64", out=o4, jtwr=jr, jtwj=jj), 3, 1, torch)
+        # Gram matrix of sqrt(w)[J | 1 | r]: (np + 1)(np + 2)/2 multiply-adds per (system, observation)
+        useful = w4.n_sys * w4.t.size * (npar + 1) * (npar + 2)
+        nb = (npar + 1 + 15) // 16
+        issued = w4.n_sys * (w4.t.size // 4) * (nb * (nb + 1) // 2) * 2048
         result["gradient_c4"] = {"chi2_grad_per_s": w4.n_sys / (msg * 1e-3), "launch_ms": msg,
                                  "triples_per_s": w4.n_sys * 1024 / (msg * 1e-3),
-                                 "nll_grad_launch_ms": msn}
-        del g4, o4, gr, gn, jit
+                                 "nll_grad_launch_ms": msn,
+                                 "gauss_newton": {"launch_ms_mixed": msgn, "launch_ms_fp64": msgn64,
+                                                  "systems_per_s_mixed": w4.n_sys / (msgn * 1e-3),
+                                                  "gram_useful_tflops": useful / (msgn * 1e-3) / 1e12,
+                                                  "mfma_issued_tflops": issued / (msgn * 1e-3) / 1e12,
+                                                  "mfma_fp64_peak_tflops": 78.6}}
+        del g4, o4, gr, gn, jit, jr, jj
 
     # ------------------------------------------------------------ ragged
     if "ragged" in rows:
