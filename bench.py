@@ -37,8 +37,8 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # Algorithmic VALU operations per (system, planet, observation) triple of the
 # mixed-precision formulation (operation count of the method as written, each
 # add/mul/fma/fract/convert/compare/select/reciprocal/sine/cosine counted once):
-#   orbital phase in binary64: quotient and its correction 3, two fractions
-#     and the M0 offset 3, scale to [-pi, pi) 1, convert 1                  8
+#   orbital phase in binary64: (t - t0)/P + phase offset as one fused
+#     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4
 #   starting guess                                                         2
 #   each Danby step before the last: scale, hardware sin and cos 3,
 #     f and its three derivatives 5, three corrections 9, update 1        18
@@ -50,7 +50,7 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 # The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
 # with e ~ U[0, 0.9] the mean number of steps before the last is
 # 1 + (0.9 - 0.8525)/0.9 = 1.0528.
-OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 8, 2, 18, 39, 20, 12
+OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 18, 39, 20, 12
 
 
 def mixed_ops_per_triple(n_pl, mean_steps):
