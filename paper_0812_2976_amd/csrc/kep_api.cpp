@@ -583,7 +583,8 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
         tune_load_locked();
         bool found = false;
         for (auto &x : g_tune)
-            if (x.key == key) {
+            if (x.key == key && (x.gmax == 2 || x.gmax == 4) && (x.block == 64 || x.block == 128 || x.block == 256) &&
+                x.sb >= 1 && x.sb <= kep::kMaxSB && kep::ragged_shape_fits(x.block, x.sb)) {
                 best_block = x.block;
                 best_sb = x.sb;
                 best_gmax = x.gmax;
@@ -605,6 +606,7 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
             for (int gm : gmaxs)
                 for (int b : blocks)
                     for (int sb : sbs) {
+                        if (!kep::ragged_shape_fits(b, sb)) continue;
                         configure(b, sb, gm);
                         const double ms = time_candidate(p, st, 2);
                         if (ms < best) { best = ms; best_block = b; best_sb = sb; best_gmax = gm; }

@@ -97,6 +97,7 @@ hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStrea
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
+bool ragged_shape_fits(int block, int sb);   // LDS of the persistent kernel within 64 KiB per block
 hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 // Gauss-Newton products: chi2 into a.out, J^T W r [np][n_sys], packed J^T W J
 hipError_t launch_gn(DenseArgs a, double *jtwr, double *jtwj, Prec prec, LaunchShape shape, hipStream_t st);

@@ -405,7 +405,7 @@ __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed
         o[c].tt = t - a.t0;
         o[c].v = v;
         o[c].s2 = (float)(s * s);
-        o[c].w = (float)(1.0 / (s * s));
+        o[c].w = rcp32(o[c].s2);
     }
     PolMixed::ModelAcc m[NCH];
 #pragma unroll
@@ -420,18 +420,31 @@ __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed
     }
 }
 
+// LDS of one wavefront: planet records [sb][kMaxPl], per system (planet
+// count or its negative when the system is invalid, system index), first
+// planet offset [sb], per-planet domain flags [sb][kMaxPl].
+__host__ __device__ inline size_t ragged_lds_per_wave(int sb)
+{
+    const size_t b = (size_t)sb * kMaxPl * sizeof(RecMixed) + (size_t)sb * 2 * sizeof(int) +
+                     (size_t)sb * sizeof(int64_t) + (size_t)sb * kMaxPl * sizeof(int);
+    return (b + 15) & ~(size_t)15;
+}
+
 // GMAX: largest observation group in 64-lane chunks (2 or 4): fewer chunks in
 // flight need fewer registers and allow more resident waves; the plan's
-// autotuner picks it.
+// autotuner picks it.  Setup runs with the lanes over (system, planet) pairs,
+// so an item of sb systems with up to 8 planets each is set up in one pass.
 template <int GMAX>
 __global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = __lane_id();
-    const int wpb = blockDim.x >> 6;
     const int wib = uniform_int(threadIdx.x >> 6);
-    RecMixed *recs = reinterpret_cast<RecMixed *>(smem) + (size_t)wib * a.sb * kMaxPl;
-    int *meta = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * kMaxPl * sizeof(RecMixed)) + (size_t)wib * a.sb * 2;
+    unsigned char *mine = smem + (size_t)wib * ragged_lds_per_wave(a.sb);
+    RecMixed *recs = reinterpret_cast<RecMixed *>(mine);
+    int *meta = reinterpret_cast<int *>(mine + (size_t)a.sb * kMaxPl * sizeof(RecMixed));
+    int64_t *pofs = reinterpret_cast<int64_t *>(meta + 2 * a.sb);
+    int *okpl = reinterpret_cast<int *>(pofs + a.sb);
     const bool has_jit = a.jitter != nullptr;
 
     for (;;) {
@@ -445,19 +458,32 @@ __global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
         if (lane < nb) {
             const int64_t sys = a.order[i0 + lane];
             const int64_t p0 = a.pl_off[sys];
-            const int npl = (int)(a.pl_off[sys + 1] - p0);
-            bool ok = isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
-            DenseArgs dummy;
-            dummy.fixed_iter = a.fixed_iter;
-            for (int j = 0; j < npl && j < kMaxPl; ++j) {
+            meta[2 * lane] = (int)(a.pl_off[sys + 1] - p0);
+            meta[2 * lane + 1] = (int)sys;
+            pofs[lane] = p0;
+        }
+        wave_sync_lds();
+        DenseArgs dummy;
+        dummy.fixed_iter = a.fixed_iter;
+        for (int q = lane; q < nb * kMaxPl; q += 64) {
+            const int s = q / kMaxPl, j = q - s * kMaxPl;
+            if (j < meta[2 * s]) {
+                const int64_t p = pofs[s] + j;
                 RecMixed r;
-                ok = PolMixed::setup(dummy, a.P[p0 + j], a.K[p0 + j], a.e[p0 + j], a.w[p0 + j], a.M0[p0 + j], r) && ok;
-                recs[lane * kMaxPl + j] = r;
+                okpl[q] = PolMixed::setup(dummy, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r) ? 1 : 0;
+                recs[q] = r;
             }
+        }
+        wave_sync_lds();
+        if (lane < nb) {
+            const int npl = meta[2 * lane];
+            const int64_t sys = meta[2 * lane + 1];
+            bool ok = isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
+            for (int j = 0; j < kMaxPl; ++j)
+                if (j < npl) ok = ok && okpl[lane * kMaxPl + j] != 0;
             if (a.offset) ok = ok && isfinite(a.offset[sys]);
             if (a.jitter) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
             meta[2 * lane] = ok ? npl : -npl;
-            meta[2 * lane + 1] = (int)sys;
         }
         wave_sync_lds();
         for (int s = 0; s < nb; ++s) {
@@ -647,9 +673,10 @@ hipError_t launch_dense_grad(DenseArgs a, Prec prec, bool nll, LaunchShape shape
 
 static size_t ragged_lds(int block, int sb)
 {
-    const int wpb = block / 64;
-    return (size_t)wpb * sb * kMaxPl * sizeof(RecMixed) + (size_t)wpb * sb * 2 * sizeof(int);
+    return (size_t)(block / 64) * ragged_lds_per_wave(sb);
 }
+
+bool ragged_shape_fits(int block, int sb) { return ragged_lds(block, sb) <= 64 * 1024; }
 
 int ragged_max_grid(LaunchShape shape, int sb, int gmax)
 {
