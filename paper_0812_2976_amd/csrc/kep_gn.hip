@@ -66,6 +66,8 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
     const double nan = __builtin_nan("");
     double *row = T + lane * STRIDE;
+    // padding columns np + 1 .. NCOL - 1 stay zero for the whole launch
+    for (int c = np + 1; c < NCOL; ++c) row[c] = 0.0;
 
     for (int64_t sys = (int64_t)blockIdx.x * wpb + wib; sys < a.n_sys; sys += n_waves) {
         wave_sync_lds();
@@ -99,13 +101,13 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
         bool bad_obs = false;
         for (int ch = 0; ch < n_chunks; ++ch) {
             const int64_t k = (int64_t)ch * 64 + lane;
-            int c0 = 0;
             if (k < a.n_obs) {
                 const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
                 const double var = sg * sg + jit * jit;
                 bool ook = isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0 && var > 0.0;
-                const double wgt = ook ? 1.0 / var : 0.0;
-                const double sw = sqrt(wgt);
+                double sw;                                   // sqrt(w) = 1 / sqrt(sigma^2 + s^2)
+                if constexpr (MIXED) sw = ook ? (double)__builtin_amdgcn_rsqf((float)var) : 0.0;
+                else sw = ook ? sqrt(1.0 / var) : 0.0;
                 const double tt = t - a.t0;
                 double model;
                 if constexpr (MIXED) {
@@ -136,9 +138,9 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
                 row[np - 1] = sw;
                 row[np] = sw * r;
                 bad_obs = bad_obs || !ook;
-                c0 = np + 1;
+            } else {
+                for (int c = 0; c <= np; ++c) row[c] = 0.0;    // rows past the last observation
             }
-            for (int c = c0; c < NCOL; ++c) row[c] = 0.0;
             wave_sync_lds();
             // Gram matrix of the 64 rows: A operand lane l = row (4s + l/16),
             // column (16 bi + l%16); the B operand reads the same pattern for bj.
