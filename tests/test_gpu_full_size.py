@@ -1,0 +1,58 @@
+"""Parity at the full sizes the benchmark times, in its launch configuration, on
+systems sampled across each batch (the oracle computes them one by one):
+c4 (262,144 x 4 x 256) gradient, likelihood and Gauss-Newton products, and the
+astrometric batch (1,048,576 x 2 x 128 epochs).  Tolerances as in the per-path
+tests."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_0812_2976_amd as kp
+from tests import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(n, k=64):
+    return np.unique(np.r_[0, 1, n - 1, np.linspace(0, n - 1, k).astype(int)])
+
+
+def test_c4_full_size_sampled(dev):
+    wl = W.dense("c4", jitter=True)
+    g = W.to_gpu(wl, dev)
+    chi2, grad = (x.cpu().numpy() for x in kp.rv_chisq_grad(**g, prec="mixed"))
+    nll, gnll = (x.cpu().numpy() for x in kp.rv_nll_grad(**g, prec="mixed"))
+    c_gn, jtwr, jtwj = (x.cpu().numpy() for x in kp.rv_chisq_gn(**g, prec="mixed"))
+    d = W.oracle_dense(wl)
+    npar = 5 * wl.n_pl + 1
+    worst = dict(chi2=0.0, grad=0.0, nll=0.0, jtwj=0.0)
+    for i in _sample(wl.n_sys):
+        i = int(i)
+        c_ref, g_ref, s_r, s_1 = (x[..., i] for x in oracle.chisq_grad_scales(d, i, i + 1))
+        worst["chi2"] = max(worst["chi2"], W.rel_err_chi2(chi2[i], c_ref))
+        worst["grad"] = max(worst["grad"], np.max(np.abs(grad[:, i] - g_ref) / (1e-3 * s_1 + 1e-5 * s_r)))
+        n_ref, _ = (x[..., i] for x in oracle.nll_grad(d, i, i + 1))
+        logs = np.sum(np.abs(np.log(wl.sigma ** 2 + wl.jitter[i] ** 2)))
+        u = 2.0 ** -24
+        worst["nll"] = max(worst["nll"], abs(nll[i] - n_ref) / (1e-5 * max(c_ref, 1.0) + wl.t.size * 3 * u + 2 * u * logs))
+        _, r_ref, j_ref = (x[..., i] for x in oracle.gn(d, i, i + 1))
+        diag = np.array([j_ref[a * npar - a * (a - 1) // 2] for a in range(npar)])
+        scale = np.array([np.sqrt(diag[a] * diag[b]) for a in range(npar) for b in range(a, npar)])
+        worst["jtwj"] = max(worst["jtwj"], np.max(np.abs(jtwj[:, i] - j_ref) / scale))
+    print(f"[c4 full size, sampled] {worst}", flush=True)
+    assert worst["chi2"] <= 1e-5 and worst["grad"] <= 1.0 and worst["nll"] <= 1.0 and worst["jtwj"] <= 1e-5
+    assert np.all(np.isfinite(chi2)) and np.all(np.isfinite(jtwj))
+    assert np.max(np.abs(c_gn - chi2) / np.maximum(chi2, 1.0)) <= 2e-5
+
+
+def test_astro_full_size_sampled(dev):
+    wl = W.astro(1048576, 2, 128)
+    g = W.astro_to_gpu(wl, dev)
+    chi2 = kp.astro_chisq(**g, prec="mixed").cpu().numpy()
+    assert np.all(np.isfinite(chi2))
+    d = W.oracle_astro(wl)
+    idx = _sample(wl.n_sys, 96)
+    ref = np.array([oracle.astro_chisq(d, int(i), int(i) + 1)[i] for i in idx])
+    err = W.rel_err_chi2(chi2[idx], ref)
+    print(f"[astro full size, sampled] max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= 1e-8
