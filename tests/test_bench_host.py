@@ -1,0 +1,39 @@
+"""Host-side logic of the benchmark (no GPU): the one-GPU contract, the algorithmic
+operation count used for the roofline, and the guard that only reports recorded
+HBM traffic for the kernel sources it was measured on."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_before_any_gpu_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_operation_count_of_the_mixed_formulation():
+    """phase 4 + start 2 + 18 per early step (1.0528 of them at e ~ U[0, 0.9]) + last step 39
+    + velocity 20 + 12 per observation shared by 4 planets."""
+    steps = bench.mean_iterations(0.9)
+    assert abs(steps - (2.0 + (0.9 - 0.8525) / 0.9)) < 1e-12
+    assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 18 * (steps - 1) + 39 + 20 + 3)) < 1e-12
+
+
+def test_recorded_traffic_requires_a_matching_source_hash(tmp_path, monkeypatch):
+    assert bench.recorded_traffic("no_such_profile") is None
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "x_traffic.md").write_text(f"kernel_source_sha256: {h}\nhbm_bytes_per_launch: 1.5e+08\n")
+    (prof / "y_traffic.md").write_text("kernel_source_sha256: 0000000000000000\nhbm_bytes_per_launch: 1.5e+08\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    assert bench.recorded_traffic("x") == 1.5e8
+    assert bench.recorded_traffic("y") is None
