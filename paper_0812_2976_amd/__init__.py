@@ -430,6 +430,7 @@ class RaggedPlan:
 
     def close(self):
         if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)        # no replay of the plan's graph may still be running
             load_library().kep_plan_destroy(self._h)
             self._h = None
 
