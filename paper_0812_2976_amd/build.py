@@ -16,6 +16,11 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkepler.so")
 SOURCES = ["kep_kernels.hip", "kep_demc.hip", "kep_astro.hip", "kep_gn.hip", "kep_api.cpp"]
+# Per-source flags.  The Gauss-Newton kernel's matrix products accumulate in
+# ordinary VGPRs (gfx950 allows it): without this the compiler moves the
+# accumulators to AGPRs and back around every unrolled group of products and
+# waits for the products to finish each time.
+EXTRA = {"kep_gn.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 ARCH = os.environ.get("KEP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -39,7 +44,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(bdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"]
-        cmd = [hipcc()] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + flags() + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
