@@ -88,6 +88,7 @@ def test_demc_population_chisq(dev, prec):
     dict(n_pl=1, nh=2, n_obs=50, n_gen=6, jump_every=2),         # smallest population
     dict(n_pl=3, nh=64, n_obs=0, n_gen=4, jump_every=0),         # no observations: flat target
     dict(n_pl=2, nh=300, n_obs=100, n_gen=4, jump_every=0, jitter=True),
+    dict(n_pl=3, nh=128, n_obs=256, n_gen=3, jump_every=0),        # small population, four observation chunks
 ])
 def test_demc_generations_fp64_match_oracle(dev, case):
     t, v, sigma, x, eps, jit = _population(case["n_pl"], case["nh"], case["n_obs"], seed=case["nh"],
