@@ -368,6 +368,29 @@ def main():
         result["cpu_baseline"] = {"value": n / dt, "unit": "chi2 evals/s", "cores": cores, "kind": "oracle",
                                   "sample": f"first {n} systems of the same c2 batch ({n * 1024} Kepler solves), "
                                             f"{dt:.2f} s wall"}
+
+        # Accuracy of the timed mixed-precision kernels against the oracle, outside
+        # the timed region: chi2 of the same sample (the GPU given the oracle's
+        # observed velocities), model velocities of its first 256 systems, and
+        # standalone Kepler solves (uniform and periapsis-stress pairs).
+        part = {k: gpu(np.ascontiguousarray(getattr(wl, a)[:, :n])) for k, a in
+                (("P", "P"), ("K", "K"), ("e", "e"), ("omega", "w"), ("M0", "M0"))}
+        chi_g = kp.rv_chisq(gpu(wl.t), gpu(v_cpu), gpu(wl.sigma), **part, t0=wl.t0, prec="mixed").cpu().numpy()
+        m = min(256, n)
+        vm_g = kp.rv_model(gpu(wl.t), *(p[:, :m].contiguous() for p in part.values()), t0=wl.t0,
+                           prec="mixed").cpu().numpy()
+        vm_o = oracle.rv_model(oracle.Dense(wl.t, v_cpu, wl.sigma, *(np.ascontiguousarray(getattr(wl, a)[:, :m])
+                                                                    for a in ("P", "K", "e", "w", "M0")),
+                                            None, None, wl.t0))
+        acc = {"chi2_rel_max": float(np.max(np.abs(chi_g - out_c) / np.maximum(out_c, 1.0))),
+               "v_abs_max_mps": float(np.max(np.abs(vm_g - vm_o))),
+               "sample": f"chi2: first {n} systems of c2; velocities: first {m} systems x 256 epochs; "
+                         f"Kepler: 2^18 pairs each"}
+        for tag, stress in (("E_abs_max_rad", False), ("E_abs_max_rad_stress", True)):
+            Ms, es = synth.kepler_pairs(1 << 18, stress=stress)
+            E_g = kp.kepler_solve(gpu(Ms), gpu(es), prec="mixed").cpu().numpy()
+            acc[tag] = float(np.max(np.abs(E_g - oracle.kepler(Ms, es))))
+        result["accuracy_vs_oracle"] = acc
     print(json.dumps(result), flush=True)
 
 
