@@ -100,6 +100,29 @@ def timed(fn, steps, warmup, torch):
     return a.elapsed_time(b) / steps, wall
 
 
+def per_launch(fn, steps, torch):
+    """Milliseconds of each of `steps` calls of fn, each bracketed by its own pair of events."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -156,6 +179,18 @@ def main():
     triples = wl.n_sys * wl.n_pl * wl.n_obs
     value = wl.n_sys / (ms * 1e-3)
     log(f"mixed rv_chisq c2: {ms:.3f} ms/launch, {value:.4e} chi2/s")
+    each = per_launch(step, args.steps, torch)
+    # the same launch followed by the copy of the chi-square vector into pinned host memory
+    host = torch.empty(wl.n_sys, dtype=torch.float64, pin_memory=True)
+
+    def step_d2h():
+        step()
+        host.copy_(out, non_blocking=True)
+
+    ms_d2h, _ = timed(step_d2h, args.steps, args.warmup, torch)
+    launch_stats = {"mean_ms": ms, "median_ms": float(np.median(each)), "min_ms": float(np.min(each)),
+                    "max_ms": float(np.max(each)), "with_d2h_ms": ms_d2h,
+                    "with_d2h_chi2_per_s": wl.n_sys / (ms_d2h * 1e-3)}
     chi2 = out.cpu().numpy()
     if not np.all(np.isfinite(chi2)):
         raise RuntimeError("non-finite chi-square in the benchmark batch")
@@ -178,6 +213,7 @@ def main():
                    "n_sys": wl.n_sys, "n_pl": wl.n_pl, "n_obs": wl.n_obs, "precision": "mixed"},
         "kepler_solves_per_s": triples / (ms * 1e-3),
         "valu_peak_frac": round(achieved / peak, 4),
+        "launch_stats": launch_stats,
         "roofline": roofline,
     }
     del g, out
@@ -246,7 +282,9 @@ def main():
                                                   "systems_per_s_mixed": w4.n_sys / (msgn * 1e-3),
                                                   "gram_useful_tflops": useful / (msgn * 1e-3) / 1e12,
                                                   "mfma_issued_tflops": issued / (msgn * 1e-3) / 1e12,
-                                                  "mfma_fp64_peak_tflops": 78.6}}
+                                                  "mfma_dtype_mixed": "f32 (binary64 sums per 64 observations)",
+                                                  "mfma_f32_peak_tflops": 157.3,
+                                                  "mfma_frac_mixed": issued / (msgn * 1e-3) / 157.3e12}}
         del g4, o4, gr, gn, jit, jr, jj
 
     # ------------------------------------------------------------ ragged
@@ -365,9 +403,20 @@ def main():
         with ThreadPoolExecutor(cores) as ex:
             list(ex.map(lambda ab: oracle.chisq(d, int(ab[0]), int(ab[1]), out=out_c), zip(bounds[:-1], bounds[1:])))
         dt = time.perf_counter() - t0
+        # one thread, as the paper's CPU baseline ran, on a sixteenth of the sample
+        n1 = max(1, n // 16)
+        out_1 = np.full(n1, np.nan)
+        t1 = time.perf_counter()
+        oracle.chisq(d, 0, n1, out=out_1)
+        dt1 = time.perf_counter() - t1
+        if not np.array_equal(out_1, out_c[:n1], equal_nan=True):
+            raise RuntimeError("single-thread oracle run disagrees with the threaded run")
         result["cpu_baseline"] = {"value": n / dt, "unit": "chi2 evals/s", "cores": cores, "kind": "oracle",
                                   "sample": f"first {n} systems of the same c2 batch ({n * 1024} Kepler solves), "
-                                            f"{dt:.2f} s wall"}
+                                            f"{dt:.2f} s wall",
+                                  "single_thread": {"value": n1 / dt1, "sample": f"first {n1} systems, "
+                                                                                  f"{dt1:.2f} s"},
+                                  "host_cpu": host_cpu_model(), "host_cpus_online": os.cpu_count()}
 
         # Accuracy of the timed mixed-precision kernels against the oracle, outside
         # the timed region: chi2 of the same sample (the GPU given the oracle's

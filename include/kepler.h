@@ -158,8 +158,11 @@ kep_status rv_nll_grad(const kep_obs *obs, const kep_params *par, double *nll, d
                                     triangle, idx(a, b) = a np - a (a - 1)/2 + (b - a),
                                     np (np + 1)/2 rows.
    The jitter is a fixed input.  J is formed from the same implicit-function
-   derivative terms as rv_chisq_grad (binary32 terms in KEP_MIXED, binary64 in
-   KEP_FP64) and the products are accumulated in binary64 on the matrix cores.
+   derivative terms as rv_chisq_grad and the products run on the matrix cores:
+   KEP_FP64 with binary64 terms and binary64 products; KEP_MIXED with binary32
+   terms and binary32 products over each group of 64 observations, the groups
+   summed in binary64 (each entry within 64 x 2^-24 of the Cauchy-Schwarz
+   bound sqrt((J^T W J)_aa (J^T W J)_bb) from the product rounding).
    Domain and errors as rv_chisq_grad. */
 kep_status rv_chisq_gn(const kep_obs *obs, const kep_params *par, double *chi2, double *jtwr, double *jtwj,
                        kep_prec prec, const kep_options *opts, void *stream);

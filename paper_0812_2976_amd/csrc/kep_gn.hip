@@ -6,12 +6,19 @@
 // These feed Levenberg-Marquardt and Newton-type optimisers (the paper asks
 // for derivatives for optimisers, Sec. 6).  J^T W J is a dense contraction
 // over the observations, so it runs on MFMA: each lane (one observation)
-// forms its row of the augmented matrix sqrt(w) [J | 1 | r] in binary64 from
-// the implicit-function derivative terms of the adjoint (kep_grad.h) and
-// stores it in the wavefront's slice of LDS; the wavefront then accumulates
-// the upper-triangular 16 x 16 blocks of its Gram matrix with
-// v_mfma_f64_16x16x4_f64, four observations per instruction.  The augmented
-// column gives J^T W r and chi2 from the same products.
+// forms its row of the augmented matrix sqrt(w) [J | 1 | r] from the
+// implicit-function derivative terms of the adjoint (kep_grad.h) and stores it
+// in the wavefront's slice of LDS; the wavefront then accumulates the
+// upper-triangular 16 x 16 blocks of its Gram matrix, four observations per
+// product.  The augmented column gives J^T W r and chi2 from the same products.
+//
+// binary64 path (k_gn64): rows in binary64, v_mfma_f64_16x16x4_f64.
+// Mixed path (k_gn32): rows in binary32 (the derivative terms are binary32
+// already), v_mfma_f32_16x16x4_f32 over each group of 64 observations, and
+// each group's sums added into binary64 accumulators, so one rounding error
+// spans at most 64 terms.  The binary32 tile halves the LDS per wavefront
+// (more resident wavefronts) and the binary32 products issue at twice the
+// binary64 rate.
 #include <hip/hip_runtime.h>
 
 #include "kep_device.h"
@@ -24,39 +31,43 @@ namespace kep {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <bool MIXED> struct GNPlanet;
-template <> struct GNPlanet<true> {
-    GradPlanet<float> g;
-    double cP, ecw, Kcw, K, Kesw;   // 2 pi K / P, e cos w, K cos w, K, K e sin w
-};
-template <> struct GNPlanet<false> {
-    GradPlanet<double> g;
-};
+// Stores block (bi, bj) of the Gram matrix of sqrt(w) [J | 1 | r]: the packed
+// upper triangle of J^T W J, J^T W r from the last column, chi2 from the
+// corner.  (i, j) is this lane's entry q of the block.
+__device__ __forceinline__ void gn_store(const DenseArgs &a, double *jtwr, double *jtwj, int64_t sys, int np, int i,
+                                         int j, double val)
+{
+    if (i <= j && j < np) jtwj[(int64_t)(i * np - i * (i - 1) / 2 + (j - i)) * a.n_sys + sys] = val;
+    else if (j == np && i < np) jtwr[(int64_t)i * a.n_sys + sys] = val;
+    else if (i == np && j == np) a.out[sys] = val;
+}
+
+// ------------------------------------------------------------------ binary64
+template <int NB>
+__host__ __device__ constexpr int gn64_stride() { return 16 * NB + 1; }   // odd row length: staggers LDS banks
 
 template <int NB>
-__host__ __device__ constexpr int gn_stride() { return 16 * NB + 1; }   // odd row length: staggers LDS banks
-
-template <bool MIXED, int NB>
-__host__ __device__ inline size_t gn_lds_per_wave()
+__host__ __device__ inline size_t gn64_lds_per_wave()
 {
-    const size_t b = (size_t)64 * gn_stride<NB>() * sizeof(double) + (size_t)kMaxPl * sizeof(GNPlanet<MIXED>);
+    const size_t b = (size_t)64 * gn64_stride<NB>() * sizeof(double) + (size_t)kMaxPl * sizeof(GradPlanet<double>);
     return (b + 15) & ~(size_t)15;
 }
 
-template <bool MIXED, int NB>
-__global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *jtwj)
+template <int NB>
+__global__ void __launch_bounds__(256) k_gn64(DenseArgs a, double *jtwr, double *jtwj)
 {
     constexpr int NCOL = 16 * NB;
-    constexpr int STRIDE = gn_stride<NB>();
+    constexpr int STRIDE = gn64_stride<NB>();
     constexpr int NPAIR = NB * (NB + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = __lane_id();
     const int wpb = blockDim.x >> 6;
     const int wib = uniform_int(threadIdx.x >> 6);
-    unsigned char *mine = smem + (size_t)wib * gn_lds_per_wave<MIXED, NB>();
+    unsigned char *mine = smem + (size_t)wib * gn64_lds_per_wave<NB>();
     double *T = reinterpret_cast<double *>(mine);
-    GNPlanet<MIXED> *pl = reinterpret_cast<GNPlanet<MIXED> *>(mine + (size_t)64 * STRIDE * sizeof(double));
+    GradPlanet<double> *pl = reinterpret_cast<GradPlanet<double> *>(mine + (size_t)64 * STRIDE * sizeof(double));
 
     const int npl = a.n_pl;
     const int np = 5 * npl + 1;
@@ -74,18 +85,8 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
         bool pok = true;
         if (lane < npl) {
             const int64_t p = (int64_t)lane * a.n_sys + sys;
-            const double P = a.P[p], K = a.K[p], e = a.e[p], w = a.w[p], M0 = a.M0[p];
-            GNPlanet<MIXED> q;
-            pok = grad_setup(P, K, e, w, M0, a.fixed_iter, q.g);
-            if constexpr (MIXED) {
-                double sw, cw;
-                sincos(w, &sw, &cw);
-                q.cP = kTwoPi * K / P;
-                q.ecw = e * cw;
-                q.Kcw = K * cw;
-                q.K = K;
-                q.Kesw = K * e * sw;
-            }
+            GradPlanet<double> q;
+            pok = grad_setup(a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], a.fixed_iter, q);
             pl[lane] = q;
         }
         const double gam = a.offset ? a.offset[sys] : 0.0;
@@ -105,34 +106,14 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
                 const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
                 const double var = sg * sg + jit * jit;
                 bool ook = isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0 && var > 0.0;
-                double sw;                                   // sqrt(w) = 1 / sqrt(sigma^2 + s^2)
-                if constexpr (MIXED) sw = ook ? (double)__builtin_amdgcn_rsqf((float)var) : 0.0;
-                else sw = ook ? sqrt(1.0 / var) : 0.0;
+                const double sw = ook ? sqrt(1.0 / var) : 0.0;   // sqrt(w) = 1 / sqrt(sigma^2 + s^2)
                 const double tt = t - a.t0;
-                double model;
-                if constexpr (MIXED) {
-                    Kahan32 msum;
-                    msum.init();
-                    for (int j = 0; j < npl; ++j) {
-                        const GNPlanet<true> &q = pl[j];
-                        float x[5];
-                        msum.add(grad_terms(q.g, tt, a.max_iter, x));
-                        row[5 * j + 0] = sw * (q.cP * (double)x[0]);
-                        row[5 * j + 1] = sw * ((double)x[1] + q.ecw);
-                        row[5 * j + 2] = sw * (q.Kcw - q.K * (double)x[2]);
-                        row[5 * j + 3] = sw * (-q.K * (double)x[3] - q.Kesw);
-                        row[5 * j + 4] = sw * (-q.K * (double)x[4]);
-                    }
-                    model = (double)msum.s - (double)msum.c;
-                } else {
-                    model = 0.0;
-                    for (int j = 0; j < npl; ++j) {
-                        const GNPlanet<false> &q = pl[j];
-                        double d[5];
-                        model += grad_eval(q.g, tt, a.max_iter, fixed, d);
+                double model = 0.0;
+                for (int j = 0; j < npl; ++j) {
+                    double d[5];
+                    model += grad_eval(pl[j], tt, a.max_iter, fixed, d);
 #pragma unroll
-                        for (int i = 0; i < 5; ++i) row[5 * j + i] = sw * d[i];
-                    }
+                    for (int i = 0; i < 5; ++i) row[5 * j + i] = sw * d[i];
                 }
                 const double r = (model + gam) - vo;
                 row[np - 1] = sw;
@@ -172,23 +153,170 @@ __global__ void __launch_bounds__(256) k_gn(DenseArgs a, double *jtwr, double *j
 #pragma unroll
             for (int bj = bi; bj < NB; ++bj) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = 16 * bi + (lane >> 4) + 4 * q, j = 16 * bj + (lane & 15);
-                    const double val = ok ? acc[p][q] : nan;
-                    if (i <= j && j < np) jtwj[(int64_t)(i * np - i * (i - 1) / 2 + (j - i)) * a.n_sys + sys] = val;
-                    else if (j == np && i < np) jtwr[(int64_t)i * a.n_sys + sys] = val;
-                    else if (i == np && j == np) a.out[sys] = val;
-                }
+                for (int q = 0; q < 4; ++q)
+                    gn_store(a, jtwr, jtwj, sys, np, 16 * bi + (lane >> 4) + 4 * q, 16 * bj + (lane & 15),
+                             ok ? acc[p][q] : nan);
                 ++p;
             }
         }
     }
 }
 
-template <bool MIXED, int NB>
-hipError_t launch_gn_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+// ------------------------------------------------------------------ mixed
+struct GNPlanet32 {
+    GradPlanet<float> g;
+    float cP, ecw, Kcw, K, Kesw;   // 2 pi K / P, e cos w, K cos w, K, K e sin w
+};
+
+// The tile is column-major, T[c * kGn32Col + obs]: a lane writes its row with
+// unit stride across the wavefront, and the matrix operands are read as runs
+// of four consecutive observations (128-bit loads).  Observation 16 g + s of
+// the group feeds step s of lane group g = l/16: the Gram matrix sums over all
+// observations, so any fixed assignment of observations to (step, k) slots,
+// the same for both operands, gives the same products.
+constexpr int kGn32Col = 68;   // 64 observations + 4: consecutive columns start 4 banks apart
+
+template <int NB>
+__host__ __device__ inline size_t gn32_lds_per_wave()
 {
-    const size_t per_wave = gn_lds_per_wave<MIXED, NB>();
+    const size_t b = (size_t)16 * NB * kGn32Col * sizeof(float) + (size_t)kMaxPl * sizeof(GNPlanet32);
+    return (b + 15) & ~(size_t)15;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_gn32(DenseArgs a, double *jtwr, double *jtwj)
+{
+    constexpr int NCOL = 16 * NB;
+    constexpr int NPAIR = NB * (NB + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = __lane_id();
+    const int wpb = blockDim.x >> 6;
+    const int wib = uniform_int(threadIdx.x >> 6);
+    unsigned char *mine = smem + (size_t)wib * gn32_lds_per_wave<NB>();
+    float *T = reinterpret_cast<float *>(mine);
+    GNPlanet32 *pl = reinterpret_cast<GNPlanet32 *>(mine + (size_t)NCOL * kGn32Col * sizeof(float));
+
+    const int npl = a.n_pl;
+    const int np = 5 * npl + 1;
+    const bool has_jit = a.jitter != nullptr;
+    const int n_chunks = (int)((a.n_obs + 63) / 64);
+    const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    const double nan = __builtin_nan("");
+    float *col = T + lane;                       // this lane's observation in column 0
+    // padding columns np + 1 .. NCOL - 1 stay zero for the whole launch
+    for (int c = np + 1; c < NCOL; ++c) col[c * kGn32Col] = 0.0f;
+
+    for (int64_t sys = (int64_t)blockIdx.x * wpb + wib; sys < a.n_sys; sys += n_waves) {
+        wave_sync_lds();
+        bool pok = true;
+        if (lane < npl) {
+            const int64_t p = (int64_t)lane * a.n_sys + sys;
+            const double P = a.P[p], K = a.K[p], e = a.e[p], w = a.w[p], M0 = a.M0[p];
+            GNPlanet32 q;
+            pok = grad_setup(P, K, e, w, M0, a.fixed_iter, q.g);
+            double sw, cw;
+            sincos(w, &sw, &cw);
+            q.cP = (float)(kTwoPi * K / P);
+            q.ecw = (float)(e * cw);
+            q.Kcw = (float)(K * cw);
+            q.K = (float)K;
+            q.Kesw = (float)(K * e * sw);
+            pl[lane] = q;
+        }
+        const double gam = a.offset ? a.offset[sys] : 0.0;
+        const double jit = has_jit ? a.jitter[sys] : 0.0;
+        bool ok = isfinite(a.t0) && !__any(!pok);
+        if (a.offset) ok = ok && isfinite(gam);
+        if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
+        wave_sync_lds();
+
+        d4 acc[NPAIR];
+#pragma unroll
+        for (int p = 0; p < NPAIR; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
+        bool bad_obs = false;
+        for (int ch = 0; ch < n_chunks; ++ch) {
+            const int64_t k = (int64_t)ch * 64 + lane;
+            if (k < a.n_obs) {
+                const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
+                const double var = sg * sg + jit * jit;
+                bool ook = isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0 && var > 0.0;
+                const float sw = ook ? __builtin_amdgcn_rsqf((float)var) : 0.0f;   // sqrt(w)
+                const double tt = t - a.t0;
+                Kahan32 msum;
+                msum.init();
+                for (int j = 0; j < npl; ++j) {
+                    const GNPlanet32 &q = pl[j];
+                    float x[5];
+                    msum.add(grad_terms(q.g, tt, a.max_iter, x));
+                    float *c = col + 5 * j * kGn32Col;
+                    c[0 * kGn32Col] = sw * (q.cP * x[0]);
+                    c[1 * kGn32Col] = sw * (x[1] + q.ecw);
+                    c[2 * kGn32Col] = sw * fmaf(-q.K, x[2], q.Kcw);
+                    c[3 * kGn32Col] = -sw * fmaf(q.K, x[3], q.Kesw);
+                    c[4 * kGn32Col] = -sw * (q.K * x[4]);
+                }
+                const double r = (((double)msum.s - (double)msum.c) + gam) - vo;   // residual in binary64
+                col[(np - 1) * kGn32Col] = sw;
+                col[np * kGn32Col] = sw * (float)r;
+                bad_obs = bad_obs || !ook;
+            } else {
+                for (int c = 0; c <= np; ++c) col[c * kGn32Col] = 0.0f;   // rows past the last observation
+            }
+            wave_sync_lds();
+            // A operand of step s, lane l: column 16 bi + l%16, observation 16 (l/16) + s;
+            // the B operand reads the same pattern for bj.
+            const float *src = T + (lane & 15) * kGn32Col + 16 * (lane >> 4);
+            f4 accf[NPAIR];
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p) accf[p] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                f4 av[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    av[b] = *reinterpret_cast<const f4 *>(src + 16 * b * kGn32Col + 4 * s4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    int p = 0;
+#pragma unroll
+                    for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+                        for (int bj = bi; bj < NB; ++bj) {
+                            accf[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi][u], av[bj][u], accf[p], 0, 0, 0);
+                            ++p;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] += (double)accf[p][q];
+            wave_sync_lds();
+        }
+        ok = ok && !__any(bad_obs);
+
+        // lane l holds entry (16 bi + 4 (l/16) + q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
+        // (the binary32 16x16x4 product keeps four consecutive output rows per lane)
+        int p = 0;
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+            for (int bj = bi; bj < NB; ++bj) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    gn_store(a, jtwr, jtwj, sys, np, 16 * bi + 4 * (lane >> 4) + q, 16 * bj + (lane & 15),
+                             ok ? acc[p][q] : nan);
+                ++p;
+            }
+        }
+    }
+}
+
+template <class KernelFn>
+hipError_t launch_gn_k(KernelFn kern, size_t per_wave, DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape,
+                       hipStream_t st)
+{
     int wpb = shape.block > 0 ? shape.block / 64 : (int)((64 * 1024) / per_wave);
     wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
     if ((size_t)wpb * per_wave > 64 * 1024) return hipErrorInvalidValue;
@@ -196,8 +324,7 @@ hipError_t launch_gn_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shap
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gn<MIXED, NB>, wpb * 64, lds) != hipSuccess ||
-            occ <= 0)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, wpb * 64, lds) != hipSuccess || occ <= 0)
             occ = 1;
         per_cu = occ;
     }
@@ -205,18 +332,15 @@ hipError_t launch_gn_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shap
     const int64_t cap = (int64_t)device_cu_count() * per_cu;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((k_gn<MIXED, NB>), dim3((unsigned)grid), dim3(wpb * 64), lds, st, a, jtwr, jtwj);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(wpb * 64), lds, st, a, jtwr, jtwj);
     return hipGetLastError();
 }
 
-template <bool MIXED>
-hipError_t launch_gn_p(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+template <int NB>
+hipError_t launch_gn_t(bool mixed, DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
 {
-    const int ncol = 5 * a.n_pl + 2;   // parameters, offset, residual
-    if (ncol <= 16) return launch_gn_t<MIXED, 1>(a, jtwr, jtwj, shape, st);
-    if (ncol <= 32) return launch_gn_t<MIXED, 2>(a, jtwr, jtwj, shape, st);
-    if (ncol <= 48) return launch_gn_t<MIXED, 3>(a, jtwr, jtwj, shape, st);
-    return hipErrorInvalidValue;
+    return mixed ? launch_gn_k(k_gn32<NB>, gn32_lds_per_wave<NB>(), a, jtwr, jtwj, shape, st)
+                 : launch_gn_k(k_gn64<NB>, gn64_lds_per_wave<NB>(), a, jtwr, jtwj, shape, st);
 }
 
 }  // namespace
@@ -224,8 +348,12 @@ hipError_t launch_gn_p(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shap
 hipError_t launch_gn(DenseArgs a, double *jtwr, double *jtwj, Prec prec, LaunchShape shape, hipStream_t st)
 {
     if (a.n_sys <= 0) return hipSuccess;
-    return prec == Prec::Mixed ? launch_gn_p<true>(a, jtwr, jtwj, shape, st)
-                               : launch_gn_p<false>(a, jtwr, jtwj, shape, st);
+    const bool mixed = prec == Prec::Mixed;
+    const int ncol = 5 * a.n_pl + 2;   // parameters, offset, residual
+    if (ncol <= 16) return launch_gn_t<1>(mixed, a, jtwr, jtwj, shape, st);
+    if (ncol <= 32) return launch_gn_t<2>(mixed, a, jtwr, jtwj, shape, st);
+    if (ncol <= 48) return launch_gn_t<3>(mixed, a, jtwr, jtwj, shape, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace kep
