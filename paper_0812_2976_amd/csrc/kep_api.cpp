@@ -524,9 +524,23 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
         work[i] = np * std::max<int64_t>(no, 1);
         triples += np * no;
     }
+    // work order: decreasing work (n_pl x n_obs), so the smallest items come
+    // last; then, within each window of kOrderWindow systems, by planet count,
+    // so that the systems of one work item mostly share a planet count (their
+    // packed tails then run the same number of planet iterations) while
+    // consecutive items still alternate between planet counts (a whole launch
+    // phase of one-planet systems, whose per-observation loads weigh most,
+    // measured 7% slower at c3)
+    constexpr size_t kOrderWindow = 256;
     std::vector<int32_t> order(n_sys);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    for (size_t w0 = 0; w0 < order.size(); w0 += kOrderWindow) {
+        const auto e = order.begin() + (ptrdiff_t)std::min(order.size(), w0 + kOrderWindow);
+        std::stable_sort(order.begin() + (ptrdiff_t)w0, e, [&](int32_t a, int32_t b) {
+            return poff[a + 1] - poff[a] > poff[b + 1] - poff[b];
+        });
+    }
 
     kep_plan *p = new kep_plan();
     p->n_obs_total = obs->n_obs_total;

@@ -378,11 +378,17 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 }
 
 // ------------------------------------------------------------------ ragged
-// Persistent kernel over CSR systems.  Work items are runs of `sb` systems in
-// decreasing order of work; each wavefront takes the next item from an
-// atomic counter until the items run out.  Setup runs one lane per system of
-// the item; evaluation runs one system at a time with lanes over that
-// system's observations, in groups of up to 4 x 64 loaded with coalesced reads.
+// Persistent kernel over CSR systems.  Work items are runs of `sb` systems of
+// the plan's work order (decreasing work, grouped by planet count within
+// short windows); each wavefront takes the next item from an atomic counter
+// until the items run out.  Setup runs with the lanes over the item's (system, planet) pairs.
+// Each system's whole groups of 64 observations are evaluated one system at a
+// time with the lanes over its observations (uniform planet records, groups
+// of up to 4 x 64 loaded with coalesced reads).  The remaining n_obs mod 64
+// observations of all the item's systems are then packed back to back into
+// one stream of lanes, each lane with its own system's planet records, and a
+// segmented scan over each group of 64 lanes returns every system's share: a
+// system's last partial group no longer leaves the rest of its wavefront idle.
 struct RecRagged {
     RecMixed pl[kMaxPl];
 };
@@ -420,31 +426,50 @@ __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed
     }
 }
 
-// LDS of one wavefront: planet records [sb][kMaxPl], per system (planet
-// count or its negative when the system is invalid, system index), first
-// planet offset [sb], per-planet domain flags [sb][kMaxPl].
+// One planet's velocity (the arithmetic of PolMixed::add_planet) from this
+// lane's own planet record: lanes of different systems differ in step count.
+__device__ __forceinline__ float ragged_vel_lane(const RecMixed &r, double tt, int max_iter)
+{
+    const float M = mean_anomaly32(tt, r.ph);
+    float s, omc;
+    kepler32(M, r.k, r.niter, max_iter, r.check != 0, s, omc);
+    const float D = fmaf(r.k.e, omc, r.k.ome);           // 1 - e cos E
+    const float num = fmaf(r.B, s, fmaf(-r.A, omc, r.A));  // A cos E + B sin E
+    return num * rcp32(D);
+}
+
+// LDS of one wavefront for sb systems: planet records [sb][kMaxPl]; per
+// system the first planet offset, the global index of its first tail
+// observation and its chi-square so far; (code, system) pairs [sb][2], where
+// code is the planet count, negative for an invalid system; per-planet domain
+// flags [sb][kMaxPl]; prefix sums of the tail lengths [sb + 1]; bad-data flags [sb].
 __host__ __device__ inline size_t ragged_lds_per_wave(int sb)
 {
-    const size_t b = (size_t)sb * kMaxPl * sizeof(RecMixed) + (size_t)sb * 2 * sizeof(int) +
-                     (size_t)sb * sizeof(int64_t) + (size_t)sb * kMaxPl * sizeof(int);
+    const size_t b = (size_t)sb * kMaxPl * sizeof(RecMixed) + (size_t)sb * 2 * sizeof(int64_t) +
+                     (size_t)sb * sizeof(double) + (size_t)sb * 2 * sizeof(int) + (size_t)sb * kMaxPl * sizeof(int) +
+                     (size_t)(sb + 1) * sizeof(int) + (size_t)sb * sizeof(int);
     return (b + 15) & ~(size_t)15;
 }
 
 // GMAX: largest observation group in 64-lane chunks (2 or 4): fewer chunks in
 // flight need fewer registers and allow more resident waves; the plan's
-// autotuner picks it.  Setup runs with the lanes over (system, planet) pairs,
-// so an item of sb systems with up to 8 planets each is set up in one pass.
+// autotuner picks it.
 template <int GMAX>
-__global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX == 2 ? 4 : 3))) k_ragged_mixed(RaggedArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = __lane_id();
     const int wib = uniform_int(threadIdx.x >> 6);
-    unsigned char *mine = smem + (size_t)wib * ragged_lds_per_wave(a.sb);
+    const int sb = a.sb;
+    unsigned char *mine = smem + (size_t)wib * ragged_lds_per_wave(sb);
     RecMixed *recs = reinterpret_cast<RecMixed *>(mine);
-    int *meta = reinterpret_cast<int *>(mine + (size_t)a.sb * kMaxPl * sizeof(RecMixed));
-    int64_t *pofs = reinterpret_cast<int64_t *>(meta + 2 * a.sb);
-    int *okpl = reinterpret_cast<int *>(pofs + a.sb);
+    int64_t *pofs = reinterpret_cast<int64_t *>(recs + sb * kMaxPl);
+    int64_t *tail0 = pofs + sb;
+    double *acc = reinterpret_cast<double *>(tail0 + sb);
+    int *meta = reinterpret_cast<int *>(acc + sb);
+    int *okpl = meta + 2 * sb;
+    int *tpre = okpl + sb * kMaxPl;
+    int *bad = tpre + sb + 1;
     const bool has_jit = a.jitter != nullptr;
 
     for (;;) {
@@ -452,16 +477,31 @@ __global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
         if (lane == 0) item = atomicAdd(a.queue, 1u);
         item = (unsigned int)uniform_int((int)__shfl(item, 0, 64));
         if ((int64_t)item >= a.n_items) break;
-        const int64_t i0 = (int64_t)item * a.sb;
-        const int nb = (int)min((int64_t)a.sb, a.n_sys - i0);
+        const int64_t i0 = (int64_t)item * sb;
+        const int nb = (int)min((int64_t)sb, a.n_sys - i0);
         wave_sync_lds();
+        int rem = 0;
         if (lane < nb) {
             const int64_t sys = a.order[i0 + lane];
             const int64_t p0 = a.pl_off[sys];
+            const int64_t o0 = a.obs_off[sys], n = a.obs_off[sys + 1] - o0;
             meta[2 * lane] = (int)(a.pl_off[sys + 1] - p0);
             meta[2 * lane + 1] = (int)sys;
             pofs[lane] = p0;
+            rem = (int)(n & 63);
+            tail0[lane] = o0 + (n - rem);
+            acc[lane] = 0.0;
+            bad[lane] = 0;
         }
+        // prefix sums of the tail lengths over the item's systems
+        int incl = rem;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += u;
+        }
+        if (lane < nb) tpre[lane + 1] = incl;
+        if (lane == 0) tpre[0] = 0;
+        const int ntail = uniform_int(__shfl(incl, nb - 1, 64));
         wave_sync_lds();
         DenseArgs dummy;
         dummy.fixed_iter = a.fixed_iter;
@@ -486,28 +526,113 @@ __global__ void __launch_bounds__(256) k_ragged_mixed(RaggedArgs a)
             meta[2 * lane] = ok ? npl : -npl;
         }
         wave_sync_lds();
+        // whole groups of 64 observations, one system at a time
         for (int s = 0; s < nb; ++s) {
             const int code = uniform_int(meta[2 * s]);
+            if (code <= 0) continue;                   // invalid: NaN, nothing to evaluate
             const int64_t sys = uniform_int(meta[2 * s + 1]);
-            const int npl = code < 0 ? -code : code;
             const int64_t o0 = a.obs_off[sys];
-            const int64_t n = a.obs_off[sys + 1] - o0;
+            const int64_t nfull = (a.obs_off[sys + 1] - o0) & ~(int64_t)63;
+            if (nfull == 0) continue;
             const double gam = a.offset ? a.offset[sys] : 0.0;
             const double jit = a.jitter ? a.jitter[sys] : 0.0;
+            const RecMixed *rs = recs + s * kMaxPl;
             Kahan32 chi;
             chi.init();
             bool bad_obs = false;
-            for (int64_t g = 0; g < n; g += 64 * GMAX) {
-                const int64_t rem = n - g;
-                const RecMixed *rs = recs + s * kMaxPl;
-                if (rem <= 64) ragged_group<1>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
-                else if (GMAX == 2 || rem <= 128) ragged_group<2>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
-                else if (rem <= 192) ragged_group<3>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
-                else ragged_group<GMAX>(a, rs, npl, o0 + g, rem, gam, jit, has_jit, chi, bad_obs);
+            for (int64_t g = 0; g < nfull; g += 64 * GMAX) {
+                const int64_t left = nfull - g;
+                if (left <= 64) ragged_group<1>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
+                else if (GMAX == 2 || left <= 128) ragged_group<2>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
+                else if (left <= 192) ragged_group<3>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
+                else ragged_group<GMAX>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
             }
             const double tot = wave_sum(chi.value());
-            const bool bad = code <= 0 || __any(bad_obs);
-            if (lane == 0) a.out[sys] = bad ? __builtin_nan("") : tot;
+            const bool b = __any(bad_obs);
+            if (lane == 0) {
+                acc[s] = tot;
+                bad[s] = b ? 1 : 0;
+            }
+        }
+        wave_sync_lds();
+        // the packed tails: lane position p of the stream belongs to system s
+        // with tpre[s] <= p < tpre[s + 1].  Positions only grow along the
+        // stream, so each lane moves its system cursor forward; the next
+        // group's observations are loaded before the current group is
+        // evaluated.
+        if (ntail > 0) {
+            int s = 0;
+            auto seek = [&](int pos) {
+                while (s + 1 < nb && tpre[s + 1] <= pos) ++s;
+            };
+            auto fetch = [&](int pos, bool in, double &t, double &v, double &sg) {
+                t = a.t0;
+                v = 0.0;
+                sg = 1.0;
+                if (in && meta[2 * s] > 0) {
+                    const int64_t k = tail0[s] + (pos - tpre[s]);
+                    t = a.t[k];
+                    v = a.v[k];
+                    sg = a.sigma[k];
+                }
+            };
+            bool in = lane < ntail;
+            int pp = in ? lane : ntail - 1;
+            seek(pp);
+            double t, v, sg;
+            fetch(pp, in, t, v, sg);
+            for (int c0 = 0; c0 < ntail; c0 += 64) {
+                const int sc = s;
+                const bool inc = in;
+                const double tc = t, vc = v, sgc = sg;
+                if (c0 + 64 < ntail) {                  // next group: cursor and loads
+                    in = c0 + 64 + lane < ntail;
+                    pp = in ? c0 + 64 + lane : ntail - 1;
+                    seek(pp);
+                    fetch(pp, in, t, v, sg);
+                }
+                const int code = meta[2 * sc];
+                const int npl = inc && code > 0 ? code : 0;
+                double x = 0.0;
+                if (npl > 0) {
+                    const int64_t sys = meta[2 * sc + 1];
+                    ObsMixed o;
+                    o.in = true;
+                    o.ok = isfinite(tc) && isfinite(vc) && isfinite(sgc) && sgc >= 0.0;
+                    o.tt = tc - a.t0;
+                    o.v = vc;
+                    o.s2 = (float)(sgc * sgc);
+                    o.w = rcp32(o.s2);
+                    PolMixed::ModelAcc m;
+                    PolMixed::model_init(m);
+                    const RecMixed *rs = recs + sc * kMaxPl;
+                    for (int j = 0; j < npl; ++j) m.k.add(ragged_vel_lane(rs[j], o.tt, a.max_iter));
+                    const double gam = a.offset ? a.offset[sys] : 0.0;
+                    const double jit = a.jitter ? a.jitter[sys] : 0.0;
+                    Kahan32 cx;
+                    cx.init();
+                    const bool okw = PolMixed::chi_add(cx, m, o, gam, jit, has_jit);
+                    x = cx.value();
+                    if (!okw || !o.ok) bad[sc] = 1;     // every writer stores the same value
+                }
+                // segmented scan: a lane adds only partial sums that start inside
+                // its own system's run of lanes (from `head`), so the lane that
+                // ends the run holds that system's share of this group, and a
+                // non-finite value stays within its own system
+                const int head = max(tpre[sc] - c0, 0);
+                const int last = min(tpre[sc + 1] - c0, 64) - 1;
+                double sum = x;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const double u = __shfl_up(sum, d, 64);
+                    if (lane - d >= head) sum += u;
+                }
+                if (inc && lane == last && code > 0) acc[sc] += sum;
+                wave_sync_lds();
+            }
+        }
+        if (lane < nb) {
+            const int code = meta[2 * lane];
+            a.out[meta[2 * lane + 1]] = (code <= 0 || bad[lane] != 0) ? __builtin_nan("") : acc[lane];
         }
     }
 }

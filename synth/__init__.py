@@ -178,12 +178,18 @@ class RaggedWorkload:
 
 
 def ragged(n_sys: int = 262144, seed: Optional[int] = None, n_pl_max: int = 7,
-           n_obs_range=(16, 1024), uniform=None, e_max: float = 0.9) -> RaggedWorkload:
+           n_obs_range=(16, 1024), uniform=None, e_max: float = 0.9, sizes=None) -> RaggedWorkload:
     """CSR ragged workload c3: n_pl ~ U{1..n_pl_max}, n_obs = round(exp U[ln lo, ln hi]),
     each system with its own sorted times and sigma ~ U[1, 5].  uniform=(n_pl, n_obs)
-    makes every system the same size (for the ragged-equals-dense check)."""
+    makes every system the same size (for the ragged-equals-dense check);
+    sizes=(n_pl array, n_obs array) gives every system's size explicitly."""
     rng = np.random.Generator(np.random.PCG64(SEEDS["c3"] if seed is None else seed))
-    if uniform is None:
+    if sizes is not None:
+        n_pl = np.asarray(sizes[0], dtype=np.int64)
+        n_obs = np.asarray(sizes[1], dtype=np.int64)
+        if n_pl.shape != (n_sys,) or n_obs.shape != (n_sys,):
+            raise ValueError("sizes must hold n_sys planet counts and n_sys observation counts")
+    elif uniform is None:
         n_pl = rng.integers(1, n_pl_max + 1, size=n_sys)
         lo, hi = n_obs_range
         n_obs = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), size=n_sys))).astype(np.int64)

@@ -115,6 +115,105 @@ def test_ragged_domain_nan_and_edge_sizes(dev):
     assert W.rel_err_chi2(chi2[~bad], ref[~bad]).max() <= 1e-5
 
 
+# observation counts around the 64-lane group boundaries, zero included: the
+# kernel evaluates whole groups of 64 per system and packs the remainders of a
+# work item's systems into one stream of lanes
+_EDGE_NOBS = np.array([0, 1, 2, 31, 33, 40, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257, 300, 1000])
+
+
+def _edge_batch(n_sys, seed):
+    rng = np.random.default_rng(seed)
+    n_obs = _EDGE_NOBS[rng.integers(0, _EDGE_NOBS.size, n_sys)]
+    n_pl = rng.integers(1, 9, n_sys)
+    rw = synth.ragged(n_sys=n_sys, seed=seed, sizes=(n_pl, n_obs))
+    synth.ragged_with_observations(rw, W.oracle_truth_model)
+    rw.offset = rng.uniform(-10, 10, n_sys)
+    # invalid data: a non-finite sigma in the partial last group of one system,
+    # in a whole group of another, and a planet outside the domain in a system
+    # that fits in one partial group
+    sizes = np.diff(rw.obs_off)
+    tail_sys = int(np.nonzero((sizes > 64) & (sizes % 64 != 0))[0][0])
+    full_sys = int(np.nonzero(sizes >= 64)[0][-1])
+    small_sys = int(np.nonzero((sizes > 0) & (sizes < 64))[0][1])
+    rw.sigma = rw.sigma.copy()
+    rw.sigma[rw.obs_off[tail_sys + 1] - 1] = np.nan
+    rw.sigma[rw.obs_off[full_sys]] = np.inf
+    rw.e = rw.e.copy()
+    rw.e[rw.pl_off[small_sys + 1] - 1] = 1.5
+    return rw, {tail_sys, full_sys, small_sys}
+
+
+def _check_edge(chi2, rw, invalid):
+    ref = _oracle(rw)
+    bad = np.isnan(ref)
+    assert set(np.nonzero(bad)[0]) == invalid
+    assert np.array_equal(np.isnan(chi2), bad)
+    empty = np.diff(rw.obs_off) == 0
+    assert np.all(chi2[empty & ~bad] == 0.0)
+    ok = ~bad
+    return bool(np.all(np.abs(chi2[ok] - ref[ok]) <= W.chi2_tol_mixed_ragged(rw, ref)[ok]))
+
+
+def test_ragged_packed_tails_edges(dev):
+    """Observation counts on both sides of every group boundary (0 to 1000),
+    one to eight planets, offsets and invalid systems whose bad value sits in a
+    packed tail, a whole group or a one-group system: NaN exactly where the
+    oracle has it, the oracle's value elsewhere."""
+    rw, invalid = _edge_batch(700, seed=41)
+    plan = _plan(rw, dev)
+    assert _check_edge(plan().cpu().numpy(), rw, invalid)
+    assert _check_edge(plan.direct().cpu().numpy(), rw, invalid)
+    for block in (64, 256):
+        assert _check_edge(_plan(rw, dev, opts=dict(block_threads=block))().cpu().numpy(), rw, invalid)
+
+
+_SHAPES_SCRIPT = r"""
+import json, sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+from tests import test_gpu_ragged as T
+res = []
+for n in (300, 600, 1200):
+    rw, invalid = T._edge_batch(n, seed=n)
+    plan = T._plan(rw, torch.device("cuda", 0))
+    ok = T._check_edge(plan().cpu().numpy(), rw, invalid)
+    res.append(dict(ok=ok, info=plan.info()))
+print(json.dumps(res))
+"""
+
+
+def test_ragged_forced_launch_shapes(dev, tmp_path):
+    """Every work-item layout the autotuner can choose gives the oracle's values:
+    a first process tunes three batches and stores their shapes in
+    KEP_TUNE_CACHE; the file is rewritten to force one system per item (64
+    threads, two groups in flight), 32 systems per item (four groups) and 16
+    per item (256 threads), and a second process runs the batches with them."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    env = dict(os.environ, KEP_TUNE_CACHE=str(cache))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def run():
+        r = subprocess.run([sys.executable, "-c", _SHAPES_SCRIPT, root], env=env, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = run()
+    assert all(x["ok"] for x in first), first
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 3
+    forced = [(64, 1, 2), (128, 32, 4), (256, 16, 2)]
+    cache.write_text("".join(f"{ln.split()[0]} {b} {sb} {g} 1.0\n" for ln, (b, sb, g) in zip(lines, forced)))
+    second = run()
+    for x, (b, sb, g) in zip(second, forced):
+        assert x["ok"], x
+        assert (x["info"]["block_threads"], x["info"]["sys_per_batch"], x["info"]["group_chunks"]) == (b, sb, g)
+
+
 def test_ragged_rejects_bad_offsets(dev):
     rw = _ragged(10, seed=2)
     rw.pl_off = rw.pl_off.copy()
