@@ -239,7 +239,7 @@ def main():
 
     # ------------------------------------------------------------ separate-function form
     if "separate" in rows:
-        log("separate-function form on c2 (per-planet velocities to HBM, then chi-square)")
+        log("separate-function form on c2 (per-planet velocities to HBM, then chi-square; Kepler's equation only)")
         g2 = dict(t=gpu(wl.t), v=gpu(wl.v), sigma=gpu(wl.sigma), P=gpu(wl.P), K=gpu(wl.K), e=gpu(wl.e),
                   omega=gpu(wl.w), M0=gpu(wl.M0))
         dv = torch.empty((wl.n_pl, wl.n_sys, wl.n_obs), dtype=torch.float32, device=dev)
@@ -248,10 +248,17 @@ def main():
                                                        out=dv), 5, 1, torch)
         msb, _ = timed(lambda: kp.rv_chisq_from_velocities(g2["t"], g2["v"], g2["sigma"], dv, out=o2), 10, 2, torch)
         dv_bytes = dv.numel() * 4
+        # Kepler's equation only: every eccentric anomaly written (into the same buffer)
+        mse, _ = timed(lambda: kp.rv_eccentric_anomalies(g2["t"], g2["P"], g2["K"], g2["e"], g2["omega"], g2["M0"],
+                                                         out=dv), 5, 1, torch)
         result["separate_c2"] = {"chi2_per_s": wl.n_sys / ((msa + msb) * 1e-3), "velocities_ms": msa,
                                  "chisq_ms": msb, "intermediate_GB": dv_bytes / 1e9,
                                  "chisq_hbm_GBps": (dv_bytes + wl.n_sys * 8) / (msb * 1e-3) / 1e9,
-                                 "time_vs_fused": (msa + msb) / ms}
+                                 "time_vs_fused": (msa + msb) / ms,
+                                 "kepler_only": {"launch_ms": mse, "solves_per_s": dv.numel() / (mse * 1e-3),
+                                                 "written_GB": dv_bytes / 1e9,
+                                                 "hbm_write_GBps": dv_bytes / (mse * 1e-3) / 1e9,
+                                                 "time_vs_fused_chisq": mse / ms}}
         del g2, dv, o2
 
     # ------------------------------------------------------------ gradient

@@ -184,6 +184,22 @@ kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float
 kep_status rv_chisq_from_velocities(const kep_obs *obs, const kep_params *par, const float *dv, double *chi2,
                                     const kep_options *opts, void *stream);
 
+/* Kepler's equation only, for every (system, planet, observation): the
+   paper's first mixed-precision use of the GPU (Sec. 5.2), which returned
+   the n_sys x n_pl x n_obs solutions instead of the chi-square.
+   E[(j * n_sys + i) * n_obs + k] (binary32, caller-owned device array of
+   n_pl * n_sys * n_obs floats, observations contiguous) is the eccentric
+   anomaly of planet j of system i at t_k: the mean anomaly of Eq. 4 formed in
+   binary64 and reduced to [-pi, pi) (Eq. 6 with the binary64 bracket of
+   Sec. 5.1), then the binary32 Danby iteration of KEP_MIXED, so
+   E lies in [-pi, pi] and differs by a multiple of 2 pi from the root for the
+   mean anomaly taken in [0, 2 pi).  obs->v and obs->sigma are not read; K
+   and omega only enter the domain check.  A system outside the domain gets
+   NaN, as does an observation with a non-finite time.  Mixed precision only;
+   errors as rv_chisq. */
+kep_status rv_eccentric_anomalies(const kep_obs *obs, const kep_params *par, float *E, const kep_options *opts,
+                                  void *stream);
+
 /* ---- astrometric Keplerian model (Thiele-Innes form) ----
    The star's reflex offset on the sky from the same phase (Eq. 4) and Kepler
    solve (Eq. 1): per planet X = cos E - e, Y = sqrt(1 - e^2) sin E and

@@ -14,6 +14,7 @@ Functions keep the C names:
   rv_nll_grad(...)                         likelihood with jitter and its gradient
   rv_chisq_gn(...)                         Gauss-Newton products J^T W r, J^T W J (matrix cores)
   rv_planet_velocities / rv_chisq_from_velocities   the separate-function form
+  rv_eccentric_anomalies(...)              Kepler's equation only, every (planet, system, time)
   RaggedPlan(...)                          CSR batches, persistent kernel + HIP graph
   DEMC(...)                                population sampler (DE-MC) on the batched chi-square
   astro_model / astro_chisq                astrometric Keplerian model (Thiele-Innes form)
@@ -98,7 +99,7 @@ class KeplerError(RuntimeError):
 _LIB = None
 
 EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_chisq_gn", "rv_planet_velocities",
-           "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
+           "rv_chisq_from_velocities", "rv_eccentric_anomalies", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
            "kep_plan_get_info", "kep_plan_destroy", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
            "kep_demc_plan_destroy", "astro_model", "astro_chisq", "kep_last_error", "kep_abi_version")
 
@@ -121,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     L.rv_chisq_gn.argtypes = [P(KepObs), P(KepParams), _D, _D, _D, ctypes.c_int, P(KepOptions), _D]
     L.rv_planet_velocities.argtypes = [P(KepObs), P(KepParams), _D, P(KepOptions), _D]
     L.rv_chisq_from_velocities.argtypes = [P(KepObs), P(KepParams), _D, _D, P(KepOptions), _D]
+    L.rv_eccentric_anomalies.argtypes = [P(KepObs), P(KepParams), _D, P(KepOptions), _D]
     L.kep_plan_ragged.argtypes = [P(KepObsCSR), P(KepParamsCSR), ctypes.c_int, P(KepOptions), _D, P(_D)]
     L.rv_chisq_ragged.argtypes = [_D, _D, _D]
     L.rv_chisq_ragged_direct.argtypes = [_D, _D, _D]
@@ -141,7 +143,8 @@ def load_library(path: str = LIB_PATH):
     L.kep_last_error.argtypes = []
     L.kep_abi_version.restype = ctypes.c_int
     for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_chisq_gn",
-                 "rv_planet_velocities", "rv_chisq_from_velocities", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
+                 "rv_planet_velocities", "rv_chisq_from_velocities", "rv_eccentric_anomalies", "kep_plan_ragged",
+                 "rv_chisq_ragged", "rv_chisq_ragged_direct",
                  "kep_plan_get_info", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
                  "astro_model", "astro_chisq"):
         getattr(L, name).restype = ctypes.c_int
@@ -324,6 +327,16 @@ def rv_planet_velocities(t, P, K, e, omega, M0, t0=0.0, out=None, opts=None):
     out = _out(out, "out", (par.n_pl, par.n_sys, obs.n_obs), dev, torch.float32)
     _check(load_library().rv_planet_velocities(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _opts(opts),
                                                _stream(dev)))
+    return out
+
+
+def rv_eccentric_anomalies(t, P, K, e, omega, M0, t0=0.0, out=None, opts=None):
+    """Every planet's eccentric anomaly (n_pl, n_sys, n_obs) in binary32, in [-pi, pi]
+    (Kepler's equation only, mixed precision)."""
+    obs, par, keep, dev = _obs_params(t, None, None, P, K, e, omega, M0, None, None, t0)
+    out = _out(out, "out", (par.n_pl, par.n_sys, obs.n_obs), dev, torch.float32)
+    _check(load_library().rv_eccentric_anomalies(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _opts(opts),
+                                                 _stream(dev)))
     return out
 
 

@@ -296,6 +296,22 @@ kep_status rv_planet_velocities(const kep_obs *obs, const kep_params *par, float
     return launch_status(kep::launch_planet_velocities(a, o.shape, (hipStream_t)stream), fn);
 }
 
+kep_status rv_eccentric_anomalies(const kep_obs *obs, const kep_params *par, float *E, const kep_options *opts,
+                                  void *stream)
+{
+    static const char *fn = "rv_eccentric_anomalies";
+    if (kep_status s = check_dense(obs, par, false, fn)) return s;
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    if (par->n_sys == 0 || obs->n_obs == 0) return KEP_OK;
+    if (!E) return fail(KEP_ERR_ARG, "%s: E is NULL", fn);
+    if (mul_overflows(par->n_sys * par->n_pl, obs->n_obs)) return fail(KEP_ERR_SHAPE, "%s: n_pl x n_sys x n_obs overflows", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::DenseArgs a = make_dense(obs, par, o, nullptr, nullptr);
+    a.dv = E;
+    return launch_status(kep::launch_eccentric_anomalies(a, o.shape, (hipStream_t)stream), fn);
+}
+
 kep_status rv_chisq_from_velocities(const kep_obs *obs, const kep_params *par, const float *dv, double *chi2,
                                     const kep_options *opts, void *stream)
 {

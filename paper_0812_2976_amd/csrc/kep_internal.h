@@ -19,7 +19,7 @@ struct DenseArgs {
     int sb;            // systems per setup batch of one wavefront (1..kMaxSB)
     double *out;       // chi2 [n_sys] or model [n_sys][n_obs]
     double *grad;      // gradient [(5 n_pl + 1 (+1 for the likelihood))][n_sys] (gradient kernels only)
-    float *dv;         // per-planet velocities [n_pl][n_sys][n_obs] (separate-function form)
+    float *dv;         // per-planet velocities or eccentric anomalies [n_pl][n_sys][n_obs]
     int fixed_iter;    // > 0: fixed Danby count; <= 0: eccentricity schedule
     int max_iter;      // cap of the convergence-tested loop
 };
@@ -100,6 +100,7 @@ int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 bool ragged_shape_fits(int block, int sb);   // LDS of the persistent kernel within 64 KiB per block
 hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 // Gauss-Newton products: chi2 into a.out, J^T W r [np][n_sys], packed J^T W J
+hipError_t launch_eccentric_anomalies(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_gn(DenseArgs a, double *jtwr, double *jtwj, Prec prec, LaunchShape shape, hipStream_t st);
 // DE-MC: chi-square of the whole population (both halves; NaN where K < 0),
 // one generation (both halves), the device generation counter's setter and

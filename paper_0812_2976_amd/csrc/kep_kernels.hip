@@ -92,6 +92,24 @@ __global__ void __launch_bounds__(256) k_dense(DenseArgs a)
             bool bad_obs = false;
             for (int g = g_first; g < g_end; ++g) {
                 if (n_groups > 1) load_group(g);
+                if constexpr (MODE == kAnomalies) {
+                    for (int j = 0; j < a.n_pl; ++j) {
+                        const Rec &rr = recs[s * a.n_pl + j];
+                        const int niter = uniform_int(rr.niter);
+                        float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            float sE, omcE;
+                            const float E = kepler32(mean_anomaly32(o[c].tt, rr.ph), rr.k, niter, a.max_iter,
+                                                     rr.check != 0, sE, omcE);
+                            if (o[c].in) {
+                                const int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
+                                row[k] = (sbad || !o[c].ok) ? __builtin_nanf("") : E;
+                            }
+                        }
+                    }
+                    continue;
+                }
                 ModelAcc m[NCH];
                 if (MODE == kPlanets) {
                     for (int j = 0; j < a.n_pl; ++j) {
@@ -734,6 +752,12 @@ hipError_t launch_planet_velocities(DenseArgs a, LaunchShape shape, hipStream_t 
 {
     if (a.n_sys <= 0 || a.n_obs <= 0) return hipSuccess;
     return launch_dense_t<PolMixed, kPlanets>(a, shape, st);
+}
+
+hipError_t launch_eccentric_anomalies(DenseArgs a, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0 || a.n_obs <= 0) return hipSuccess;
+    return launch_dense_t<PolMixed, kAnomalies>(a, shape, st);
 }
 
 hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStream_t st)

@@ -284,8 +284,11 @@ __device__ __forceinline__ void pol_add_planet(const typename Pol::Rec &r, const
 
 // Dense kernel.  MODE kChi2: chi-square per system; kModel: model velocities
 // [n_sys][n_obs]; kPlanets: every planet's velocity [n_pl][n_sys][n_obs] in
-// binary32 (the paper's separate-function form, Sec. 4.4, first implementation).
-enum { kChi2 = 0, kModel = 1, kPlanets = 2 };
+// binary32 (the paper's separate-function form, Sec. 4.4, first implementation);
+// kAnomalies: every planet's eccentric anomaly [n_pl][n_sys][n_obs] in binary32
+// (the paper's first mixed-precision use of the GPU, Kepler's equation only,
+// Sec. 5.2; mixed policy only).
+enum { kChi2 = 0, kModel = 1, kPlanets = 2, kAnomalies = 3 };
 
 
 }  // namespace kep
