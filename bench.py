@@ -42,15 +42,17 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 #   starting guess                                                         2
 #   each Danby step before the last: scale, hardware sin and cos 3,
 #     f and its three derivatives 5, three corrections 9, update 1        18
-#   last Danby step: sin, 1 - cos, E - sin E with folding 23, f and its
-#     three derivatives 5, three corrections 9, update and step 2         39
+#   last Danby step: sin, 1 - cos, E - sin E from the unfolded polynomials
+#     on |E| <= 3.25 (square 1, two degree-5 polynomials 10, cube, three
+#     products 4) 15, f and its three derivatives 5, three corrections 9,
+#     update and step 2                                                    31
 #   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20
 #   per observation: binary64 residual 6, weighted square 2,
 #     Kahan chi-square 4 -> 12 / n_pl
 # The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
 # with e ~ U[0, 0.9] the mean number of steps before the last is
 # 1 + (0.9 - 0.8525)/0.9 = 1.0528.
-OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 18, 39, 20, 12
+OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 18, 31, 20, 12
 
 
 def mixed_ops_per_triple(n_pl, mean_steps):

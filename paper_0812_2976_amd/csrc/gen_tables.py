@@ -8,6 +8,11 @@
    precision near periapsis (E -> 0), where Kepler's function
    f(E) = (1-e) E + e (E - sin E) - M and its slope (1-e) + e (1 - cos E)
    would otherwise cancel catastrophically for e close to 1.
+   A second pair, one degree higher, covers |x| <= 3.25 without folding the
+   argument: the last step of the eccentricity schedule starts within
+   0.015 rad of a root in [-pi, pi] (item 2's scan), so |E| <= 3.143 there.
+   Its binary32 coefficients are rounded one at a time from the constant
+   term up, the remaining ones refitted after each rounding.
 
 2. Iteration schedules for Danby's quartic iteration started from the paper's
    guess E0 = M + 0.85 e sign(M) (Sec. 4.3) on a centred M in [-pi, pi]:
@@ -58,6 +63,44 @@ def fit_relative_minimax(target, grid, deg, iters=40):
     return c32, err32
 
 
+def fit_relative_minimax_f32(target, grid, deg, iters=40):
+    """As fit_relative_minimax, with the coefficients rounded to binary32 one at
+    a time from the constant term up and the others refitted to the residual."""
+    V = np.vander(grid, deg + 1, increasing=True)
+    fixed = []
+    for k in range(deg + 1):
+        resid = target - (V[:, :k] @ np.array(fixed) if k else 0.0)
+        Vr = V[:, k:]
+        w = np.ones_like(grid)
+        for _ in range(iters):
+            W = np.sqrt(w) / target
+            c, *_ = np.linalg.lstsq(Vr * W[:, None], resid * W, rcond=None)
+            err = np.abs(Vr @ c - resid) / target
+            w = w * (err + 1e-30)
+            w /= w.sum()
+        fixed.append(float(np.float32(c[0])))
+    c32 = np.array(fixed, dtype=np.float32)
+    return c32, np.max(np.abs(V @ c32.astype(np.float64) - target) / target)
+
+
+def last_step_reach(n_list=(2, 3, 4, 5), bands=None):
+    """Largest |E| and distance to the root before the last step of the schedule."""
+    M = np.concatenate([np.linspace(-np.pi, np.pi, 20001),
+                        np.outer([-1.0, 1.0], np.logspace(-10, 0, 2001)).ravel()])
+    far, reach = 0.0, 0.0
+    for n, (lo, hi) in bands.items():
+        for e in np.linspace(lo, hi, 60):
+            E = M + 0.85 * e * np.sign(M)
+            for _ in range(n - 1):
+                E = _danby_step(E, e, M)
+            R = E.copy()
+            for _ in range(10):
+                R = _danby_step(R, e, M)
+            far = max(far, float(np.max(np.abs(E - R))))
+            reach = max(reach, float(np.max(np.abs(E))))
+    return far, reach
+
+
 def danby_errors(e, M, n_max):
     """Worst |E_n - E*| over the M grid after n Danby steps (float64, n = 1..n_max)."""
     ld = np.longdouble
@@ -106,10 +149,17 @@ def main():
     grid = np.linspace(0.0, ymax, 3001)
     p, ep = fit_relative_minimax(_exact(_p_exact, grid), grid, 4)
     q, eq = fit_relative_minimax(_exact(_q_exact, grid), grid, 4)
+    wmax = 3.25
+    gridw = np.linspace(0.0, wmax * wmax, 3001)
+    pw, epw = fit_relative_minimax_f32(_exact(_p_exact, gridw), gridw, 5)
+    qw, eqw = fit_relative_minimax_f32(_exact(_q_exact, gridw), gridw, 5)
     pi_hi = np.float32(np.pi)
     pi_lo = np.float32(float(mp.pi - mp.mpf(float(pi_hi))))
     s32 = schedule(1e-9)
     s64 = schedule(1e-15)
+    bands = {2: (0.0, s32[2]), 3: (s32[2], s32[3]), 4: (s32[3], s32[4]), 5: (s32[4], s32[5])}
+    far, reach = last_step_reach(bands=bands)
+    assert reach < wmax, (reach, wmax)
     lines = [
         "// Generated by gen_tables.py -- do not edit by hand.",
         "#pragma once",
@@ -118,6 +168,14 @@ def main():
         f"// max relative error with float coefficients: p {ep:.2e}, q {eq:.2e}).",
     ]
     for name, c in (("KEP_P", p), ("KEP_Q", q)):
+        for i, v in enumerate(c):
+            lines.append(f"#define {name}{i} {float(v)!r}f")
+    lines += [
+        f"// The same on |x| <= {wmax} without folding (one degree higher; max relative error",
+        f"// p {epw:.2e}, q {eqw:.2e}): the last step of the schedule starts at most {far:.3f} rad",
+        f"// from the root, at |E| <= {reach:.4f}.",
+    ]
+    for name, c in (("KEP_PW", pw), ("KEP_QW", qw)):
         for i, v in enumerate(c):
             lines.append(f"#define {name}{i} {float(v)!r}f")
     lines += [

@@ -89,6 +89,24 @@ __device__ __forceinline__ SinCos32 sincos32(float x)
     return r;
 }
 
+// The same three values for |x| <= 3.25 without folding the argument (the
+// wider-range polynomials, one degree higher).  Valid for the last step of the
+// eccentricity schedule, which starts within 0.015 rad of a root in
+// [-pi, pi]; near +-pi, sin x = x - (x - sin x) keeps an absolute error of a
+// few ulp of pi (the velocity needs no more).
+__device__ __forceinline__ SinCos32 sincos32_wide(float x)
+{
+    const float x2 = x * x;
+    const float p = fmaf(fmaf(fmaf(fmaf(fmaf(KEP_PW5, x2, KEP_PW4), x2, KEP_PW3), x2, KEP_PW2), x2, KEP_PW1), x2, KEP_PW0);
+    const float q = fmaf(fmaf(fmaf(fmaf(fmaf(KEP_QW5, x2, KEP_QW4), x2, KEP_QW3), x2, KEP_QW2), x2, KEP_QW1), x2, KEP_QW0);
+    const float x3 = x * x2;
+    SinCos32 r;
+    r.xms = x3 * p;
+    r.s = fmaf(-x3, p, x);
+    r.omc = x2 * q;
+    return r;
+}
+
 // Per-planet eccentricity constants of the binary32 Kepler step: e, 1 - e
 // (rounded from binary64, so it keeps its relative precision as e -> 1), e/2
 // and e/6 (the factors of f'' and f''' in Danby's corrections).
@@ -149,12 +167,13 @@ __device__ __forceinline__ void danby_step32_fast(float &E, float M, const Ecc32
 // f' = (1-e) + e (1 - cos E), f'' = e sin E, f''' = e cos E, all free of
 // cancellation near periapsis.  Returns the step and leaves sin E, 1 - cos E
 // of the iterate it started from in `sc`.  With CLAMP the new iterate is kept
-// in [lo, hi]; the last step of the schedule starts within 0.05 of the root
-// and needs no clamp.
-template <bool CLAMP>
+// in [lo, hi]; the last step of the schedule starts within 0.015 of the root
+// and needs no clamp.  WIDE: sin and cos from the unfolded wider-range
+// polynomials (only where |E| <= 3.25 is guaranteed: the schedule's last step).
+template <bool CLAMP, bool WIDE = false>
 __device__ __forceinline__ float danby_step32(float &E, float M, const Ecc32 &k, float lo, float hi, SinCos32 &sc)
 {
-    sc = sincos32(E);
+    sc = WIDE ? sincos32_wide(E) : sincos32(E);
     const float f = fmaf(k.ome, E, fmaf(k.e, sc.xms, -M));
     const float f1 = fmaf(k.e, sc.omc, k.ome);
     const float d3 = danby_delta(f, f1, k.eh * sc.s, fmaf(-k.e6, sc.omc, k.e6));
@@ -193,7 +212,9 @@ __device__ __forceinline__ float kepler32(float M, const Ecc32 &k, int niter, in
     float st = 0.0f;
     if (niter > 0) {
         for (int it = 0; it < niter - 1; ++it) danby_step32_fast(E, M, k);
-        st = danby_step32<false>(E, M, k, 0.0f, 0.0f, sc);
+        // a step count fixed by the caller does not bound the last iterate
+        st = check_large ? danby_step32<false>(E, M, k, 0.0f, 0.0f, sc)
+                         : danby_step32<false, true>(E, M, k, 0.0f, 0.0f, sc);
     } else {
         check_large = true;
         const float lo = M - k.e, hi = M + k.e;

@@ -111,8 +111,13 @@ struct PolMixed {
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k);
             }
+            if (!check) {                              // the schedule bounds the last iterate
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
+                for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false, true>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
+            }
         } else {
             check = true;
             const int n = max_iter > 0 ? max_iter : 1;

@@ -18,11 +18,11 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
 
 
 def test_operation_count_of_the_mixed_formulation():
-    """phase 4 + start 2 + 18 per early step (1.0528 of them at e ~ U[0, 0.9]) + last step 39
-    + velocity 20 + 12 per observation shared by 4 planets."""
+    """phase 4 + start 2 + 18 per early step (1.0528 of them at e ~ U[0, 0.9]) + last step 31
+    (unfolded sin/cos polynomials) + velocity 20 + 12 per observation shared by 4 planets."""
     steps = bench.mean_iterations(0.9)
     assert abs(steps - (2.0 + (0.9 - 0.8525) / 0.9)) < 1e-12
-    assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 18 * (steps - 1) + 39 + 20 + 3)) < 1e-12
+    assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 18 * (steps - 1) + 31 + 20 + 3)) < 1e-12
 
 
 def test_recorded_traffic_requires_a_matching_source_hash(tmp_path, monkeypatch):
