@@ -259,14 +259,17 @@ typedef struct kep_params_csr {
 typedef struct kep_plan kep_plan;   /* opaque; owned by the library */
 
 /* Build a plan for one ragged batch: copies the CSR offsets to the host,
-   checks them, orders the systems by work (n_pl * n_obs, largest first),
+   checks them and keeps device copies of the checked offsets (later changes
+   to obs->obs_off and par->pl_off have no effect on the plan), orders the
+   systems by work (n_pl * n_obs, largest first; by planet count within
+   windows of 256 systems),
    picks the launch shape (the autotuner times block size x systems per work
    item x observation group size on this batch unless opts fixes
    block_threads; results are cached per device and shape class, and kept in
    the text file named by the environment variable KEP_TUNE_CACHE if set), and
    records {queue reset, persistent kernel} as a HIP graph.  May allocate and synchronises `stream`.  The plan keeps the
-   input pointers: their contents may change between calls, their addresses
-   and sizes may not.  Only KEP_MIXED is implemented for ragged batches
+   other input pointers: their contents may change between calls, their
+   addresses and sizes may not.  Only KEP_MIXED is implemented for ragged batches
    (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */
 kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, kep_prec prec,
                            const kep_options *opts, void *stream, kep_plan **out);

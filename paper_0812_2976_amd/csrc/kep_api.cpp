@@ -346,6 +346,8 @@ struct kep_plan {
     double tuned_ms = 0.0;
     int64_t n_obs_total = 0, n_pl_total = 0, triples = 0;
     int32_t *d_order = nullptr;
+    int64_t *d_obs_off = nullptr;     // the checked CSR offsets (the plan's own copies)
+    int64_t *d_pl_off = nullptr;
     unsigned int *d_queue = nullptr;
     double *bound_out = nullptr;      // output pointer recorded in the graph
     hipGraph_t graph = nullptr;
@@ -489,6 +491,8 @@ void plan_free(kep_plan *p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_obs_off) (void)hipFree(p->d_obs_off);
+    if (p->d_pl_off) (void)hipFree(p->d_pl_off);
     if (p->d_queue) (void)hipFree(p->d_queue);
     delete p;
 }
@@ -567,6 +571,15 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work order", fn);
     }
+    // the kernel reads the offsets the plan checked, not the caller's arrays,
+    // whose later contents could send it outside the observation arrays
+    const size_t off_bytes = sizeof(int64_t) * (size_t)(n_sys + 1);
+    if (hipMalloc(&p->d_obs_off, off_bytes) != hipSuccess || hipMalloc(&p->d_pl_off, off_bytes) != hipSuccess ||
+        hipMemcpy(p->d_obs_off, ooff.data(), off_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_pl_off, poff.data(), off_bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        plan_free(p);
+        return fail(KEP_ERR_DEVICE, "%s: cannot copy the CSR offsets", fn);
+    }
     if (hipMalloc(&p->d_queue, sizeof(unsigned int)) != hipSuccess) {
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work queue", fn);
@@ -575,14 +588,14 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     a.t = obs->t;
     a.v = obs->v;
     a.sigma = obs->sigma;
-    a.obs_off = obs->obs_off;
+    a.obs_off = p->d_obs_off;
     a.t0 = obs->t0;
     a.P = par->P;
     a.K = par->K;
     a.e = par->e;
     a.w = par->omega;
     a.M0 = par->M0;
-    a.pl_off = par->pl_off;
+    a.pl_off = p->d_pl_off;
     a.offset = par->offset;
     a.jitter = par->jitter;
     a.order = p->d_order;

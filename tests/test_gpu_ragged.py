@@ -280,3 +280,17 @@ def test_autotune_table_persists(dev, tmp_path):
         assert a[k] == b[k]
     assert b["tuned_ms"] == pytest.approx(float(lines[4]), rel=1e-6)
     assert int(lines[1]) == a["block_threads"] and int(lines[2]) == a["sys_per_batch"] and int(lines[3]) == a["group_chunks"]
+
+
+def test_ragged_plan_keeps_its_checked_offsets(dev):
+    """The plan evaluates the offsets it checked: overwriting the caller's offset
+    arrays afterwards (here with zeros, which would empty every system) changes
+    nothing."""
+    rw = _ragged(500, seed=9)
+    plan = _plan(rw, dev)
+    before = plan().cpu().numpy()
+    plan.obs_off.zero_()
+    plan.pl_off.zero_()
+    torch.cuda.synchronize()
+    after = plan().cpu().numpy()
+    assert np.all(np.isfinite(before)) and np.array_equal(before, after)
