@@ -86,9 +86,10 @@ def test_chisq_fp64_matches_oracle(dev, case):
 def test_model_fp64_matches_oracle(dev):
     """Binary64 model velocities within 1e-9 m/s of the oracle.  This also pins the
     phase: at these epochs (t ~ 2.455e6 d, t0 = 0) one ulp of q = (t - t0)/P is
-    up to 4.7e-10 cycles = 2.9e-9 rad, which moves a velocity by K (dM) b/D, at
-    least 1e-8 m/s for these amplitudes, so only a quotient bit-identical to the
-    oracle's (IEEE division in both) stays within the bound."""
+    up to 4.7e-10 cycles = 2.9e-9 rad, which moves a velocity by
+    K |sin(w + f)| b/D^2 dM, typically 1e-8 to 1e-6 m/s for these amplitudes, so
+    the quotient has to be bit-identical to the oracle's (IEEE division in both)
+    nearly everywhere to stay within the bound."""
     wl = W.dense("c1", n_sys=96, n_obs=130, n_pl=4)
     wl.offset = np.linspace(-5, 5, wl.n_sys)
     g = W.to_gpu(wl, dev)
