@@ -28,35 +28,56 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
-# VALU instruction occupies a SIMD for 4 cycles).  Equals the non-packed FP32
-# FMA rate (78.6 TFLOP/s = 157.3 packed / 2) in instructions, and the FP64
-# vector rate (78.6 TFLOP/s) in instructions.
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Peak of the formulation's operation mix on MI355X (256 CUs x 4 SIMDs at
+# 2.4 GHz).  Per SIMD and cycle the chip completes 32 binary32 lane operations
+# (the published 157.3 TFLOP/s FP32 vector rate = 1024 SIMDs x 32 lanes x 2
+# flops x 2.4 GHz), 16 binary64 ones (78.6 TFLOP/s) and 8 transcendental ones
+# (hardware sine, cosine, reciprocal: a quarter of the binary32 rate).  A mix
+# of n32 + n64 + ntr operations per triple needs n32/32 + n64/16 + ntr/8 SIMD
+# cycles; its peak is the operation count over that time.
+SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
+LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
+
 
 # Algorithmic VALU operations per (system, planet, observation) triple of the
 # mixed-precision formulation (operation count of the method as written, each
-# add/mul/fma/fract/convert/compare/select/reciprocal/sine/cosine counted once):
+# add/mul/fma/fract/convert/compare/select/reciprocal/sine/cosine counted once;
+# in brackets the binary64 and transcendental ones, the rest binary32):
 #   orbital phase in binary64: (t - t0)/P + phase offset as one fused
-#     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4
+#     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4  [4 f64]
 #   starting guess                                                         2
 #   each Danby step before the last: scale, hardware sin and cos 3,
-#     f and its three derivatives 5, three corrections 9, update 1        18
+#     f and its three derivatives 5, three corrections 9, update 1        18  [5 trans]
 #   last Danby step: sin, 1 - cos, E - sin E from the unfolded polynomials
 #     on |E| <= 3.25 (square 1, two degree-5 polynomials 10, cube, three
 #     products 4) 15, f and its three derivatives 5, three corrections 9,
-#     update and step 2                                                    31
-#   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20
+#     update and step 2                                                    31  [3 trans]
+#   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20  [1 trans]
 #   per observation: binary64 residual 6, weighted square 2,
-#     Kahan chi-square 4 -> 12 / n_pl
+#     Kahan chi-square 4 -> 12 / n_pl                                          [6 f64]
 # The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
 # with e ~ U[0, 0.9] the mean number of steps before the last is
 # 1 + (0.9 - 0.8525)/0.9 = 1.0528.
 OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 18, 31, 20, 12
+F64_PHASE, F64_OBS = 4, 6
+TRANS_FAST, TRANS_LAST, TRANS_VEL = 5, 3, 1
 
 
 def mixed_ops_per_triple(n_pl, mean_steps):
     return OPS_PHASE + OPS_START + OPS_FAST * (mean_steps - 1) + OPS_LAST + OPS_VEL + OPS_OBS / n_pl
+
+
+def mixed_op_classes(n_pl, mean_steps):
+    """The operations of mixed_ops_per_triple by class: binary64, transcendental, binary32."""
+    f64 = F64_PHASE + F64_OBS / n_pl
+    trans = TRANS_FAST * (mean_steps - 1) + TRANS_LAST + TRANS_VEL
+    return {"f32": mixed_ops_per_triple(n_pl, mean_steps) - f64 - trans, "f64": f64, "trans": trans}
+
+
+def mix_peak_ops_per_s(classes):
+    """Operations per second of a mix at the per-class lane rates (LANES_PER_CYCLE)."""
+    cycles = sum(n / LANES_PER_CYCLE[c] for c, n in classes.items())
+    return sum(classes.values()) / cycles * SIMDS * CLOCK_HZ
 
 
 def mean_iterations(e_max, s2=0.8525, s3=0.975):
@@ -197,12 +218,17 @@ def main():
     if not np.all(np.isfinite(chi2)):
         raise RuntimeError("non-finite chi-square in the benchmark batch")
 
-    ops = mixed_ops_per_triple(wl.n_pl, mean_iterations(0.9)) * triples
+    steps = mean_iterations(0.9)
+    ops = mixed_ops_per_triple(wl.n_pl, steps) * triples
+    classes = mixed_op_classes(wl.n_pl, steps)
     achieved = ops / (ms * 1e-3) / 1e12
-    peak = VALU_PEAK_OPS / 1e12
+    peak = mix_peak_ops_per_s(classes) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
                 "frac": round(achieved / peak, 4), "traffic": recorded_traffic("rv_chisq_mixed_c2"),
                 "kernel": "k_dense<PolMixed,4,0>", "ops_per_triple": round(ops / triples, 2),
+                "ops_per_triple_by_class": {c: round(n, 3) for c, n in classes.items()},
+                "peak_basis": "per SIMD and cycle: 32 binary32, 16 binary64, 8 transcendental lane operations; "
+                              "1024 SIMDs at 2.4 GHz",
                 "launch_ms": round(ms, 4)}
 
     result = {

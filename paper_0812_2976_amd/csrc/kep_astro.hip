@@ -56,52 +56,6 @@ __device__ __forceinline__ bool astro_setup(const AstroArgs &a, int64_t p, Astro
     return ok;
 }
 
-// sin x and cos x in binary64 for the Kepler root of a centred mean anomaly
-// (|x| <= pi once converged; a step count fixed by the caller may leave the
-// iterate a little farther out).  x is first reduced by the nearest multiple
-// of 2 pi (2 pi in two parts; for |x| < pi, the usual case, this leaves x
-// exactly as it is), then folded to |y| <= pi / 2 with y = +-(pi - |x|), pi in
-// two parts (the first subtraction is exact for pi / 2 <= |x| <= 2 pi), and
-// the Taylor series of sin to y^21 and of cos to y^22 are summed by Horner's
-// rule (remainders below 2e-17 on |y| <= pi / 2; n! is exact in binary64 up
-// to 22!, so each coefficient 1/n! is correctly rounded).
-__device__ __forceinline__ void sincos_root(double x, double &s, double &c)
-{
-    constexpr double kPiHi = 3.141592653589793116;
-    constexpr double kPiLo = 1.2246467991473532e-16;
-    const double kq = rint(x * kInvTwoPi);
-    x = fma(-kq, 2.0 * kPiLo, fma(-kq, 2.0 * kPiHi, x));
-    const double ax = fabs(x);
-    const bool fold = ax > 1.5707963267948966;
-    const double yf = (kPiHi - ax) + kPiLo;
-    const double y = fold ? (x < 0.0 ? -yf : yf) : x;
-    const double y2 = y * y;
-    double ps = -1.0 / 51090942171709440000.0;               // 1/21!
-    ps = fma(ps, y2, 1.0 / 121645100408832000.0);            // 1/19!
-    ps = fma(ps, y2, -1.0 / 355687428096000.0);              // 1/17!
-    ps = fma(ps, y2, 1.0 / 1307674368000.0);                 // 1/15!
-    ps = fma(ps, y2, -1.0 / 6227020800.0);                   // 1/13!
-    ps = fma(ps, y2, 1.0 / 39916800.0);                      // 1/11!
-    ps = fma(ps, y2, -1.0 / 362880.0);                       // 1/9!
-    ps = fma(ps, y2, 1.0 / 5040.0);                          // 1/7!
-    ps = fma(ps, y2, -1.0 / 120.0);                          // 1/5!
-    ps = fma(ps, y2, 1.0 / 6.0);                             // 1/3!
-    double pc = 1.0 / 1124000727777607680000.0;              // 1/22!
-    pc = fma(pc, y2, -1.0 / 2432902008176640000.0);          // 1/20!
-    pc = fma(pc, y2, 1.0 / 6402373705728000.0);              // 1/18!
-    pc = fma(pc, y2, -1.0 / 20922789888000.0);               // 1/16!
-    pc = fma(pc, y2, 1.0 / 87178291200.0);                   // 1/14!
-    pc = fma(pc, y2, -1.0 / 479001600.0);                    // 1/12!
-    pc = fma(pc, y2, 1.0 / 3628800.0);                       // 1/10!
-    pc = fma(pc, y2, -1.0 / 40320.0);                        // 1/8!
-    pc = fma(pc, y2, 1.0 / 720.0);                           // 1/6!
-    pc = fma(pc, y2, -1.0 / 24.0);                           // 1/4!
-    pc = fma(pc, y2, 0.5);                                   // 1/2!
-    s = fma(-y * y2, ps, y);                                 // y - y^3 (1/3! - y^2/5! + ...)
-    const double cy = fma(-y2, pc, 1.0);                     // 1 - y^2 (1/2! - y^2/4! + ...)
-    c = fold ? -cy : cy;
-}
-
 // cos E and sin E of one planet at tt = t - t0, mixed precision: binary64
 // centred phase M, binary32 Danby iteration on (float)M, one binary64 Newton
 // step against M, sin/cos carried to the corrected E to second order.
@@ -115,7 +69,7 @@ __device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int
     float s32, omc32;
     const double E0 = (double)kepler32((float)M, r.k, r.niter, max_iter, r.check != 0, s32, omc32);
     double s, c;
-    sincos_root(E0, s, c);
+    sincos_reduced(E0, s, c);
     const double d = -(E0 - r.e * s - M) / (1.0 - r.e * c);
     const double hd2 = 0.5 * d * d;
     cE = c - d * s - hd2 * c;

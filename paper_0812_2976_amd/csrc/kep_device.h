@@ -107,6 +107,22 @@ __device__ __forceinline__ SinCos32 sincos32_wide(float x)
     return r;
 }
 
+// sin w and cos w of an angle whose products are rounded to binary32
+// afterwards (the planet constants A and B of the mixed chi-square path): w
+// reduced by the nearest multiple of 2 pi in binary64, then the binary32
+// polynomials of sincos32 (|error| a few 1e-8, the size of the rounding of A
+// and B themselves).  Its few registers keep the per-batch setup of the dense
+// kernel within the five-wavefront register budget without scratch; the
+// general binary64 routine needed 16 more registers there.
+__device__ __forceinline__ void sincos_angle32(double w, double &s, double &c)
+{
+    const double kq = rint(w * kInvTwoPi);
+    const float x = (float)fma(-kq, 2.4492935982947064e-16, fma(-kq, 6.283185307179586232, w));
+    const SinCos32 r = sincos32(x);
+    s = (double)r.s;
+    c = (double)(1.0f - r.omc);
+}
+
 // Per-planet eccentricity constants of the binary32 Kepler step: e, 1 - e
 // (rounded from binary64, so it keeps its relative precision as e -> 1), e/2
 // and e/6 (the factors of f'' and f''' in Danby's corrections).
@@ -234,6 +250,53 @@ __device__ __forceinline__ float kepler32(float M, const Ecc32 &k, int niter, in
     omcE = sc.omc;
     rotate32(sinE, omcE, st);
     return E;
+}
+
+// sin x and cos x in binary64 without the general routine's large-argument
+// machinery: x is reduced by the nearest multiple of 2 pi (2 pi in two parts;
+// exact for |x| < pi, and within an ulp of x up to |x| ~ 1e6, the precision x
+// itself carries there), folded to |y| <= pi / 2 with y = +-(pi - |x|), pi in
+// two parts (the first subtraction is exact for pi / 2 <= |x| <= 2 pi), and the
+// Taylor series of sin to y^21 and of cos to y^22 are summed by Horner's rule
+// (remainders below 2e-17 on |y| <= pi / 2; n! is exact in binary64 up to 22!,
+// so each coefficient 1/n! is correctly rounded).  For Kepler roots of a
+// centred mean anomaly (the astrometric correction step); the plain binary64
+// path keeps the general routine.
+__device__ __forceinline__ void sincos_reduced(double x, double &s, double &c)
+{
+    constexpr double kPiHi = 3.141592653589793116;
+    constexpr double kPiLo = 1.2246467991473532e-16;
+    const double kq = rint(x * kInvTwoPi);
+    x = fma(-kq, 2.0 * kPiLo, fma(-kq, 2.0 * kPiHi, x));
+    const double ax = fabs(x);
+    const bool fold = ax > 1.5707963267948966;
+    const double yf = (kPiHi - ax) + kPiLo;
+    const double y = fold ? (x < 0.0 ? -yf : yf) : x;
+    const double y2 = y * y;
+    double ps = -1.0 / 51090942171709440000.0;               // 1/21!
+    ps = fma(ps, y2, 1.0 / 121645100408832000.0);            // 1/19!
+    ps = fma(ps, y2, -1.0 / 355687428096000.0);              // 1/17!
+    ps = fma(ps, y2, 1.0 / 1307674368000.0);                 // 1/15!
+    ps = fma(ps, y2, -1.0 / 6227020800.0);                   // 1/13!
+    ps = fma(ps, y2, 1.0 / 39916800.0);                      // 1/11!
+    ps = fma(ps, y2, -1.0 / 362880.0);                       // 1/9!
+    ps = fma(ps, y2, 1.0 / 5040.0);                          // 1/7!
+    ps = fma(ps, y2, -1.0 / 120.0);                          // 1/5!
+    ps = fma(ps, y2, 1.0 / 6.0);                             // 1/3!
+    double pc = 1.0 / 1124000727777607680000.0;              // 1/22!
+    pc = fma(pc, y2, -1.0 / 2432902008176640000.0);          // 1/20!
+    pc = fma(pc, y2, 1.0 / 6402373705728000.0);              // 1/18!
+    pc = fma(pc, y2, -1.0 / 20922789888000.0);               // 1/16!
+    pc = fma(pc, y2, 1.0 / 87178291200.0);                   // 1/14!
+    pc = fma(pc, y2, -1.0 / 479001600.0);                    // 1/12!
+    pc = fma(pc, y2, 1.0 / 3628800.0);                       // 1/10!
+    pc = fma(pc, y2, -1.0 / 40320.0);                        // 1/8!
+    pc = fma(pc, y2, 1.0 / 720.0);                           // 1/6!
+    pc = fma(pc, y2, -1.0 / 24.0);                           // 1/4!
+    pc = fma(pc, y2, 0.5);                                   // 1/2!
+    s = fma(-y * y2, ps, y);                                 // y - y^3 (1/3! - y^2/5! + ...)
+    const double cy = fma(-y2, pc, 1.0);                     // 1 - y^2 (1/2! - y^2/4! + ...)
+    c = fold ? -cy : cy;
 }
 
 // Per-planet constants of the binary64 orbital phase: P, 1/P (correctly

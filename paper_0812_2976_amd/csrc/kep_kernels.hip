@@ -19,9 +19,19 @@
 
 namespace kep {
 
-template <class Pol, int NCH, int MODE>
+// Residency target of the dense kernels: the mixed-precision variants with up
+// to four chunks per lane are held to five wavefronts per SIMD (at most 102
+// VGPRs).  With four chunks the compiler would otherwise use 126 VGPRs (four
+// wavefronts); the extra wavefront lets the SIMD issue binary32 arithmetic
+// from more wavefronts at once (c2: 2.60 -> 2.39 ms).  With the binary32
+// angle of the planet setup (sincos_angle32) it fits in 95 VGPRs without
+// scratch.
+template <class Pol, int NCH>
+constexpr int dense_waves_per_simd() { return (Pol::kMixed && NCH <= 4) ? 5 : 1; }
 
-__global__ void __launch_bounds__(256) k_dense(DenseArgs a)
+template <class Pol, int NCH, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dense_waves_per_simd<Pol, NCH>())))
+k_dense(DenseArgs a)
 {
     using Rec = typename Pol::Rec;
     using Obs = typename Pol::Obs;
@@ -262,9 +272,16 @@ __global__ void k_fill_u32(unsigned int *p, unsigned int value, int64_t n)
 // 5 n_pl + 1 running sums per system; keeping them in the lane that owns the
 // system avoids a cross-lane reduction per sum).  Observations are uniform
 // across the wave and arrive through scalar loads.  The per-planet terms are
-// in kep_grad.h.
+// in kep_grad.h.  With four planets the compiler would use about 200 VGPRs
+// (two wavefronts per SIMD); it is held to three (c4: 1.05 -> 0.98 ms; the
+// values it moves to scratch are per-system constants).  Four wavefronts
+// would put the running sums in scratch and ran no faster.
+template <int NPL>
+constexpr int grad_waves_per_simd() { return NPL == 4 ? 3 : 1; }
+
 template <int NPL, bool NLL>
-__global__ void __launch_bounds__(256) k_grad_mixed(DenseArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grad_waves_per_simd<NPL>())))
+k_grad_mixed(DenseArgs a)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const bool has_jit = a.jitter != nullptr;
@@ -407,10 +424,6 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 // one stream of lanes, each lane with its own system's planet records, and a
 // segmented scan over each group of 64 lanes returns every system's share: a
 // system's last partial group no longer leaves the rest of its wavefront idle.
-struct RecRagged {
-    RecMixed pl[kMaxPl];
-};
-
 template <int NCH>
 __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed *recs, int npl, int64_t o0,
                                              int64_t nrem, double gam, double jit, bool has_jit, Kahan32 &chi,

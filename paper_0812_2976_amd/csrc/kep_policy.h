@@ -26,7 +26,7 @@ __device__ __forceinline__ bool planet_ok(double P, double K, double e, double w
 }
 
 // ------------------------------------------------------------------ mixed
-struct RecMixed {          // 64 bytes, one per (system, planet)
+struct RecMixed {          // 56 bytes, one per (system, planet)
     Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
     Ecc32 k;               // e, 1 - e, e/2, e/6
     float A, B;            // K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
@@ -43,6 +43,7 @@ struct ObsMixed {
 };
 
 struct PolMixed {
+    static constexpr bool kMixed = true;
     using Rec = RecMixed;
     using Obs = ObsMixed;
     struct ModelAcc { Kahan32 k; };
@@ -57,7 +58,7 @@ struct PolMixed {
         r.k = make_ecc32(e);
         const double b2 = (1.0 - e) * (1.0 + e);
         double sw, cw;
-        sincos(w, &sw, &cw);
+        sincos_angle32(w, sw, cw);
         r.A = (float)(K * b2 * cw);
         r.B = (float)(-K * sqrt(b2) * sw);
         r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e);
@@ -189,6 +190,7 @@ struct Obs64 {
 };
 
 struct Pol64 {
+    static constexpr bool kMixed = false;
     using Rec = Rec64;
     using Obs = Obs64;
     struct ModelAcc { double s; };

@@ -25,6 +25,22 @@ def test_operation_count_of_the_mixed_formulation():
     assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 18 * (steps - 1) + 31 + 20 + 3)) < 1e-12
 
 
+def test_mix_peak_of_the_formulation():
+    """The classes add up to the operation count; a pure binary32 mix peaks at the
+    FP32 vector rate (157.3 TFLOP/s / 2 flops per operation), a pure binary64 one at
+    half of it, and the formulation's mix (64.19 binary32, 5.5 binary64, 9.26
+    transcendental operations per triple) at 78.95 / (64.19/32 + 5.5/16 + 9.26/8)
+    operations per SIMD cycle."""
+    steps = bench.mean_iterations(0.9)
+    c = bench.mixed_op_classes(4, steps)
+    assert abs(sum(c.values()) - bench.mixed_ops_per_triple(4, steps)) < 1e-12
+    assert abs(c["f64"] - 5.5) < 1e-12 and abs(c["trans"] - (5 * (steps - 1) + 4)) < 1e-12
+    assert abs(bench.mix_peak_ops_per_s({"f32": 1.0}) - 157.3e12 / 2) < 0.1e12
+    assert abs(bench.mix_peak_ops_per_s({"f64": 1.0}) - 78.6e12 / 2) < 0.1e12
+    cycles = c["f32"] / 32 + c["f64"] / 16 + c["trans"] / 8
+    assert abs(bench.mix_peak_ops_per_s(c) - sum(c.values()) / cycles * 1024 * 2.4e9) < 1.0
+
+
 def test_recorded_traffic_requires_a_matching_source_hash(tmp_path, monkeypatch):
     assert bench.recorded_traffic("no_such_profile") is None
     h = bench.kernel_source_hash()
