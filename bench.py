@@ -47,20 +47,21 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 #     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4  [4 f64]
 #   starting guess                                                         2
 #   each Danby step before the last: scale, hardware sin and cos 3,
-#     f and its three derivatives 5, three corrections 9, update 1        18  [5 trans]
+#     f and its three derivatives 5, three corrections with one
+#     reciprocal 11, update 1                                             20  [3 trans]
 #   last Danby step: sin, 1 - cos, E - sin E from the unfolded polynomials
 #     on |E| <= 3.25 (square 1, two degree-5 polynomials 10, cube, three
-#     products 4) 15, f and its three derivatives 5, three corrections 9,
-#     update and step 2                                                    31  [3 trans]
+#     products 4) 15, f and its three derivatives 5, three corrections
+#     with one reciprocal 11, update and step 2                            33  [1 trans]
 #   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20  [1 trans]
 #   per observation: binary64 residual 6, weighted square 2,
 #     Kahan chi-square 4 -> 12 / n_pl                                          [6 f64]
 # The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
 # with e ~ U[0, 0.9] the mean number of steps before the last is
 # 1 + (0.9 - 0.8525)/0.9 = 1.0528.
-OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 18, 31, 20, 12
+OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 20, 33, 20, 12
 F64_PHASE, F64_OBS = 4, 6
-TRANS_FAST, TRANS_LAST, TRANS_VEL = 5, 3, 1
+TRANS_FAST, TRANS_LAST, TRANS_VEL = 3, 1, 1
 
 
 def mixed_ops_per_triple(n_pl, mean_steps):

@@ -155,11 +155,21 @@ __device__ __forceinline__ int sched64(double e)
 
 // Danby's three corrections (Sec. 4.3: Newton, Halley-like, quartic) from
 // f and its derivatives f' = f1, f''/2 = f2h, f'''/6 = f3s.
+// One reciprocal instead of three: d1 = -f/f1 makes the second denominator
+// f1 + d1 f2h = N/f1 with N = f1^2 - f f2h, so d2 = -f f1/N, and the third
+// denominator f1 + d2 (f2h + d2 f3s) = f1 (N^2 - f f2h N + f^2 f1 f3s)/N^2, so
+//   d3 = -f N^2 / (f1 (N^2 - f f2h N + f^2 f1 f3s)).
+// Same value as the three divisions (and the same vanishing denominator where
+// the Halley-like step breaks down); a transcendental takes four binary32
+// operations' issue time, so four more multiply-adds for two fewer
+// reciprocals is the cheaper form.
 __device__ __forceinline__ float danby_delta(float f, float f1, float f2h, float f3s)
 {
-    float d1 = -f * rcp32(f1);
-    float d2 = -f * rcp32(fmaf(d1, f2h, f1));
-    return -f * rcp32(fmaf(d2, fmaf(d2, f3s, f2h), f1));
+    const float g = f * f2h;
+    const float N = fmaf(f1, f1, -g);
+    const float N2 = N * N;
+    const float den = f1 * fmaf(f * f1, f * f3s, fmaf(-g, N, N2));
+    return -(f * N2) * rcp32(den);
 }
 
 // A Danby step for the iterations before the last one: sin and cos from the

@@ -18,23 +18,24 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
 
 
 def test_operation_count_of_the_mixed_formulation():
-    """phase 4 + start 2 + 18 per early step (1.0528 of them at e ~ U[0, 0.9]) + last step 31
-    (unfolded sin/cos polynomials) + velocity 20 + 12 per observation shared by 4 planets."""
+    """phase 4 + start 2 + 20 per early step (1.0528 of them at e ~ U[0, 0.9]) + last step 33
+    (unfolded sin/cos polynomials, corrections with one reciprocal) + velocity 20 + 12 per
+    observation shared by 4 planets."""
     steps = bench.mean_iterations(0.9)
     assert abs(steps - (2.0 + (0.9 - 0.8525) / 0.9)) < 1e-12
-    assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 18 * (steps - 1) + 31 + 20 + 3)) < 1e-12
+    assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 20 * (steps - 1) + 33 + 20 + 3)) < 1e-12
 
 
 def test_mix_peak_of_the_formulation():
     """The classes add up to the operation count; a pure binary32 mix peaks at the
     FP32 vector rate (157.3 TFLOP/s / 2 flops per operation), a pure binary64 one at
-    half of it, and the formulation's mix (64.19 binary32, 5.5 binary64, 9.26
-    transcendental operations per triple) at 78.95 / (64.19/32 + 5.5/16 + 9.26/8)
-    operations per SIMD cycle."""
+    half of it, and the formulation's mix (binary32, 5.5 binary64 and 3 per early
+    step + 2 transcendental operations per triple) at its operations over
+    n32/32 + n64/16 + ntr/8 SIMD cycles."""
     steps = bench.mean_iterations(0.9)
     c = bench.mixed_op_classes(4, steps)
     assert abs(sum(c.values()) - bench.mixed_ops_per_triple(4, steps)) < 1e-12
-    assert abs(c["f64"] - 5.5) < 1e-12 and abs(c["trans"] - (5 * (steps - 1) + 4)) < 1e-12
+    assert abs(c["f64"] - 5.5) < 1e-12 and abs(c["trans"] - (3 * (steps - 1) + 2)) < 1e-12
     assert abs(bench.mix_peak_ops_per_s({"f32": 1.0}) - 157.3e12 / 2) < 0.1e12
     assert abs(bench.mix_peak_ops_per_s({"f64": 1.0}) - 78.6e12 / 2) < 0.1e12
     cycles = c["f32"] / 32 + c["f64"] / 16 + c["trans"] / 8
