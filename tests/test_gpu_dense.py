@@ -119,6 +119,26 @@ def test_chisq_mixed_matches_oracle(dev, case):
     assert err.max() <= 1e-5
 
 
+def test_mixed_angles_outside_one_turn(dev):
+    """Arguments of periapsis and mean anomalies at epoch far outside [0, 2 pi)
+    (negative, tens and thousands of turns): the mixed path reduces them by the
+    nearest multiple of 2 pi in binary64 and must still match the oracle, which
+    takes sin, cos and the phase of the values as given."""
+    wl = W.dense("c1", n_sys=400, n_obs=128, n_pl=3)
+    rng = np.random.default_rng(17)
+    turns = rng.choice([-1000.0, -7.0, -1.0, 3.0, 50.0, 2000.0], size=wl.w.shape)
+    wl.w = wl.w + 2 * np.pi * turns
+    wl.M0 = wl.M0 - 2 * np.pi * turns[::-1]
+    g = W.to_gpu(wl, dev)
+    chi2 = kp.rv_chisq(**g, prec="mixed").cpu().numpy()
+    ref = W.oracle_par(oracle.chisq, W.oracle_dense(wl), wl.n_sys)
+    err = W.rel_err_chi2(chi2, ref)
+    _report("chi2 mixed, angles outside one turn", err)
+    assert err.max() <= 1e-5
+    vm = kp.rv_model(g["t"], g["P"], g["K"], g["e"], g["omega"], g["M0"], prec="mixed").cpu().numpy()
+    assert np.abs(vm - oracle.rv_model(W.oracle_dense(wl))).max() <= 1e-3
+
+
 @pytest.mark.parametrize("stress", [False, True])
 def test_model_mixed_matches_oracle(dev, stress):
     wl = W.dense("c2", n_sys=512, stress=stress)
