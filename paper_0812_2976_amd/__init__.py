@@ -271,7 +271,11 @@ def rv_model(t, P, K, e, omega, M0, offset=None, t0=0.0, prec="mixed", out=None,
 
 
 def rv_chisq(t, v, sigma, P, K, e, omega, M0, offset=None, jitter=None, t0=0.0, prec="mixed", out=None, opts=None):
-    """chi-square per system (Eq. 5), shape (n_sys,)."""
+    """chi-square per system (Eq. 5), shape (n_sys,).
+
+    P, K, e, omega, M0 are planes of shape (n_pl, n_sys). Parameters held
+    system-major, (n_sys, n_pl), are passed as their transposed views (`P.T`); every
+    entry point copies a non-contiguous argument into a contiguous plane first."""
     obs, par, keep, dev = _obs_params(t, v, sigma, P, K, e, omega, M0, offset, jitter, t0)
     out = _out(out, "out", (par.n_sys,), dev)
     L = load_library()
