@@ -45,10 +45,14 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 # in brackets the binary64 and transcendental ones, the rest binary32):
 #   orbital phase in binary64: (t - t0)/P + phase offset as one fused
 #     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4  [4 f64]
-#   starting guess                                                         2
-#   each Danby step before the last: scale, hardware sin and cos 3,
-#     f and its three derivatives 5, three corrections with one
-#     reciprocal 11, update 1                                             20  [3 trans]
+#   starting value at e <= 0.8525 (the table of kep_start_tab.h): |M|
+#     scaled and clamped 2, knot index and fraction 2, address 1, two
+#     interpolations in e 2 (binary16 operands widened inside the
+#     multiply-add), one in |M| 2, sign of M 1                             10  [one LDS read]
+#   at e > 0.8525 instead: the paper's starting guess 2, and each Danby
+#     step before the last: scale, hardware sin and cos 3, f and its
+#     three derivatives 5, three corrections with one reciprocal 11,
+#     update 1                                                            20  [3 trans]
 #   last Danby step: sin, 1 - cos, E - sin E from the unfolded polynomials
 #     on |E| <= 3.25 (square 1, two degree-5 polynomials 10, cube, three
 #     products 4) 15, f and its three derivatives 5, three corrections
@@ -56,23 +60,27 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 #   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20  [1 trans]
 #   per observation: binary64 residual 6, weighted square 2,
 #     Kahan chi-square 4 -> 12 / n_pl                                          [6 f64]
-# The eccentricity schedule takes 2 steps for e <= 0.8525 and 3 up to 0.975;
-# with e ~ U[0, 0.9] the mean number of steps before the last is
-# 1 + (0.9 - 0.8525)/0.9 = 1.0528.
-OPS_PHASE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 2, 20, 33, 20, 12
+# With e ~ U[0, 0.9] a fraction 0.8525 / 0.9 = 0.9472 of the planets start from
+# the table; the others (0.8525 < e <= 0.975 on the eccentricity schedule) take
+# two steps before the last: 2 (0.9 - 0.8525) / 0.9 = 0.1056 early steps per
+# triple on average.
+OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 10, 2, 20, 33, 20, 12
 F64_PHASE, F64_OBS = 4, 6
 TRANS_FAST, TRANS_LAST, TRANS_VEL = 3, 1, 1
 
 
-def mixed_ops_per_triple(n_pl, mean_steps):
-    return OPS_PHASE + OPS_START + OPS_FAST * (mean_steps - 1) + OPS_LAST + OPS_VEL + OPS_OBS / n_pl
+def mixed_ops_per_triple(n_pl, f_table, early):
+    """f_table: fraction of the planets started from the table; early: mean Danby
+    steps before the last per triple."""
+    return (OPS_PHASE + f_table * OPS_TABLE + (1.0 - f_table) * OPS_START + OPS_FAST * early + OPS_LAST + OPS_VEL
+            + OPS_OBS / n_pl)
 
 
-def mixed_op_classes(n_pl, mean_steps):
+def mixed_op_classes(n_pl, f_table, early):
     """The operations of mixed_ops_per_triple by class: binary64, transcendental, binary32."""
     f64 = F64_PHASE + F64_OBS / n_pl
-    trans = TRANS_FAST * (mean_steps - 1) + TRANS_LAST + TRANS_VEL
-    return {"f32": mixed_ops_per_triple(n_pl, mean_steps) - f64 - trans, "f64": f64, "trans": trans}
+    trans = TRANS_FAST * early + TRANS_LAST + TRANS_VEL
+    return {"f32": mixed_ops_per_triple(n_pl, f_table, early) - f64 - trans, "f64": f64, "trans": trans}
 
 
 def mix_peak_ops_per_s(classes):
@@ -81,13 +89,20 @@ def mix_peak_ops_per_s(classes):
     return sum(classes.values()) / cycles * SIMDS * CLOCK_HZ
 
 
-def mean_iterations(e_max, s2=0.8525, s3=0.975):
-    return 2.0 + max(0.0, min(e_max, s3) - s2) / e_max
+def table_fraction(e_max, s_table=0.8525):
+    """Fraction of e ~ U[0, e_max] inside the starting-value table's range."""
+    return min(e_max, s_table) / e_max
+
+
+def early_steps(e_max, s2=0.8525, s3=0.975):
+    """Mean Danby steps before the last per planet at e ~ U[0, e_max <= s3]: planets
+    beyond the table's range follow the schedule, two early steps up to s3."""
+    return 2.0 * max(0.0, min(e_max, s3) - s2) / e_max
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_grad.h"):
+    for f in ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_start_tab.h", "kep_grad.h"):
         with open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -219,9 +234,9 @@ def main():
     if not np.all(np.isfinite(chi2)):
         raise RuntimeError("non-finite chi-square in the benchmark batch")
 
-    steps = mean_iterations(0.9)
-    ops = mixed_ops_per_triple(wl.n_pl, steps) * triples
-    classes = mixed_op_classes(wl.n_pl, steps)
+    f_table, early = table_fraction(0.9), early_steps(0.9)
+    ops = mixed_ops_per_triple(wl.n_pl, f_table, early) * triples
+    classes = mixed_op_classes(wl.n_pl, f_table, early)
     achieved = ops / (ms * 1e-3) / 1e12
     peak = mix_peak_ops_per_s(classes) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",

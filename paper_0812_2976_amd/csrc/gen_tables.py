@@ -25,7 +25,16 @@
    single step from the starting guess is large (up to 0.85 e), and its own
    binary32 rounding (a few ulp of the step) would exceed the target.
 
-Run:  python gen_tables.py   (rewrites kep_tables.h next to this file)
+3. Starting values for the binary32 Kepler solve (the paper's interpolated initial
+   guess, Sec. 5.4) on the two-step band e <= KEP_S32_E2: E(e_i, M_j) on 17
+   eccentricities and 130 knots M_j = j pi / 128, stored as binary16 pairs (value,
+   difference to the next eccentricity row) in kep_start_tab.h.  The scan checks that
+   bilinear interpolation starts within a few 1e-3 rad of the root and that one Danby
+   step from there lands within 1e-9 rad (float64), so the kernels that hold the table
+   take the last step only.
+
+Run:  python gen_tables.py         (rewrites kep_tables.h and kep_start_tab.h)
+      python gen_tables.py start   (kep_start_tab.h only)
 """
 import os
 
@@ -144,6 +153,93 @@ def schedule(target, n_list=(2, 3, 4, 5), step=1.0 / 2000):
     return thresholds
 
 
+START_OUT = os.path.join(HERE, "kep_start_tab.h")
+START_NE = 17          # eccentricity rows e_i = i emax / 16
+START_NM = 130         # knots M_j = j pi / 128, j = 0 .. 129 (two beyond pi: |M| may round past it)
+
+
+def _root64(e, M):
+    """Root of Kepler's equation in float64 (Danby steps to convergence, then Newton)."""
+    E = M + 0.85 * e * np.sign(np.sin(M))
+    for _ in range(12):
+        E = _danby_step(E, e, M)
+    for _ in range(2):
+        E = E - (E - e * np.sin(E) - M) / (1 - e * np.cos(E))
+    return E
+
+
+def start_table(emax):
+    """Rows i < NE - 1 of binary16 pairs (E(e_i, M_j), E(e_i+1, M_j) - E(e_i, M_j)), knots
+    over M >= 0; the difference is taken between the rounded values."""
+    M = np.arange(START_NM) * (np.pi / 128)
+    T = np.array([_root64(i * emax / (START_NE - 1), M) for i in range(START_NE)]).astype(np.float16)
+    pairs = np.empty((START_NE - 1, START_NM, 2), dtype=np.float16)
+    pairs[:, :, 0] = T[:-1]
+    pairs[:, :, 1] = (T[1:].astype(np.float64) - T[:-1]).astype(np.float16)
+    return pairs
+
+
+def start_lookup(pairs, emax, e, M):
+    """The kernels' starting value: bilinear in (e, |M|) from the binary16 pairs, sign of M
+    (the interpolation itself in float64)."""
+    fi = np.float64(e) * ((START_NE - 1) / emax)
+    i = min(int(fi), START_NE - 2)
+    we = fi - i
+    fj = np.abs(M) * (128 / np.pi)
+    j = fj.astype(int)
+    wm = fj - j
+    p = pairs.astype(np.float64)
+    r0 = p[i, j, 0] + we * p[i, j, 1]
+    r1 = p[i, j + 1, 0] + we * p[i, j + 1, 1]
+    return np.copysign(r0 + wm * (r1 - r0), M)
+
+
+def start_scan(pairs, emax, n_e=400):
+    """Worst distance of the table start from the root, and worst error after one
+    Danby step from it (float64), over e in [0, emax] and a dense M grid."""
+    M = np.concatenate([np.linspace(-np.pi, np.pi, 20001),
+                        np.outer([-1.0, 1.0], np.logspace(-10, 0, 2001)).ravel()])
+    far, err = 0.0, 0.0
+    for e in np.linspace(0.0, emax, n_e):
+        R = _root64(e, M)
+        E0 = start_lookup(pairs, emax, e, M)
+        far = max(far, float(np.max(np.abs(E0 - R))))
+        err = max(err, float(np.max(np.abs(_danby_step(E0, e, M) - R))))
+    return far, err
+
+
+def write_start_table(emax):
+    pairs = start_table(emax)
+    far, err = start_scan(pairs, emax)
+    assert err <= 1e-9, err
+    lines = [
+        "// Generated by gen_tables.py -- do not edit by hand.",
+        "#pragma once",
+        "",
+        "// Starting values for the binary32 Kepler solve at e <= KEP_TAB_EMAX.  With",
+        f"// e_i = i KEP_TAB_EMAX / {START_NE - 1} and M_j = j pi / 128, word [i][j] holds the binary16",
+        "// pair (E(e_i, M_j), E(e_i+1, M_j) - E(e_i, M_j)) (first value in the low half),",
+        "// i < KEP_TAB_NE - 1, j < KEP_TAB_NM.  Bilinear interpolation in (e, |M|) with the sign",
+        f"// of M starts at most {far:.2e} rad from the root; one Danby step from there lands",
+        f"// within {err:.1e} rad (float64 scan over e and M).",
+        f"#define KEP_TAB_NE {START_NE}",
+        f"#define KEP_TAB_NM {START_NM}",
+        f"#define KEP_TAB_EMAX {emax!r}",
+        f"#define KEP_TAB_MSCALE {float(np.float32(128 / np.pi))!r}f",
+        "",
+        "static __device__ const unsigned int kep_start_tab[(KEP_TAB_NE - 1) * KEP_TAB_NM] = {",
+    ]
+    bits = pairs.view(np.uint16).astype(np.uint32)
+    words = (bits[:, :, 0] | (bits[:, :, 1] << 16)).ravel()
+    flat = [f"0x{int(w):08x}u" for w in words]
+    for k in range(0, len(flat), 8):
+        lines.append("    " + ", ".join(flat[k:k + 8]) + ",")
+    lines.append("};")
+    with open(START_OUT, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"start table: far {far:.3e}, one step {err:.3e}")
+
+
 def main():
     ymax = (np.pi / 2) ** 2 * 1.001
     grid = np.linspace(0.0, ymax, 3001)
@@ -192,7 +288,12 @@ def main():
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(open(OUT).read())
+    write_start_table(s32[2])
 
 
 if __name__ == "__main__":
-    main()
+    import sys
+    if sys.argv[1:] == ["start"]:
+        write_start_table(0.8525)
+    else:
+        main()

@@ -29,6 +29,18 @@ namespace kep {
 template <class Pol, int NCH>
 constexpr int dense_waves_per_simd() { return (Pol::kMixed && NCH <= 4) ? 5 : 1; }
 
+// The mixed velocity kernels start the Kepler solve from the table of
+// kep_start_tab.h, copied once into each block's LDS behind the records.
+template <class Pol, int MODE>
+constexpr bool dense_uses_table() { return Pol::kMixed && MODE != kAnomalies; }
+
+__host__ __device__ inline size_t dense_table_offset(int wpb, int sb, int n_pl, size_t rec_size)
+{
+    return ((size_t)wpb * sb * n_pl * rec_size + (size_t)wpb * sb * sizeof(int) + 15) & ~(size_t)15;
+}
+
+constexpr size_t kDenseTableBytes = sizeof(kep_start_tab);
+
 template <class Pol, int NCH, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dense_waves_per_simd<Pol, NCH>())))
 k_dense(DenseArgs a)
@@ -43,6 +55,14 @@ k_dense(DenseArgs a)
     const int wib = uniform_int(threadIdx.x >> 6);
     Rec *recs = reinterpret_cast<Rec *>(smem) + (size_t)wib * a.sb * a.n_pl;
     int *sysbad = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * a.n_pl * sizeof(Rec)) + wib * a.sb;
+    // mixed velocities: the block's copy of the starting-value table after the records
+    const uint32_t *tab = nullptr;
+    if constexpr (dense_uses_table<Pol, MODE>()) {
+        uint32_t *t = reinterpret_cast<uint32_t *>(smem + dense_table_offset(wpb, a.sb, a.n_pl, sizeof(Rec)));
+        for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) t[q] = kep_start_tab[q];
+        __syncthreads();
+        tab = t;
+    }
 
     const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
@@ -125,7 +145,7 @@ k_dense(DenseArgs a)
                     for (int j = 0; j < a.n_pl; ++j) {
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) Pol::model_init(m[c]);
-                        pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a);
+                        pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a, tab);
                         float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) {
@@ -139,7 +159,7 @@ k_dense(DenseArgs a)
                 }
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) Pol::model_init(m[c]);
-                for (int j = 0; j < a.n_pl; ++j) pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a);
+                for (int j = 0; j < a.n_pl; ++j) pol_add_planet<Pol, NCH>(recs[s * a.n_pl + j], o, m, a, tab);
                 if (MODEL) {
 #pragma unroll
                     for (int c = 0; c < NCH; ++c) {
@@ -716,10 +736,17 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     const int block = shape.block > 0 ? shape.block : 256;
     const int wpb = block / 64;
     const size_t rec_bytes = (size_t)wpb * a.n_pl * sizeof(typename Pol::Rec) + (size_t)wpb * sizeof(int);
+    constexpr bool table = dense_uses_table<Pol, MODE>();
+    auto lds_of = [&](int64_t sb) {
+        return table ? dense_table_offset(wpb, (int)sb, a.n_pl, sizeof(typename Pol::Rec)) + kDenseTableBytes
+                     : rec_bytes * (size_t)sb;
+    };
     // systems per setup batch: at most kMaxSB and at most 48 KiB of LDS per block
-    int64_t sb_cap = (int64_t)(48 * 1024) / (int64_t)rec_bytes;
+    // (with the table, 32 KiB: five blocks of four wavefronts share a CU's 160 KiB)
+    const int64_t budget = table ? (int64_t)(32 * 1024) - (int64_t)kDenseTableBytes - 16 : (int64_t)(48 * 1024);
+    int64_t sb_cap = budget / (int64_t)rec_bytes;
     sb_cap = sb_cap < 1 ? 1 : (sb_cap > kMaxSB ? kMaxSB : sb_cap);
-    size_t lds = rec_bytes * (size_t)sb_cap;
+    size_t lds = lds_of(sb_cap);
     const int nch_needed = (int)((a.n_obs + 63) / 64);
     void (*kern)(DenseArgs);
     int nch;
@@ -740,7 +767,7 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     int64_t sb = (a.n_sys + mw - 1) / mw;
     sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
     a.sb = (int)sb;
-    lds = rec_bytes * (size_t)sb;
+    lds = lds_of(sb);
     const int64_t n_batches = (a.n_sys + sb - 1) / sb;
     const int64_t n_groups = (a.n_obs + 64 * nch - 1) / (64 * nch);
     const int64_t n_items = MODE != kChi2 ? n_batches * (n_groups > 0 ? n_groups : 1) : n_batches;

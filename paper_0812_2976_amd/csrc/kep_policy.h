@@ -9,6 +9,7 @@
 
 #include "kep_device.h"
 #include "kep_internal.h"
+#include "kep_start_tab.h"
 
 namespace kep {
 
@@ -25,12 +26,22 @@ __device__ __forceinline__ bool planet_ok(double P, double K, double e, double w
            isfinite(w) && isfinite(M0);
 }
 
+// The two binary16 halves of a table word, widened to binary32.
+__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)w); }
+__device__ __forceinline__ float half_hi(uint32_t w)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
 // ------------------------------------------------------------------ mixed
 struct RecMixed {          // 56 bytes, one per (system, planet)
     Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
     Ecc32 k;               // e, 1 - e, e/2, e/6
     float A, B;            // K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
-    int niter, check;      // Danby steps (0: convergence test); 1 if fixed by the caller
+    float twe;             // weight of row trow + 1 of the starting-value table
+    int16_t niter;         // Danby steps from the paper's guess (0: convergence test)
+    int8_t check;          // 1 if the step count is fixed by the caller
+    int8_t trow;           // row of the starting-value table, -1: the paper's guess only
 };
 
 struct ObsMixed {
@@ -61,8 +72,17 @@ struct PolMixed {
         sincos_angle32(w, sw, cw);
         r.A = (float)(K * b2 * cw);
         r.B = (float)(-K * sqrt(b2) * sw);
-        r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e);
+        r.niter = (int16_t)(a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e));
         r.check = a.fixed_iter > 0 ? 1 : 0;
+        // kernels that hold the table start from it (one Danby step) at e <= KEP_TAB_EMAX
+        r.trow = -1;
+        r.twe = 0.0f;
+        if (a.fixed_iter <= 0 && e <= KEP_TAB_EMAX) {
+            const double fi = e * ((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
+            const int i = min((int)fi, KEP_TAB_NE - 2);
+            r.trow = (int8_t)i;
+            r.twe = (float)(fi - i);
+        }
         return ok;
     }
 
@@ -90,24 +110,51 @@ struct PolMixed {
         o.w = 1.0f;
     }
 
+    // tab: the starting-value table in LDS (the words of kep_start_tab), or null
     template <int NCH>
     static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
-                                                      int max_iter, int /*fixed: already in rr.niter*/)
+                                                      int max_iter, int /*fixed: already in rr.niter*/,
+                                                      const uint32_t *tab = nullptr)
     {
         // rr comes from an LDS broadcast: every lane holds the same values
         const Phase64 ph = rr.ph;
         const Ecc32 k = rr.k;
         const float A = rr.A, B = rr.B;
         const int niter = uniform_int(rr.niter);
+        const int trow = uniform_int(rr.trow);
         float M[NCH], E[NCH], st[NCH];
         SinCos32 sc[NCH];
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            M[c] = mean_anomaly32(o[c].tt, ph);
-            E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
-        }
+        for (int c = 0; c < NCH; ++c) M[c] = mean_anomaly32(o[c].tt, ph);
         bool check = uniform_int(rr.check) != 0;
-        if (niter > 0) {
+        if (tab != nullptr && trow >= 0) {
+            // tabulated starting value (the paper's interpolated initial guess, Sec. 5.4):
+            // bilinear in (e, |M|) within 3.7e-3 rad of the root, close enough for the
+            // accurate last step alone (4.5e-11 rad in float64; scan in gen_tables.py)
+            // (every chunk's reads are issued before any is used)
+            const uint32_t *row = tab + trow * KEP_TAB_NM;
+            const float twe = rr.twe;
+            float wm[NCH];
+            uint32_t q0[NCH], q1[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const float fj = fminf(fabsf(M[c]) * KEP_TAB_MSCALE, 128.0f);   // NaN -> 128
+                const int j = (int)fj;
+                wm[c] = __builtin_amdgcn_fractf(fj);
+                q0[c] = row[j];                        // binary16 (E_i, E_i+1 - E_i) at knot j
+                q1[c] = row[j + 1];
+            }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const float r0 = fmaf(twe, half_hi(q0[c]), half_lo(q0[c]));
+                const float r1 = fmaf(twe, half_hi(q1[c]), half_lo(q1[c]));
+                E[c] = copysignf(fmaf(wm[c], r1 - r0, r0), M[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false, true>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
+        } else if (niter > 0) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
             for (int it = 0; it < niter - 1; ++it) {   // steps before the last: hardware sin/cos
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) danby_step32_fast(E[c], M[c], k);
@@ -120,6 +167,8 @@ struct PolMixed {
                 for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
             }
         } else {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) E[c] = fmaf(copysignf(0.85f, M[c]), k.e, M[c]);
             check = true;
             const int n = max_iter > 0 ? max_iter : 1;
             for (int it = 0; it < n; ++it) {           // convergence-tested (beyond the schedule),
@@ -284,9 +333,11 @@ __device__ __forceinline__ int fixed64(int fixed_iter) { return fixed_iter > 0 ?
 
 template <class Pol, int NCH>
 __device__ __forceinline__ void pol_add_planet(const typename Pol::Rec &r, const typename Pol::Obs (&o)[NCH],
-                                               typename Pol::ModelAcc (&m)[NCH], const DenseArgs &a)
+                                               typename Pol::ModelAcc (&m)[NCH], const DenseArgs &a,
+                                               const uint32_t *tab = nullptr)
 {
-    Pol::template add_planet<NCH>(r, o, m, a.max_iter, fixed64(a.fixed_iter));
+    if constexpr (Pol::kMixed) Pol::template add_planet<NCH>(r, o, m, a.max_iter, 0, tab);
+    else Pol::template add_planet<NCH>(r, o, m, a.max_iter, fixed64(a.fixed_iter));
 }
 
 // Dense kernel.  MODE kChi2: chi-square per system; kModel: model velocities

@@ -18,12 +18,16 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
 
 
 def test_operation_count_of_the_mixed_formulation():
-    """phase 4 + start 2 + 20 per early step (1.0528 of them at e ~ U[0, 0.9]) + last step 33
-    (unfolded sin/cos polynomials, corrections with one reciprocal) + velocity 20 + 12 per
-    observation shared by 4 planets."""
-    steps = bench.mean_iterations(0.9)
-    assert abs(steps - (2.0 + (0.9 - 0.8525) / 0.9)) < 1e-12
-    assert abs(bench.mixed_ops_per_triple(4, steps) - (4 + 2 + 20 * (steps - 1) + 33 + 20 + 3)) < 1e-12
+    """phase 4 + table start 10 for the 0.8525 / 0.9 of planets inside the table's range,
+    else the paper's start 2 and two early steps of 20 + last step 33 (unfolded sin/cos
+    polynomials, corrections with one reciprocal) + velocity 20 + 12 per observation
+    shared by 4 planets."""
+    f, early = bench.table_fraction(0.9), bench.early_steps(0.9)
+    assert abs(f - 0.8525 / 0.9) < 1e-12 and abs(early - 2 * (1 - f)) < 1e-12
+    want = 4 + f * 10 + (1 - f) * (2 + 2 * 20) + 33 + 20 + 3
+    assert abs(bench.mixed_ops_per_triple(4, f, early) - want) < 1e-12
+    # without the table (e beyond its range) the count is the schedule's
+    assert abs(bench.mixed_ops_per_triple(4, 0.0, 2.0) - (4 + 2 + 40 + 33 + 20 + 3)) < 1e-12
 
 
 def test_mix_peak_of_the_formulation():
@@ -32,10 +36,10 @@ def test_mix_peak_of_the_formulation():
     half of it, and the formulation's mix (binary32, 5.5 binary64 and 3 per early
     step + 2 transcendental operations per triple) at its operations over
     n32/32 + n64/16 + ntr/8 SIMD cycles."""
-    steps = bench.mean_iterations(0.9)
-    c = bench.mixed_op_classes(4, steps)
-    assert abs(sum(c.values()) - bench.mixed_ops_per_triple(4, steps)) < 1e-12
-    assert abs(c["f64"] - 5.5) < 1e-12 and abs(c["trans"] - (3 * (steps - 1) + 2)) < 1e-12
+    f, early = bench.table_fraction(0.9), bench.early_steps(0.9)
+    c = bench.mixed_op_classes(4, f, early)
+    assert abs(sum(c.values()) - bench.mixed_ops_per_triple(4, f, early)) < 1e-12
+    assert abs(c["f64"] - 5.5) < 1e-12 and abs(c["trans"] - (3 * early + 2)) < 1e-12
     assert abs(bench.mix_peak_ops_per_s({"f32": 1.0}) - 157.3e12 / 2) < 0.1e12
     assert abs(bench.mix_peak_ops_per_s({"f64": 1.0}) - 78.6e12 / 2) < 0.1e12
     cycles = c["f32"] / 32 + c["f64"] / 16 + c["trans"] / 8
