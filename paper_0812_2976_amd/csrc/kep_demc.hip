@@ -75,7 +75,8 @@ DenseArgs half_dense(const DemcArgs &a, const DenseArgs &base, const double *pla
 //      setup does from parameter planes;
 //   D. lanes over chains: domain and prior-support flags;
 //   then evaluates each proposal's chi-square with the lanes over
-//   observations, exactly as the dense chi-square kernel does, and
+//   observations, exactly as the dense chi-square kernel does (in mixed
+//   precision from the block's LDS copy of the Kepler starting-value table), and
 //   E. lanes over chains: accepts iff 2 ln u < chi2(x) - chi2(y) and K >= 0,
 //      copying y into the chain.
 // Everything one lane hands to another goes through the wave's slice of LDS;
@@ -114,6 +115,14 @@ __global__ void __launch_bounds__(256) k_demc_half(DenseArgs a, DemcArgs m, int 
     int *okpl_l = reinterpret_cast<int *>(r12_l + 2 * sb);
     int *bad_l = okpl_l + sb * npl;
     int *supp_l = bad_l + sb;
+    // mixed: the block's copy of the Kepler starting-value table after the wave slices
+    const uint32_t *tab = nullptr;
+    if constexpr (Pol::kMixed) {
+        uint32_t *t = reinterpret_cast<uint32_t *>(smem + (size_t)wpb * demc_lds_per_wave(sb, npl, d, sizeof(Rec)));
+        for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) t[q] = kep_start_tab[q];
+        __syncthreads();
+        tab = t;
+    }
 
     const int64_t nh = m.nh;
     const uint64_t g = m.gen_ptr ? *m.gen_ptr + m.gen : m.gen;
@@ -208,7 +217,7 @@ __global__ void __launch_bounds__(256) k_demc_half(DenseArgs a, DemcArgs m, int 
                 ModelAcc mm[NCH];
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) Pol::model_init(mm[c]);
-                for (int j = 0; j < npl; ++j) pol_add_planet<Pol, NCH>(recs[s * npl + j], o, mm, a);
+                for (int j = 0; j < npl; ++j) pol_add_planet<Pol, NCH>(recs[s * npl + j], o, mm, a, tab);
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     if (o[c].in) {
@@ -243,8 +252,9 @@ static hipError_t launch_demc_half_t(DemcArgs m, DenseArgs a, int h, LaunchShape
     const int block = shape.block > 0 ? shape.block : 256;
     const int wpb = block / 64;
     const size_t rec = sizeof(typename Pol::Rec);
+    const size_t table = Pol::kMixed ? sizeof(kep_start_tab) : 0;
     int sb_cap = kMaxSB;
-    while (sb_cap > 1 && (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec) > 48 * 1024) sb_cap /= 2;
+    while (sb_cap > 1 && (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec) + table > 48 * 1024) sb_cap /= 2;
     const int nch_needed = (int)((a.n_obs + 63) / 64);
     void (*kern)(DenseArgs, DemcArgs, int);
     if (nch_needed <= 1) kern = k_demc_half<Pol, 1>;
@@ -254,7 +264,7 @@ static hipError_t launch_demc_half_t(DemcArgs m, DenseArgs a, int h, LaunchShape
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
         int occ = 0;
-        const size_t lds = (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec);
+        const size_t lds = (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec) + table;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess || occ <= 0) occ = 1;
         per_cu = occ;
     }
@@ -265,7 +275,7 @@ static hipError_t launch_demc_half_t(DemcArgs m, DenseArgs a, int h, LaunchShape
     int64_t sb = (m.nh + mw - 1) / mw;
     sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
     a.sb = (int)sb;
-    const size_t lds = (size_t)wpb * demc_lds_per_wave(a.sb, a.n_pl, m.d, rec);
+    const size_t lds = (size_t)wpb * demc_lds_per_wave(a.sb, a.n_pl, m.d, rec) + table;
     const int64_t n_batches = (m.nh + sb - 1) / sb;
     int64_t grid = (n_batches + wpb - 1) / wpb;
     const int64_t cap = (int64_t)device_cu_count() * per_cu;

@@ -746,6 +746,9 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     const int64_t budget = table ? (int64_t)(32 * 1024) - (int64_t)kDenseTableBytes - 16 : (int64_t)(48 * 1024);
     int64_t sb_cap = budget / (int64_t)rec_bytes;
     sb_cap = sb_cap < 1 ? 1 : (sb_cap > kMaxSB ? kMaxSB : sb_cap);
+    // a multiple of 16 systems reads whole 128-byte lines of every parameter plane:
+    // a line split between two batches may be fetched by two XCDs' L2s
+    if (sb_cap > 16) sb_cap &= ~(int64_t)15;
     size_t lds = lds_of(sb_cap);
     const int nch_needed = (int)((a.n_obs + 63) / 64);
     void (*kern)(DenseArgs);
