@@ -57,9 +57,11 @@ __device__ __forceinline__ bool astro_setup(const AstroArgs &a, int64_t p, Astro
 }
 
 // cos E and sin E of one planet at tt = t - t0, mixed precision: binary64
-// centred phase M, binary32 Danby iteration on (float)M, one binary64 Newton
-// step against M, sin/cos carried to the corrected E to second order.
-__device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int max_iter, double &cE, double &sE)
+// centred phase M, binary32 Danby iteration on (float)M (from the starting-value
+// table where e <= KEP_TAB_EMAX), one binary64 Newton step against M, sin/cos
+// carried to the corrected E to second order.
+__device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int max_iter, const uint32_t *tab,
+                                               double &cE, double &sE)
 {
     const double q0 = tt * r.ph.rP;
     const double res = fma(-q0, r.ph.P, tt);
@@ -67,7 +69,7 @@ __device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int
     const double u = __builtin_amdgcn_fract(__builtin_amdgcn_fract(q) + r.ph.m0h);
     const double M = fma(u, kTwoPi, -kPi);
     float s32, omc32;
-    const double E0 = (double)kepler32((float)M, r.k, r.niter, max_iter, r.check != 0, s32, omc32);
+    const double E0 = (double)kepler32_start((float)M, r.k, tab, r.niter, max_iter, r.check != 0, s32, omc32);
     double s, c;
     sincos_reduced(E0, s, c);
     const double d = -(E0 - r.e * s - M) / (1.0 - r.e * c);
@@ -98,6 +100,14 @@ __global__ void __launch_bounds__(256) k_astro(AstroArgs a)
     const int npl = a.n_pl;
     AstroRec *recs = reinterpret_cast<AstroRec *>(smem) + (size_t)wib * a.sb * npl;
     int *sysbad = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * npl * sizeof(AstroRec)) + wib * a.sb;
+    // mixed: the block's copy of the Kepler starting-value table
+    const uint32_t *tab = nullptr;
+    if constexpr (MIXED) {
+        __shared__ uint32_t tab_s[(KEP_TAB_NE - 1) * KEP_TAB_NM];
+        for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) tab_s[q] = kep_start_tab[q];
+        __syncthreads();
+        tab = tab_s;
+    }
 
     const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
@@ -170,7 +180,7 @@ __global__ void __launch_bounds__(256) k_astro(AstroArgs a)
                     for (int c = 0; c < NCH; ++c) {
                         if (!o[c].in) continue;
                         double cE, sE;
-                        if (MIXED) astro_cs_mixed(r, o[c].t - a.t0, a.max_iter, cE, sE);
+                        if (MIXED) astro_cs_mixed(r, o[c].t - a.t0, a.max_iter, tab, cE, sE);
                         else astro_cs_f64(r, o[c].t - a.t0, fixed, a.max_iter, cE, sE);
                         const double X = cE - r.e, Y = r.b * sE;
                         ra[c] = fma(r.B, X, fma(r.G, Y, ra[c]));

@@ -73,11 +73,13 @@ __device__ __forceinline__ bool grad_setup(double P, double K, double e, double 
 //   x[3] = sin(w+f)              dv/dw  = -K x[3] - K e sin w
 //   x[4] = sin(w+f) df/dM        dv/dM0 = -K x[4]
 // with q = (t - t0)/P, df/dM = b/D^2, df/de = sin E (2 - e cos E - e^2)/(b D^2).
-__device__ __forceinline__ float grad_terms(const GradPlanet<float> &g, double tt, int max_iter, float (&x)[5])
+// tab: the block's LDS copy of the Kepler starting-value table, or null.
+__device__ __forceinline__ float grad_terms(const GradPlanet<float> &g, double tt, int max_iter, float (&x)[5],
+                                            const uint32_t *tab = nullptr)
 {
     const float M = mean_anomaly32(tt, g.ph);
     float sE, omcE;
-    kepler32(M, g.k, g.niter, max_iter, g.check != 0, sE, omcE);
+    kepler32_start(M, g.k, tab, g.niter, max_iter, g.check != 0, sE, omcE);
     const float iD = rcp32(fmaf(g.k.e, omcE, g.k.ome));   // 1 / (1 - e cos E)
     const float cf = (g.k.ome - omcE) * iD;                 // cos f = (cos E - e)/D
     const float sf = g.b * sE * iD;                         // sin f = b sin E / D

@@ -303,6 +303,9 @@ template <int NPL, bool NLL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grad_waves_per_simd<NPL>())))
 k_grad_mixed(DenseArgs a)
 {
+    __shared__ uint32_t tab[(KEP_TAB_NE - 1) * KEP_TAB_NM];    // Kepler starting values
+    for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) tab[q] = kep_start_tab[q];
+    __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const bool has_jit = a.jitter != nullptr;
     for (int64_t sys = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sys < a.n_sys; sys += stride) {
@@ -335,7 +338,7 @@ k_grad_mixed(DenseArgs a)
             Kahan32 msum;
             msum.init();
 #pragma unroll
-            for (int j = 0; j < NPL; ++j) msum.add(grad_terms(pl[j], tt, a.max_iter, x[j]));
+            for (int j = 0; j < NPL; ++j) msum.add(grad_terms(pl[j], tt, a.max_iter, x[j], tab));
             const float r = (float)(((double)msum.s - (double)msum.c + gam) - vo);
             const float var = (float)(sg * sg) + jit2;
             ok = ok && var > 0.0f;

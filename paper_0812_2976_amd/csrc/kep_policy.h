@@ -33,6 +33,35 @@ __device__ __forceinline__ float half_hi(uint32_t w)
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
 }
 
+// Kepler solve of one lane for kernels whose lanes hold different planets: from
+// the LDS starting-value table (bilinear in (e, |M|), row and weight from the
+// binary32 e) and the accurate last step alone where e <= KEP_TAB_EMAX and the
+// step count is the schedule's, else kepler32.  Returns E and sin E, 1 - cos E.
+__device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const uint32_t *tab, int niter,
+                                                int max_iter, bool check, float &sinE, float &omcE)
+{
+    if (tab != nullptr && !check && k.e <= (float)KEP_TAB_EMAX) {
+        const float fi = k.e * (float)((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
+        const int i = min((int)fi, KEP_TAB_NE - 2);
+        const float twe = fi - (float)i;
+        const float fj = fminf(fabsf(M) * KEP_TAB_MSCALE, 128.0f);   // NaN -> 128
+        const int j = (int)fj;
+        const float wm = __builtin_amdgcn_fractf(fj);
+        const uint32_t *q = tab + i * KEP_TAB_NM + j;
+        const uint32_t w0 = q[0], w1 = q[1];
+        const float r0 = fmaf(twe, half_hi(w0), half_lo(w0));
+        const float r1 = fmaf(twe, half_hi(w1), half_lo(w1));
+        float E = copysignf(fmaf(wm, r1 - r0, r0), M);
+        SinCos32 sc;
+        const float st = danby_step32<false, true>(E, M, k, 0.0f, 0.0f, sc);
+        sinE = sc.s;
+        omcE = sc.omc;
+        rotate32(sinE, omcE, st);
+        return E;
+    }
+    return kepler32(M, k, niter, max_iter, check, sinE, omcE);
+}
+
 // ------------------------------------------------------------------ mixed
 struct RecMixed {          // 56 bytes, one per (system, planet)
     Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
