@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 template <int NCH>
 __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed *recs, int npl, int64_t o0,
                                              int64_t nrem, double gam, double jit, bool has_jit, Kahan32 &chi,
-                                             bool &bad_obs)
+                                             bool &bad_obs, const uint32_t *tab)
 {
     const int lane = __lane_id();
     ObsMixed o[NCH];
@@ -470,7 +470,7 @@ __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed
     PolMixed::ModelAcc m[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) PolMixed::model_init(m[c]);
-    for (int j = 0; j < npl; ++j) PolMixed::add_planet<NCH>(recs[j], o, m, a.max_iter, 0);
+    for (int j = 0; j < npl; ++j) PolMixed::add_planet<NCH>(recs[j], o, m, a.max_iter, 0, tab);
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
         if (o[c].in) {
@@ -482,11 +482,11 @@ __device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed
 
 // One planet's velocity (the arithmetic of PolMixed::add_planet) from this
 // lane's own planet record: lanes of different systems differ in step count.
-__device__ __forceinline__ float ragged_vel_lane(const RecMixed &r, double tt, int max_iter)
+__device__ __forceinline__ float ragged_vel_lane(const RecMixed &r, double tt, int max_iter, const uint32_t *tab)
 {
     const float M = mean_anomaly32(tt, r.ph);
     float s, omc;
-    kepler32(M, r.k, r.niter, max_iter, r.check != 0, s, omc);
+    kepler32_start(M, r.k, tab, r.niter, max_iter, r.check != 0, s, omc);
     const float D = fmaf(r.k.e, omc, r.k.ome);           // 1 - e cos E
     const float num = fmaf(r.B, s, fmaf(-r.A, omc, r.A));  // A cos E + B sin E
     return num * rcp32(D);
@@ -525,6 +525,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
     int *tpre = okpl + sb * kMaxPl;
     int *bad = tpre + sb + 1;
     const bool has_jit = a.jitter != nullptr;
+    __shared__ uint32_t tab[(KEP_TAB_NE - 1) * KEP_TAB_NM];    // Kepler starting values
+    for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) tab[q] = kep_start_tab[q];
+    __syncthreads();
 
     for (;;) {
         unsigned int item = 0;
@@ -596,10 +599,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
             bool bad_obs = false;
             for (int64_t g = 0; g < nfull; g += 64 * GMAX) {
                 const int64_t left = nfull - g;
-                if (left <= 64) ragged_group<1>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
-                else if (GMAX == 2 || left <= 128) ragged_group<2>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
-                else if (left <= 192) ragged_group<3>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
-                else ragged_group<GMAX>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs);
+                if (left <= 64) ragged_group<1>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
+                else if (GMAX == 2 || left <= 128) ragged_group<2>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
+                else if (left <= 192) ragged_group<3>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
+                else ragged_group<GMAX>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
             }
             const double tot = wave_sum(chi.value());
             const bool b = __any(bad_obs);
@@ -660,7 +663,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                     PolMixed::ModelAcc m;
                     PolMixed::model_init(m);
                     const RecMixed *rs = recs + sc * kMaxPl;
-                    for (int j = 0; j < npl; ++j) m.k.add(ragged_vel_lane(rs[j], o.tt, a.max_iter));
+                    for (int j = 0; j < npl; ++j) m.k.add(ragged_vel_lane(rs[j], o.tt, a.max_iter, tab));
                     const double gam = a.offset ? a.offset[sys] : 0.0;
                     const double jit = a.jitter ? a.jitter[sys] : 0.0;
                     Kahan32 cx;
