@@ -29,10 +29,10 @@ namespace kep {
 template <class Pol, int NCH>
 constexpr int dense_waves_per_simd() { return (Pol::kMixed && NCH <= 4) ? 5 : 1; }
 
-// The mixed velocity kernels start the Kepler solve from the table of
-// kep_start_tab.h, copied once into each block's LDS behind the records.
+// The mixed kernels start the Kepler solve from the table of kep_start_tab.h,
+// copied once into each block's LDS behind the records.
 template <class Pol, int MODE>
-constexpr bool dense_uses_table() { return Pol::kMixed && MODE != kAnomalies; }
+constexpr bool dense_uses_table() { return Pol::kMixed; }
 
 __host__ __device__ inline size_t dense_table_offset(int wpb, int sb, int n_pl, size_t rec_size)
 {
@@ -130,8 +130,8 @@ k_dense(DenseArgs a)
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) {
                             float sE, omcE;
-                            const float E = kepler32(mean_anomaly32(o[c].tt, rr.ph), rr.k, niter, a.max_iter,
-                                                     rr.check != 0, sE, omcE);
+                            const float E = kepler32_start(mean_anomaly32(o[c].tt, rr.ph), rr.k, tab, niter,
+                                                           a.max_iter, rr.check != 0, sE, omcE);
                             if (o[c].in) {
                                 const int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
                                 row[k] = (sbad || !o[c].ok) ? __builtin_nanf("") : E;
