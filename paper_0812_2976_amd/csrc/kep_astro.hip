@@ -103,9 +103,8 @@ __global__ void __launch_bounds__(256) k_astro(AstroArgs a)
     // mixed: the block's copy of the Kepler starting-value table
     const uint32_t *tab = nullptr;
     if constexpr (MIXED) {
-        __shared__ uint32_t tab_s[(KEP_TAB_NE - 1) * KEP_TAB_NM];
-        for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) tab_s[q] = kep_start_tab[q];
-        __syncthreads();
+        __shared__ uint32_t tab_s[kTabWords];
+        load_start_table(tab_s);
         tab = tab_s;
     }
 

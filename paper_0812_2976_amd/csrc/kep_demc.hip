@@ -119,8 +119,7 @@ __global__ void __launch_bounds__(256) k_demc_half(DenseArgs a, DemcArgs m, int 
     const uint32_t *tab = nullptr;
     if constexpr (Pol::kMixed) {
         uint32_t *t = reinterpret_cast<uint32_t *>(smem + (size_t)wpb * demc_lds_per_wave(sb, npl, d, sizeof(Rec)));
-        for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) t[q] = kep_start_tab[q];
-        __syncthreads();
+        load_start_table(t);
         tab = t;
     }
 

@@ -59,8 +59,7 @@ k_dense(DenseArgs a)
     const uint32_t *tab = nullptr;
     if constexpr (dense_uses_table<Pol, MODE>()) {
         uint32_t *t = reinterpret_cast<uint32_t *>(smem + dense_table_offset(wpb, a.sb, a.n_pl, sizeof(Rec)));
-        for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) t[q] = kep_start_tab[q];
-        __syncthreads();
+        load_start_table(t);
         tab = t;
     }
 
@@ -303,9 +302,8 @@ template <int NPL, bool NLL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grad_waves_per_simd<NPL>())))
 k_grad_mixed(DenseArgs a)
 {
-    __shared__ uint32_t tab[(KEP_TAB_NE - 1) * KEP_TAB_NM];    // Kepler starting values
-    for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) tab[q] = kep_start_tab[q];
-    __syncthreads();
+    __shared__ uint32_t tab[kTabWords];    // Kepler starting values
+    load_start_table(tab);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const bool has_jit = a.jitter != nullptr;
     for (int64_t sys = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sys < a.n_sys; sys += stride) {
@@ -525,9 +523,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
     int *tpre = okpl + sb * kMaxPl;
     int *bad = tpre + sb + 1;
     const bool has_jit = a.jitter != nullptr;
-    __shared__ uint32_t tab[(KEP_TAB_NE - 1) * KEP_TAB_NM];    // Kepler starting values
-    for (int q = threadIdx.x; q < (KEP_TAB_NE - 1) * KEP_TAB_NM; q += blockDim.x) tab[q] = kep_start_tab[q];
-    __syncthreads();
+    __shared__ uint32_t tab[kTabWords];    // Kepler starting values
+    load_start_table(tab);
 
     for (;;) {
         unsigned int item = 0;

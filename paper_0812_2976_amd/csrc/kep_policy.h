@@ -33,25 +33,48 @@ __device__ __forceinline__ float half_hi(uint32_t w)
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
 }
 
+// The starting-value table (Sec. 5.4's interpolated guess; kep_start_tab.h).
+constexpr int kTabWords = (KEP_TAB_NE - 1) * KEP_TAB_NM;
+
+// Copy of the table into a block's LDS; every thread of the block calls it
+// before any wave reads the table (it ends with the block barrier).
+__device__ __forceinline__ void load_start_table(uint32_t *dst)
+{
+    for (int q = threadIdx.x; q < kTabWords; q += blockDim.x) dst[q] = kep_start_tab[q];
+    __syncthreads();
+}
+
+// Knot of |M| and its fraction: j in [0, 128] (a NaN clamps to the last knot, so
+// the two words j, j + 1 read after it stay inside the row).
+__device__ __forceinline__ int start_knot(float M, float &wm)
+{
+    const float fj = fminf(fabsf(M) * KEP_TAB_MSCALE, 128.0f);
+    wm = __builtin_amdgcn_fractf(fj);
+    return (int)fj;
+}
+
+// Bilinear starting value from the words of knots j and j + 1 of a row:
+// weight twe towards the next eccentricity row, wm towards knot j + 1, sign of M.
+__device__ __forceinline__ float start_value(uint32_t w0, uint32_t w1, float twe, float wm, float M)
+{
+    const float r0 = fmaf(twe, half_hi(w0), half_lo(w0));
+    const float r1 = fmaf(twe, half_hi(w1), half_lo(w1));
+    return copysignf(fmaf(wm, r1 - r0, r0), M);
+}
+
 // Kepler solve of one lane for kernels whose lanes hold different planets: from
-// the LDS starting-value table (bilinear in (e, |M|), row and weight from the
-// binary32 e) and the accurate last step alone where e <= KEP_TAB_EMAX and the
-// step count is the schedule's, else kepler32.  Returns E and sin E, 1 - cos E.
+// the LDS starting-value table (row and weight from the binary32 e) and the
+// accurate last step alone where e <= KEP_TAB_EMAX and the step count is the
+// schedule's, else kepler32.  Returns E and sin E, 1 - cos E.
 __device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const uint32_t *tab, int niter,
                                                 int max_iter, bool check, float &sinE, float &omcE)
 {
     if (tab != nullptr && !check && k.e <= (float)KEP_TAB_EMAX) {
         const float fi = k.e * (float)((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
         const int i = min((int)fi, KEP_TAB_NE - 2);
-        const float twe = fi - (float)i;
-        const float fj = fminf(fabsf(M) * KEP_TAB_MSCALE, 128.0f);   // NaN -> 128
-        const int j = (int)fj;
-        const float wm = __builtin_amdgcn_fractf(fj);
-        const uint32_t *q = tab + i * KEP_TAB_NM + j;
-        const uint32_t w0 = q[0], w1 = q[1];
-        const float r0 = fmaf(twe, half_hi(w0), half_lo(w0));
-        const float r1 = fmaf(twe, half_hi(w1), half_lo(w1));
-        float E = copysignf(fmaf(wm, r1 - r0, r0), M);
+        float wm;
+        const uint32_t *q = tab + i * KEP_TAB_NM + start_knot(M, wm);
+        float E = start_value(q[0], q[1], fi - (float)i, wm, M);
         SinCos32 sc;
         const float st = danby_step32<false, true>(E, M, k, 0.0f, 0.0f, sc);
         sinE = sc.s;
@@ -167,18 +190,12 @@ struct PolMixed {
             uint32_t q0[NCH], q1[NCH];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const float fj = fminf(fabsf(M[c]) * KEP_TAB_MSCALE, 128.0f);   // NaN -> 128
-                const int j = (int)fj;
-                wm[c] = __builtin_amdgcn_fractf(fj);
-                q0[c] = row[j];                        // binary16 (E_i, E_i+1 - E_i) at knot j
-                q1[c] = row[j + 1];
+                const uint32_t *q = row + start_knot(M[c], wm[c]);
+                q0[c] = q[0];                          // binary16 (E_i, E_i+1 - E_i) at knot j
+                q1[c] = q[1];
             }
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-                const float r0 = fmaf(twe, half_hi(q0[c]), half_lo(q0[c]));
-                const float r1 = fmaf(twe, half_hi(q1[c]), half_lo(q1[c]));
-                E[c] = copysignf(fmaf(wm[c], r1 - r0, r0), M[c]);
-            }
+            for (int c = 0; c < NCH; ++c) E[c] = start_value(q0[c], q1[c], twe, wm[c], M[c]);
 #pragma unroll
             for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false, true>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
         } else if (niter > 0) {
