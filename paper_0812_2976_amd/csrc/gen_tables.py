@@ -208,7 +208,7 @@ def start_scan(pairs, emax, n_e=400):
     return far, err
 
 
-def write_start_table(emax):
+def write_start_table(emax, out=START_OUT):
     pairs = start_table(emax)
     far, err = start_scan(pairs, emax)
     assert err <= 1e-9, err
@@ -235,7 +235,7 @@ def write_start_table(emax):
     for k in range(0, len(flat), 8):
         lines.append("    " + ", ".join(flat[k:k + 8]) + ",")
     lines.append("};")
-    with open(START_OUT, "w") as f:
+    with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(f"start table: far {far:.3e}, one step {err:.3e}")
 

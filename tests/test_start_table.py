@@ -88,3 +88,16 @@ def test_start_and_one_step(tab):
     print(f"start {far:.3e} rad, after one step {err:.3e} rad")
     assert far <= 4e-3
     assert err <= 1e-9
+
+
+def test_header_is_what_the_generator_writes(tmp_path):
+    """kep_start_tab.h is exactly the output of gen_tables.py for the schedule's
+    two-step bound (no hand edits; the generator's own scan asserts 1e-9)."""
+    import importlib.util
+    path = os.path.join(os.path.dirname(HEADER), "gen_tables.py")
+    spec = importlib.util.spec_from_file_location("gen_tables", path)
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    out = tmp_path / "kep_start_tab.h"
+    gen.write_start_table(_read_header()[2], out=str(out))
+    assert out.read_text() == open(HEADER).read()
