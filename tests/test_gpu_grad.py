@@ -50,10 +50,12 @@ def test_grad_fp64_matches_oracle(dev, case):
     dict(n_sys=300, n_pl=3, n_obs=100, jitter=True),
     dict(n_sys=100, n_pl=6, n_obs=300),
     dict(n_sys=256, n_pl=4, n_obs=256, stress=True),
+    # lanes on both sides of the starting-value table's range within one wavefront
+    dict(n_sys=640, n_pl=3, n_obs=120, e_range=(0.0, 0.99)),
 ])
 def test_grad_mixed_matches_oracle(dev, case):
     wl = W.dense("c4", n_sys=case["n_sys"], n_pl=case["n_pl"], n_obs=case["n_obs"],
-                 jitter=case.get("jitter", False), stress=case.get("stress", False))
+                 jitter=case.get("jitter", False), stress=case.get("stress", False), e_range=case.get("e_range"))
     g = W.to_gpu(wl, dev)
     chi2, grad = kp.rv_chisq_grad(**g, prec="mixed")
     chi2, grad = chi2.cpu().numpy(), grad.cpu().numpy()
