@@ -33,6 +33,12 @@ MUTANTS = {
                           "JJ[a * np - a * (a - 1) / 2 + (b - a)] += row[a] * row[b];"),
     "gn_jtwr_sign": ("Jr[a] += wk * row[a] * r;", "Jr[a] -= wk * row[a] * r;"),
     "gn_offset_column": ("row[np - 1] = 1.0L;", "row[np - 1] = 0.0L;"),
+    # gradient error scales
+    "scale_r_abs_dropped": ("sr[5 * j + a] += fabsl(c * dv[a]);", "sr[5 * j + a] += c * dv[a];"),
+    "scale_1_factor_two_dropped": ("s1[5 * j + a] += 2.0L * wk * fabsl(dv[a]);", "s1[5 * j + a] += wk * fabsl(dv[a]);"),
+    "scale_1_weight_dropped": ("s1[npar - 1] += 2.0L * wk;", "s1[npar - 1] += 2.0L;"),
+    "scale_r_offset_abs_dropped": ("sr[npar - 1] += fabsl(c);", "sr[npar - 1] += c;"),
+    "scale_row_mixup": ("s1[5 * j + a] += 2.0L * wk * fabsl(dv[a]);", "s1[5 * j + a] += 2.0L * wk * fabsl(dv[(a + 1) % 5]);"),
     # population sampler (pins in test_oracle_demc.py)
     "demc_acceptance_without_half": ("if (2.0 * log(u) < c_old - c_new)", "if (log(u) < c_old - c_new)", "demc"),
     "demc_own_half_differences": ("const double *xo = s->x + (int64_t)(1 - h) * d * nh;", "const double *xo = xh;",

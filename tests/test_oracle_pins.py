@@ -371,6 +371,85 @@ def test_grad_zero_at_noise_free_truth():
     assert np.max(np.abs(grad[:, 0])) < 1e-6
 
 
+# ------------------------------------------- gradient error scales (Sec. 6)
+# The scales S_r = sum_k |2 w_k r_k dv_k/dtheta| and S_1 = sum_k 2 w_k |dv_k/dtheta|
+# turn a residual error and a relative error per term into a bound on the
+# gradient's error; every mixed-precision gradient tolerance is built from them.
+def _scales_case(jitter):
+    wl = _small_dense(n_sys=4, n_pl=2, n_obs=30, offset=True, jitter=jitter)
+    wl.t0 = 2455500.0
+    synth.with_observations(wl, _mp_model)
+    return wl
+
+
+@pytest.mark.parametrize("jitter", [False, True])
+def test_grad_scales_offset_and_amplitude_closed_forms(jitter):
+    """Offset row: dv/dgamma = 1, so S_1 = 2 sum w and S_r = 2 sum w |r|.  K rows:
+    the model is linear in K_j (Eq. 3), dv/dK_j = v_j / K_j, so S_1 = (2/K_j) sum w |v_j|
+    and S_r = (2/K_j) sum w |r v_j|.  w = 1/(sigma^2 + s^2) (Eq. 5)."""
+    wl = _scales_case(jitter)
+    d = _dense(wl)
+    _, _, s_r, s_1 = oracle.chisq_grad_scales(d)
+    model = oracle.rv_model(d)
+    for i in range(wl.n_sys):
+        s = 0.0 if wl.jitter is None else wl.jitter[i]
+        w = 1.0 / (wl.sigma ** 2 + s ** 2)
+        r = model[i] - wl.v
+        assert s_1[-1, i] == pytest.approx(2 * np.sum(w), rel=1e-13)
+        assert s_r[-1, i] == pytest.approx(2 * np.sum(w * np.abs(r)), rel=1e-12)
+        for j in range(wl.n_pl):
+            vj = np.array([oracle.planet_rv(tk, wl.t0, wl.P[j, i], wl.K[j, i], wl.e[j, i], wl.w[j, i],
+                                            wl.M0[j, i]) for tk in wl.t])
+            K = wl.K[j, i]
+            assert s_1[5 * j + 1, i] == pytest.approx(2 / K * np.sum(w * np.abs(vj)), rel=1e-12)
+            assert s_r[5 * j + 1, i] == pytest.approx(2 / K * np.sum(w * np.abs(r * vj)), rel=1e-11)
+
+
+def test_grad_scales_match_finite_difference_terms():
+    """Every row of S_1 and S_r against the per-observation derivatives dv_k/dtheta
+    taken by binary64 central differences of one planet's velocity (Eq. 3), with the
+    residuals of the oracle's model: a wrong term, weight or row in the scales fails."""
+    wl = _scales_case(False)
+    d = _dense(wl)
+    _, _, s_r, s_1 = oracle.chisq_grad_scales(d)
+    model = oracle.rv_model(d)
+    w = 1.0 / wl.sigma ** 2
+    span = np.max(np.abs(wl.t - wl.t0))
+    names = ("P", "K", "e", "w", "M0")
+    for i in range(wl.n_sys):
+        r = model[i] - wl.v
+        for j in range(wl.n_pl):
+            par = {nm: getattr(wl, nm)[j, i] for nm in names}
+            for a, nm in enumerate(names):
+                x0 = par[nm]
+                h = 1e-6 * x0 * x0 / (TWO_PI * span) if nm == "P" else 1e-6 * max(abs(x0), 1.0)
+                hi, lo = dict(par), dict(par)
+                hi[nm], lo[nm] = x0 + h, x0 - h
+                dv = np.array([(oracle.planet_rv(tk, wl.t0, hi["P"], hi["K"], hi["e"], hi["w"], hi["M0"]) -
+                                oracle.planet_rv(tk, wl.t0, lo["P"], lo["K"], lo["e"], lo["w"], lo["M0"])) / (2 * h)
+                               for tk in wl.t])
+                assert s_1[5 * j + a, i] == pytest.approx(np.sum(2 * w * np.abs(dv)), rel=2e-6), (i, j, nm)
+                assert s_r[5 * j + a, i] == pytest.approx(np.sum(np.abs(2 * w * r * dv)), rel=2e-6), (i, j, nm)
+
+
+def test_grad_scales_bound_the_gradient():
+    """|g| <= S_r componentwise (triangle inequality), with equality where every term
+    has one sign: with a large offset every residual is positive, so the offset row
+    has g = S_r exactly.  S_1 >= 0 and S_r <= max|r| S_1."""
+    wl = _scales_case(True)
+    d = _dense(wl)
+    _, g, s_r, s_1 = oracle.chisq_grad_scales(d)
+    assert np.all(np.abs(g) <= s_r * (1 + 1e-14))
+    assert np.all(s_1 > 0)
+    model = oracle.rv_model(d)
+    rmax = np.max(np.abs(model - wl.v[None, :]), axis=1)
+    assert np.all(s_r <= rmax[None, :] * s_1 * (1 + 1e-14))
+    wl.offset = wl.offset + 1e4
+    _, g, s_r, _ = oracle.chisq_grad_scales(_dense(wl))
+    assert np.all(g[-1] > 0)
+    assert np.allclose(g[-1], s_r[-1], rtol=1e-13, atol=0)
+
+
 # ------------------------------------------------------------------ ragged CSR
 def test_ragged_equals_per_system_dense():
     """CSR packing changes only the layout: each ragged system equals a dense
