@@ -550,7 +550,8 @@ class RVChiSq(torch.autograd.Function):
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
         n_pl = ctx.n_pl
+        need = ctx.needs_input_grad
         gp = grad[:5 * n_pl].view(n_pl, 5, -1) * g[None, None, :]
-        d = [gp[:, i, :] for i in range(5)]
-        doff = grad[5 * n_pl] * g
+        d = [gp[:, i, :] if need[i] else None for i in range(5)]
+        doff = grad[5 * n_pl] * g if need[5] else None     # None also when offset was None
         return d[0], d[1], d[2], d[3], d[4], doff, None, None, None, None, None, None

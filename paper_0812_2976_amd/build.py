@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkepler.so")
-SOURCES = ["kep_kernels.hip", "kep_demc.hip", "kep_astro.hip", "kep_gn.hip", "kep_api.cpp"]
+SOURCES = ["kep_kernels.hip", "kep_adjoint.hip", "kep_demc.hip", "kep_astro.hip", "kep_gn.hip", "kep_api.cpp"]
 # Per-source flags.  The Gauss-Newton kernel's matrix products accumulate in
 # ordinary VGPRs (gfx950 allows it): without this the compiler moves the
 # accumulators to AGPRs and back around every unrolled group of products and
@@ -41,14 +41,18 @@ def build(verbose: bool = False) -> str:
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
+    procs = []
+    for src in SOURCES:           # the sources compile independently: in parallel
         obj = os.path.join(bdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"]
         cmd = [hipcc()] + flags() + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((subprocess.Popen(cmd), cmd))
         objs.append(obj)
+    failed = [cmd for p, cmd in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -69,10 +70,15 @@ kep_status check_prec(kep_prec p, const char *fn)
     return KEP_OK;
 }
 
+// The device count is read until a device is found, then remembered: the
+// query costs as much as a small launch.
 kep_status check_device(const char *fn)
 {
+    static std::atomic<bool> found{false};
+    if (found.load(std::memory_order_relaxed)) return KEP_OK;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(KEP_ERR_DEVICE, "%s: no HIP device", fn);
+    found.store(true, std::memory_order_relaxed);
     return KEP_OK;
 }
 

@@ -226,11 +226,7 @@ hipError_t launch_astro_t(AstroArgs a, LaunchShape shape, hipStream_t st)
     else { kern = k_astro<MIXED, 4, MODEL>; nch = 4; }
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, rec_bytes * (size_t)sb_cap) !=
-                hipSuccess || occ <= 0)
-            occ = 1;
-        per_cu = occ;
+        per_cu = cached_occupancy((const void *)kern, block, rec_bytes * (size_t)sb_cap);
     }
     const int64_t mw = (int64_t)device_cu_count() * per_cu * wpb;
     int64_t sb = (a.n_sys + mw - 1) / (mw > 0 ? mw : 1);

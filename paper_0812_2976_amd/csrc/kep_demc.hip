@@ -262,10 +262,8 @@ static hipError_t launch_demc_half_t(DemcArgs m, DenseArgs a, int h, LaunchShape
     else kern = k_demc_half<Pol, 8>;
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
-        int occ = 0;
         const size_t lds = (size_t)wpb * demc_lds_per_wave(sb_cap, a.n_pl, m.d, rec) + table;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess || occ <= 0) occ = 1;
-        per_cu = occ;
+        per_cu = cached_occupancy((const void *)kern, block, lds);
     }
     const int64_t max_waves = (int64_t)device_cu_count() * per_cu * wpb;
     // ceil: every wave gets at most one batch when the cap allows it, so no wave

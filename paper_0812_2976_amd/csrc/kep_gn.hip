@@ -163,10 +163,6 @@ __global__ void __launch_bounds__(256) k_gn64(DenseArgs a, double *jtwr, double 
 }
 
 // ------------------------------------------------------------------ mixed
-struct GNPlanet32 {
-    GradPlanet<float> g;
-    float cP, ecw, Kcw, K, Kesw;   // 2 pi K / P, e cos w, K cos w, K, K e sin w
-};
 
 // The tile is column-major, T[c * kGn32Col + obs]: a lane writes its row with
 // unit stride across the wavefront, and the matrix operands are read as runs
@@ -179,7 +175,7 @@ constexpr int kGn32Col = 68;   // 64 observations + 4: consecutive columns start
 template <int NB>
 __host__ __device__ inline size_t gn32_lds_per_wave()
 {
-    const size_t b = (size_t)16 * NB * kGn32Col * sizeof(float) + (size_t)kMaxPl * sizeof(GNPlanet32);
+    const size_t b = (size_t)16 * NB * kGn32Col * sizeof(float) + (size_t)kMaxPl * sizeof(RecGrad);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -194,7 +190,7 @@ __global__ void __launch_bounds__(256) k_gn32(DenseArgs a, double *jtwr, double 
     const int wib = uniform_int(threadIdx.x >> 6);
     unsigned char *mine = smem + (size_t)wib * gn32_lds_per_wave<NB>();
     float *T = reinterpret_cast<float *>(mine);
-    GNPlanet32 *pl = reinterpret_cast<GNPlanet32 *>(mine + (size_t)NCOL * kGn32Col * sizeof(float));
+    RecGrad *pl = reinterpret_cast<RecGrad *>(mine + (size_t)NCOL * kGn32Col * sizeof(float));
 
     const int npl = a.n_pl;
     const int np = 5 * npl + 1;
@@ -211,16 +207,8 @@ __global__ void __launch_bounds__(256) k_gn32(DenseArgs a, double *jtwr, double 
         bool pok = true;
         if (lane < npl) {
             const int64_t p = (int64_t)lane * a.n_sys + sys;
-            const double P = a.P[p], K = a.K[p], e = a.e[p], w = a.w[p], M0 = a.M0[p];
-            GNPlanet32 q;
-            pok = grad_setup(P, K, e, w, M0, a.fixed_iter, q.g);
-            double sw, cw;
-            sincos(w, &sw, &cw);
-            q.cP = (float)(kTwoPi * K / P);
-            q.ecw = (float)(e * cw);
-            q.Kcw = (float)(K * cw);
-            q.K = (float)K;
-            q.Kesw = (float)(K * e * sw);
+            RecGrad q;
+            pok = grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], q);
             pl[lane] = q;
         }
         const double gam = a.offset ? a.offset[sys] : 0.0;
@@ -242,20 +230,29 @@ __global__ void __launch_bounds__(256) k_gn32(DenseArgs a, double *jtwr, double 
                 bool ook = isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0 && var > 0.0;
                 const float sw = ook ? __builtin_amdgcn_rsqf((float)var) : 0.0f;   // sqrt(w)
                 const double tt = t - a.t0;
-                Kahan32 msum;
-                msum.init();
+                // per planet: the binary32 Kepler solve from the starting-value
+                // table (read through the cache) or the schedule, the binary64
+                // correction of E and binary64 velocity, the derivative terms of the
+                // corrected root (as the mixed adjoint: kep_grad.h)
+                double model = 0.0;
                 for (int j = 0; j < npl; ++j) {
-                    const GNPlanet32 &q = pl[j];
-                    float x[5];
-                    msum.add(grad_terms(q.g, tt, a.max_iter, x));
+                    const RecGrad &q = pl[j];
+                    const double M64 = mean_anomaly64_exact(tt, q.ph);
+                    float M[1] = {(float)M64}, E[1], sv[1], omc[1];
+                    PolMixed::solve<1, false>(q.k, uniform_int(q.niter), uniform_int(q.check) != 0,
+                                              uniform_int(q.trow), q.twe, M, E, sv, omc, a.max_iter, kep_start_tab);
+                    float sE, cme, x[5];
+                    model += refine_velocity(q, E[0], M64, sE, cme);
+                    grad_terms_ce(q, sE, cme, (float)(tt * q.ph.rP), x);
+                    const float fK = (float)q.fK;
                     float *c = col + 5 * j * kGn32Col;
-                    c[0 * kGn32Col] = sw * (q.cP * x[0]);
-                    c[1 * kGn32Col] = sw * (x[1] + q.ecw);
-                    c[2 * kGn32Col] = sw * fmaf(-q.K, x[2], q.Kcw);
-                    c[3 * kGn32Col] = -sw * fmaf(q.K, x[3], q.Kesw);
-                    c[4 * kGn32Col] = -sw * (q.K * x[4]);
+                    c[0 * kGn32Col] = sw * ((float)q.fP * x[0]);
+                    c[1 * kGn32Col] = sw * x[1];
+                    c[2 * kGn32Col] = sw * (fK * x[2]);
+                    c[3 * kGn32Col] = -sw * (fK * x[3]);
+                    c[4 * kGn32Col] = -sw * (fK * x[4]);
                 }
-                const double r = (((double)msum.s - (double)msum.c) + gam) - vo;   // residual in binary64
+                const double r = (model + gam) - vo;   // residual in binary64
                 col[(np - 1) * kGn32Col] = sw;
                 col[np * kGn32Col] = sw * (float)r;
                 bad_obs = bad_obs || !ook;
@@ -323,10 +320,7 @@ hipError_t launch_gn_k(KernelFn kern, size_t per_wave, DenseArgs a, double *jtwr
     const size_t lds = (size_t)wpb * per_wave;
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, wpb * 64, lds) != hipSuccess || occ <= 0)
-            occ = 1;
-        per_cu = occ;
+        per_cu = cached_occupancy((const void *)kern, wpb * 64, lds);
     }
     int64_t grid = (a.n_sys + wpb - 1) / wpb;
     const int64_t cap = (int64_t)device_cu_count() * per_cu;

@@ -1,7 +1,9 @@
 // Per-planet terms of the chi-square gradient and of the Gauss-Newton products:
 // the velocity of one planet and its partial derivatives with respect to
-// (P, K, e, omega, M0).  Shared by the gradient kernels and the Gauss-Newton
-// kernel.
+// (P, K, e, omega, M0), in binary64 (the plain path) and in the mixed form
+// (binary32 Kepler solve, binary64 correction of the root and of the
+// velocity, binary32 derivative terms).  Shared by the gradient, likelihood
+// and Gauss-Newton kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,37 +19,9 @@ namespace kep {
 // so no iteration is differentiated.
 template <class T> struct GradPlanet;
 
-template <> struct GradPlanet<float> {
-    Phase64 ph;                // P, 1/P, fract(M0/(2 pi) + 1/2)
-    Ecc32 k;                   // e, 1 - e, e/2, e/6
-    float b, K, cw, sw;        // sqrt(1 - e^2), K, cos w, sin w
-    float Kecw, c0;            // K e cos w, 2 - e - e^2
-    int niter, check;
-};
-
 template <> struct GradPlanet<double> {
     double P, rP, M0, e, b, K, cw, sw;
 };
-
-__device__ __forceinline__ bool grad_setup(double P, double K, double e, double w, double M0, int fixed_iter,
-                                           GradPlanet<float> &g)
-{
-    bool ok = planet_ok(P, K, e, w, M0);
-    if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
-    g.ph = make_phase64(P, M0);
-    g.k = make_ecc32(e);
-    g.b = (float)sqrt((1.0 - e) * (1.0 + e));
-    g.K = (float)K;
-    double sw, cw;
-    sincos(w, &sw, &cw);
-    g.cw = (float)cw;
-    g.sw = (float)sw;
-    g.Kecw = (float)(K * e * cw);
-    g.c0 = (float)(2.0 - e - e * e);
-    g.niter = fixed_iter > 0 ? fixed_iter : sched32(g.k.e);
-    g.check = fixed_iter > 0 ? 1 : 0;
-    return ok;
-}
 
 __device__ __forceinline__ bool grad_setup(double P, double K, double e, double w, double M0, int,
                                            GradPlanet<double> &g)
@@ -64,35 +38,205 @@ __device__ __forceinline__ bool grad_setup(double P, double K, double e, double 
     return ok;
 }
 
-// Velocity of one planet at time tt = t - t0 and the five per-observation
-// terms whose weighted sums give its gradient (the planet's constant factors
-// are applied once per system):
-//   x[0] = sin(w+f) df/dM q      dv/dP  = (2 pi K / P) x[0]
-//   x[1] = cos(w+f)              dv/dK  = x[1] + e cos w
-//   x[2] = sin(w+f) df/de        dv/de  = K cos w - K x[2]
-//   x[3] = sin(w+f)              dv/dw  = -K x[3] - K e sin w
-//   x[4] = sin(w+f) df/dM        dv/dM0 = -K x[4]
-// with q = (t - t0)/P, df/dM = b/D^2, df/de = sin E (2 - e cos E - e^2)/(b D^2).
-// tab: the block's LDS copy of the Kepler starting-value table, or null.
-__device__ __forceinline__ float grad_terms(const GradPlanet<float> &g, double tt, int max_iter, float (&x)[5],
-                                            const uint32_t *tab = nullptr)
+// ---------------------------------------------------------------------------
+// Mixed-precision adjoint with a binary64 correction of the root.  The binary32
+// iteration leaves E with an error of a few 1e-7 rad / (1 - e cos E) (the
+// rounding of M to binary32 and of Kepler's residual near |M| ~ pi), and a
+// binary32 velocity carries a few ulp of 100 m/s: together about 1e-5 m/s.
+// Both enter the gradient through the residual r, which is small near a good
+// fit (|r| ~ sigma), so the gradient's error relative to its scale
+// sum_k |2 w r dv/dtheta| grows as the fit improves.  Below, one Newton step
+// with Danby's second-order term (Sec. 4.3) against the binary64 mean anomaly
+// corrects E, and the velocity is formed in binary64 from binary64 sin E and
+// cos E; the derivative terms stay binary32 (their relative error enters the
+// gradient only relative to that scale).
+
+// sin E and cos E in binary64 of a binary32 Kepler root (|E| <= pi for a
+// centred mean anomaly, a little more after a caller-fixed step count):
+// E = y + n pi/2 with n the nearest integer to 2E/pi and pi/2 in two parts,
+// each product taken inside a fused multiply-add, then the Taylor series of
+// sin y to y^13 and of cos y to y^14 on |y| <= pi/4 (remainders below
+// 2.1e-14 and 1.1e-15; coefficients 1/n!), rotated by the quadrant n mod 4.
+__device__ __forceinline__ void sincos_root64(float E, double &s, double &c)
 {
-    const float M = mean_anomaly32(tt, g.ph);
-    float sE, omcE;
-    kepler32_start(M, g.k, tab, g.niter, max_iter, g.check != 0, sE, omcE);
-    const float iD = rcp32(fmaf(g.k.e, omcE, g.k.ome));   // 1 / (1 - e cos E)
-    const float cf = (g.k.ome - omcE) * iD;                 // cos f = (cos E - e)/D
-    const float sf = g.b * sE * iD;                         // sin f = b sin E / D
-    const float cwf = g.cw * cf - g.sw * sf;                // cos(w + f)
-    const float swf = g.sw * cf + g.cw * sf;                // sin(w + f)
+    const float nf = rintf(E * 0.636619772f);
+    const int n = (int)nf;
+    const double dn = (double)nf;
+    const double y = fma(-dn, 6.123233995736766036e-17, fma(-dn, 1.5707963267948965580, (double)E));
+    const double y2 = y * y;
+    double ps = 1.0 / 6227020800.0;                 // 1/13!
+    ps = fma(ps, y2, -1.0 / 39916800.0);            // 1/11!
+    ps = fma(ps, y2, 1.0 / 362880.0);               // 1/9!
+    ps = fma(ps, y2, -1.0 / 5040.0);                // 1/7!
+    ps = fma(ps, y2, 1.0 / 120.0);                  // 1/5!
+    ps = fma(ps, y2, -1.0 / 6.0);                   // 1/3!
+    const double sy = fma(y * y2, ps, y);
+    double pc = -1.0 / 87178291200.0;               // 1/14!
+    pc = fma(pc, y2, 1.0 / 479001600.0);            // 1/12!
+    pc = fma(pc, y2, -1.0 / 3628800.0);             // 1/10!
+    pc = fma(pc, y2, 1.0 / 40320.0);                // 1/8!
+    pc = fma(pc, y2, -1.0 / 720.0);                 // 1/6!
+    pc = fma(pc, y2, 1.0 / 24.0);                   // 1/4!
+    pc = fma(pc, y2, -0.5);                         // 1/2!
+    const double cy = fma(y2, pc, 1.0);
+    // quadrant q = n mod 4: (sin, cos) = (sy, cy), (cy, -sy), (-sy, -cy), (-cy, sy)
+    const int q = n & 3;
+    const double s0 = (q & 1) ? cy : sy;
+    const double c0 = (q & 1) ? sy : cy;
+    s = (q & 2) ? -s0 : s0;
+    c = (q == 1 || q == 2) ? -c0 : c0;
+}
+
+// Per-planet record of the mixed adjoint (one per system and planet, in LDS).
+struct RecGrad {
+    Phase64 ph;                    // P, 1/P, fract(M0/(2 pi) + 1/2)
+    double e, A, B;                // binary64 e, K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
+    double fP, fK;                 // gradient row factors 2 pi K/P, K
+    Ecc32 k;                       // binary32 e, 1 - e, e/2, e/6
+    float b, rb, b2, c0;           // b, 1/b, 1 - e^2, 2 - 2 e^2
+    float cw, sw, bcw, bsw;        // cos w, sin w, b cos w, b sin w
+    float twe;                     // weight of table row trow + 1
+    int16_t niter;                 // Danby steps from the paper's guess (0: convergence test)
+    int8_t check;                  // 1 if the step count is fixed by the caller
+    int8_t trow;                   // row of the starting-value table, -1: the paper's guess
+};
+
+__device__ __forceinline__ bool grad_setup_rec(int fixed_iter, double P, double K, double e, double w, double M0,
+                                               RecGrad &r)
+{
+    const bool ok = planet_ok(P, K, e, w, M0);
+    if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
+    r.ph = make_phase64(P, M0);
+    r.k = make_ecc32(e);
+    const double b2 = (1.0 - e) * (1.0 + e), b = sqrt(b2);
+    double sw, cw;
+    sincos_reduced(w, sw, cw);     // to an ulp of w (|w| up to ~1e6 rad); few registers
+    r.e = e;
+    r.A = K * b2 * cw;
+    r.B = -K * b * sw;
+    r.fP = kTwoPi * K / P;
+    r.fK = K;
+    r.b = (float)b;
+    r.rb = (float)(1.0 / b);
+    r.b2 = (float)b2;
+    r.c0 = (float)(2.0 - 2.0 * e * e);
+    r.cw = (float)cw;
+    r.sw = (float)sw;
+    r.bcw = (float)(b * cw);
+    r.bsw = (float)(b * sw);
+    r.niter = (int16_t)(fixed_iter > 0 ? fixed_iter : sched32(r.k.e));
+    r.check = fixed_iter > 0 ? 1 : 0;
+    r.trow = -1;
+    r.twe = 0.0f;
+    if (fixed_iter <= 0 && e <= KEP_TAB_EMAX) {
+        const double fi = e * ((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
+        const int i = min((int)fi, KEP_TAB_NE - 2);
+        r.trow = (int8_t)i;
+        r.twe = (float)(fi - i);
+    }
+    return ok;
+}
+
+// Mean anomaly in binary64 for the corrected root, centred on [-pi, pi): the
+// quotient q = (t - t0)/P correctly rounded (the product with the correctly
+// rounded 1/P, then one correction by its exact remainder, t - t0 - q P by a
+// fused multiply-add), as the plain path's IEEE division gives it; fract(q) is
+// exact, and the phase offset is added to the fraction, not to q, so that no
+// rounding at the magnitude of q (~1e-9 rad at 2.5e6 orbits) enters M.
+__device__ __forceinline__ double mean_anomaly64_exact(double tt, const Phase64 &p)
+{
+    const double q0 = tt * p.rP;
+    const double q = fma(fma(-q0, p.P, tt), p.rP, q0);
+    const double ph = __builtin_amdgcn_fract(__builtin_amdgcn_fract(q) + p.m0h);
+    return fma(ph, kTwoPi, -kPi);
+}
+
+// From the binary32 root E of M32 = (float)M64: the binary64 residual
+// f = E - e sin E - M64, the corrected step d = d1 / (1 + d1 e sin E / (2 D))
+// with d1 = -f / D, D = 1 - e cos E (Danby's second correction; the result is
+// within about d^3 e / (6 D) of the root), sin and cos rotated to E + d to
+// second order, and the velocity v = (A cos E + B sin E) / (1 - e cos E) in
+// binary64 (the reciprocal refined by one Newton step from the binary32 one).
+// Also returns sin E and cos E - e rounded to binary32 for the derivative terms.
+__device__ __forceinline__ double refine_velocity(const RecGrad &r, float E, double M64, float &sE, float &cme)
+{
+    double s, c;
+    sincos_root64(E, s, c);
+    const double f = fma(-r.e, s, (double)E - M64);
+    const float rD = rcp32((float)fma(-r.e, c, 1.0));
+    const float d1 = -(float)f * rD;
+    const float d = fmaf(-d1, 0.5f * d1 * r.k.e * (float)s * rD, d1);
+    const double dd = (double)d, ph = (double)(0.5f * d * d);
+    const double s1 = fma(c, dd, fma(-s, ph, s));        // sin(E + d)
+    const double c1 = fma(-s, dd, fma(-c, ph, c));       // cos(E + d)
+    const double D = fma(-r.e, c1, 1.0);
+    const double r0 = (double)rcp32((float)D);
+    const double rD64 = fma(r0, fma(-D, r0, 1.0), r0);
+    sE = (float)s1;
+    cme = (float)(c1 - r.e);
+    return fma(r.A, c1, r.B * s1) * rD64;
+}
+
+// The five per-observation terms of planet r's gradient rows from binary32
+// sin E and cos E - e; qf = (t - t0)/P.  With D = 1 - e cos E,
+// df/dM = b/D^2, df/de = sin E (2 - e cos E - e^2)/(b D^2):
+//   x[0] = sin(w+f) df/dM q           dv/dP  = (2 pi K/P) x[0]
+//   x[1] = cos(w+f) + e cos w         dv/dK  = x[1]
+//   x[2] = cos w - sin(w+f) df/de     dv/de  = K x[2]
+//   x[3] = sin(w+f) + e sin w         dv/dw  = -K x[3]
+//   x[4] = sin(w+f) df/dM             dv/dM0 = -K x[4]
+// x[1] and x[3] in the forms b (b cos w cos E - sin w sin E)/D and
+// b (b sin w cos E + cos w sin E)/D: summing cos(w+f) and e cos w (or the
+// sines) loses the factor 1 - e near apoapsis (f ~ pi), where they nearly
+// cancel, and at e ~ 0.99 that is two decimal digits of the binary32 terms.
+__device__ __forceinline__ void grad_terms_ce(const RecGrad &r, float sE, float cme, float qf, float (&x)[5])
+{
+    const float iD = rcp32(fmaf(-r.k.e, cme, r.b2));       // 1/(1 - e cos E) = 1/((1 - e^2) - e (cos E - e))
+    const float cE = cme + r.k.e;
+    const float cf = cme * iD;                               // cos f
+    const float sf = r.b * sE * iD;                          // sin f
+    const float swf = r.sw * cf + r.cw * sf;                 // sin(w + f)
     const float iD2 = iD * iD;
-    const float a = swf * (g.b * iD2);                      // sin(w+f) df/dM
-    x[0] = a * (float)(tt * g.ph.rP);
-    x[1] = cwf;
-    x[2] = swf * (sE * fmaf(g.k.e, omcE, g.c0) * iD2 * rcp32(g.b));
-    x[3] = swf;
+    const float a = swf * (r.b * iD2);                       // sin(w+f) df/dM
+    const float bi = r.b * iD;
+    x[0] = a * qf;
+    x[1] = bi * fmaf(r.bcw, cE, -r.sw * sE);
+    x[2] = fmaf(-swf, sE * fmaf(-r.k.e, cme, r.c0) * iD2 * r.rb, r.cw);
+    x[3] = bi * fmaf(r.bsw, cE, r.cw * sE);
     x[4] = a;
-    return fmaf(g.K, cwf, g.Kecw);
+}
+
+// Sum over the 64 lanes of R per-lane rows (R a power of two <= 64), leaving
+// each row's total in the lanes l with l / (64 / R) equal to the row: each
+// step halves the rows a lane holds, keeping one half and adding the
+// partner's copy of it (R - 1 exchanges in all, instead of R full butterflies).
+// (The per-lane choice between the two halves is made by an explicit
+// v_cndmask: written as a select of two array elements, the compiler turns it
+// into an indexed read of the whole array, a chain of compares and selects.)
+__device__ __forceinline__ float lane_select(uint64_t mask, float if_clear, float if_set)
+{
+    float r;
+    __asm__("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(mask));
+    return r;
+}
+
+template <int R>
+__device__ __forceinline__ float rows_reduce_scatter(float (&x)[R])
+{
+#pragma unroll
+    for (int h = R / 2, o = 32; h >= 1; h >>= 1, o >>= 1) {
+        const uint64_t up = __ballot((__lane_id() & o) != 0);     // lanes keeping the upper half
+#pragma unroll
+        for (int i = 0; i < h; ++i) {
+            const float keep = lane_select(up, x[i], x[i + h]);
+            const float send = lane_select(up, x[i + h], x[i]);
+            x[i] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    float v = x[0];
+#pragma unroll
+    for (int o = 32 / R; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 // binary64 plain path: velocity of one planet and its five partial derivatives

@@ -92,12 +92,14 @@ hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int6
                                int fixed_iter, int max_iter, LaunchShape shape, hipStream_t st);
 hipError_t launch_dense(DenseArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 hipError_t launch_dense_grad(DenseArgs a, Prec prec, bool nll, LaunchShape shape, hipStream_t st);
+// the mixed-precision adjoint (lanes over observations, binary64 correction of E and v)
+hipError_t launch_grad_mixed(DenseArgs a, bool nll, LaunchShape shape, hipStream_t st);
 hipError_t launch_planet_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
-bool ragged_shape_fits(int block, int sb);   // LDS of the persistent kernel within 64 KiB per block
+bool ragged_shape_fits(int block, int sb);   // LDS of the persistent kernel (slices + table) within 64 KiB
 hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 // Gauss-Newton products: chi2 into a.out, J^T W r [np][n_sys], packed J^T W J
 hipError_t launch_eccentric_anomalies(DenseArgs a, LaunchShape shape, hipStream_t st);
@@ -112,5 +114,7 @@ hipError_t launch_demc_advance(uint64_t *gen, uint64_t inc, hipStream_t st);
 // one fused half-step (propose, chi-square, accept) of half h
 hipError_t launch_demc_half(DemcArgs m, DenseArgs base, Prec prec, int h, LaunchShape shape, hipStream_t st);
 int device_cu_count();
+// blocks of `kern` per CU at this block size and dynamic LDS (cached per device)
+int cached_occupancy(const void *kern, int block, size_t lds);
 
 }  // namespace kep

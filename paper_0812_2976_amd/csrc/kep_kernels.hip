@@ -12,6 +12,9 @@
 // The chi-square is reduced across the wave in binary64 (Sec. 4.4's final sum).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "kep_device.h"
 #include "kep_internal.h"
 #include "kep_grad.h"
@@ -287,96 +290,10 @@ __global__ void k_fill_u32(unsigned int *p, unsigned int value, int64_t n)
 }
 
 // ------------------------------------------------------------------ gradient
-// chi-square and its gradient with one lane per system (the adjoint needs
-// 5 n_pl + 1 running sums per system; keeping them in the lane that owns the
-// system avoids a cross-lane reduction per sum).  Observations are uniform
-// across the wave and arrive through scalar loads.  The per-planet terms are
-// in kep_grad.h.  With four planets the compiler would use about 200 VGPRs
-// (two wavefronts per SIMD); it is held to three (c4: 1.05 -> 0.98 ms; the
-// values it moves to scratch are per-system constants).  Four wavefronts
-// would put the running sums in scratch and ran no faster.
-template <int NPL>
-constexpr int grad_waves_per_simd() { return NPL == 4 ? 3 : 1; }
-
-template <int NPL, bool NLL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(grad_waves_per_simd<NPL>())))
-k_grad_mixed(DenseArgs a)
-{
-    __shared__ uint32_t tab[kTabWords];    // Kepler starting values
-    load_start_table(tab);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const bool has_jit = a.jitter != nullptr;
-    for (int64_t sys = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; sys < a.n_sys; sys += stride) {
-        GradPlanet<float> pl[NPL];
-        bool ok = isfinite(a.t0);
-#pragma unroll
-        for (int j = 0; j < NPL; ++j) {
-            const int64_t p = (int64_t)j * a.n_sys + sys;
-            ok = grad_setup(a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], a.fixed_iter, pl[j]) && ok;
-        }
-        const double gam = a.offset ? a.offset[sys] : 0.0;
-        const double jit = a.jitter ? a.jitter[sys] : 0.0;
-        if (a.offset) ok = ok && isfinite(gam);
-        if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
-        const float jit2 = (float)(jit * jit);
-        Kahan32 chi;
-        chi.init();
-        double acc[NPL][5], sum_c2 = 0.0;   // binary64 running sums of 2 w r x
-        double sum_lv = 0.0, sum_w = 0.0, sum_wr2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < NPL; ++j) {
-#pragma unroll
-            for (int i = 0; i < 5; ++i) acc[j][i] = 0.0;
-        }
-        for (int64_t k = 0; k < a.n_obs; ++k) {
-            const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
-            ok = ok && isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0;
-            const double tt = t - a.t0;
-            float x[NPL][5];
-            Kahan32 msum;
-            msum.init();
-#pragma unroll
-            for (int j = 0; j < NPL; ++j) msum.add(grad_terms(pl[j], tt, a.max_iter, x[j], tab));
-            const float r = (float)(((double)msum.s - (double)msum.c + gam) - vo);
-            const float var = (float)(sg * sg) + jit2;
-            ok = ok && var > 0.0f;
-            const float w = rcp32(var);
-            const float wr = w * r;
-            chi.add(wr * r);
-            if (NLL) {
-                sum_lv += (double)logf(var);
-                sum_w += (double)w;
-                sum_wr2 = fma((double)wr, (double)wr, sum_wr2);
-            }
-            const double c2 = 2.0 * (double)wr;
-            sum_c2 += c2;
-#pragma unroll
-            for (int j = 0; j < NPL; ++j) {
-#pragma unroll
-                for (int i = 0; i < 5; ++i) acc[j][i] = fma(c2, (double)x[j][i], acc[j][i]);
-            }
-        }
-        const double nan = __builtin_nan("");
-        a.out[sys] = ok ? chi.value() + sum_lv : nan;
-        if (NLL) a.grad[(int64_t)(5 * NPL + 1) * a.n_sys + sys] = ok ? 2.0 * jit * (sum_w - sum_wr2) : nan;
-#pragma unroll
-        for (int j = 0; j < NPL; ++j) {
-            const int64_t p = (int64_t)j * a.n_sys + sys;
-            const double K = a.K[p], e = a.e[p], P = a.P[p];
-            const double cw = pl[j].cw, sw = pl[j].sw;
-            double gj[5];
-            gj[0] = kTwoPi * K / P * acc[j][0];
-            gj[1] = acc[j][1] + e * cw * sum_c2;
-            gj[2] = K * cw * sum_c2 - K * acc[j][2];
-            gj[3] = -K * acc[j][3] - K * e * sw * sum_c2;
-            gj[4] = -K * acc[j][4];
-#pragma unroll
-            for (int i = 0; i < 5; ++i) a.grad[(int64_t)(5 * j + i) * a.n_sys + sys] = ok ? gj[i] : nan;
-        }
-        a.grad[(int64_t)(5 * NPL) * a.n_sys + sys] = ok ? sum_c2 : nan;
-    }
-}
-
+// Plain binary64 chi-square and gradient with one lane per system (the
+// adjoint needs 5 n_pl + 1 running sums per system; the lane that owns the
+// system keeps them).  Observations are uniform across the wave and arrive
+// through scalar loads.  The mixed-precision adjoint is in kep_adjoint.hip.
 template <int NPL, bool NLL>
 __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 {
@@ -707,6 +624,27 @@ int device_cu_count()
     return g_cu_count;
 }
 
+// Occupancy per (device, kernel, block size, LDS bytes), looked up once: the
+// runtime query costs microseconds, as much as a small launch.
+int cached_occupancy(const void *kern, int block, size_t lds)
+{
+    struct Entry { int dev; const void *kern; int block; size_t lds; int occ; };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (const Entry &e : cache)
+            if (e.dev == dev && e.kern == kern && e.block == block && e.lds == lds) return e.occ;
+    }
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess || occ <= 0) occ = 1;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cache.size() < 4096) cache.push_back(Entry{dev, kern, block, lds, occ});
+    return occ;
+}
+
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
@@ -762,9 +700,7 @@ static hipError_t launch_dense_t(DenseArgs a, LaunchShape shape, hipStream_t st)
     else { kern = k_dense<Pol, 8, MODE>; nch = 8; }
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess || occ <= 0) occ = 1;
-        per_cu = occ;
+        per_cu = cached_occupancy((const void *)kern, block, lds);
     }
     const int64_t max_waves = (int64_t)device_cu_count() * per_cu * wpb;
     // ceil: every wave gets at most one batch when the cap allows it, so no wave
@@ -841,11 +777,10 @@ static int grad_grid(int64_t n_sys, int block, int per_cu)
 hipError_t launch_dense_grad(DenseArgs a, Prec prec, bool nll, LaunchShape shape, hipStream_t st)
 {
     if (a.n_sys <= 0) return hipSuccess;
+    if (prec == Prec::Mixed) return launch_grad_mixed(a, nll, shape, st);
     const int block = shape.block > 0 ? shape.block : 256;
     const int grid = grad_grid(a.n_sys, block, shape.blocks_per_cu);
-#define KEP_GRAD_LAUNCH(N, L)                                                                   \
-    if (prec == Prec::Mixed) hipLaunchKernelGGL((k_grad_mixed<N, L>), dim3(grid), dim3(block), 0, st, a); \
-    else hipLaunchKernelGGL((k_grad_f64<N, L>), dim3(grid), dim3(block), 0, st, a);
+#define KEP_GRAD_LAUNCH(N, L) hipLaunchKernelGGL((k_grad_f64<N, L>), dim3(grid), dim3(block), 0, st, a);
 #define KEP_GRAD_CASE(N)                                                                     \
     case N:                                                                                  \
         if (nll) { KEP_GRAD_LAUNCH(N, true) } else { KEP_GRAD_LAUNCH(N, false) }              \
@@ -871,19 +806,17 @@ static size_t ragged_lds(int block, int sb)
     return (size_t)(block / 64) * ragged_lds_per_wave(sb);
 }
 
-bool ragged_shape_fits(int block, int sb) { return ragged_lds(block, sb) <= 64 * 1024; }
+// The block's LDS is the waves' dynamic slices plus the static copy of the
+// Kepler starting-value table.
+bool ragged_shape_fits(int block, int sb) { return ragged_lds(block, sb) + sizeof(kep_start_tab) <= 64 * 1024; }
 
 int ragged_max_grid(LaunchShape shape, int sb, int gmax)
 {
     const int block = shape.block > 0 ? shape.block : 256;
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) {
-        int occ = 0;
         void (*kern)(RaggedArgs) = gmax == 2 ? k_ragged_mixed<2> : k_ragged_mixed<4>;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, ragged_lds(block, sb)) != hipSuccess ||
-            occ <= 0)
-            occ = 1;
-        per_cu = occ;
+        per_cu = cached_occupancy((const void *)kern, block, ragged_lds(block, sb));
     }
     return device_cu_count() * per_cu;
 }

@@ -162,30 +162,25 @@ struct PolMixed {
         o.w = 1.0f;
     }
 
-    // tab: the starting-value table in LDS (the words of kep_start_tab), or null
-    template <int NCH>
-    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
-                                                      int max_iter, int /*fixed: already in rr.niter*/,
-                                                      const uint32_t *tab = nullptr)
+    // Kepler solve of NCH chunks of one planet (wave-uniform constants): E, and
+    // sin E, 1 - cos E at E.  From the starting-value table (one accurate Danby
+    // step) where the planet has a table row, else the paper's guess and the
+    // eccentricity schedule (or a caller-fixed count, or the convergence-tested
+    // loop).  tab: the starting-value table in LDS (the words of kep_start_tab), or null.
+    // ROTATE = false: E only (s and omc are left unset).
+    template <int NCH, bool ROTATE = true>
+    static __device__ __forceinline__ void solve(const Ecc32 &k, int niter, bool check, int trow, float twe,
+                                                 const float (&M)[NCH], float (&E)[NCH], float (&s)[NCH],
+                                                 float (&omc)[NCH], int max_iter, const uint32_t *tab)
     {
-        // rr comes from an LDS broadcast: every lane holds the same values
-        const Phase64 ph = rr.ph;
-        const Ecc32 k = rr.k;
-        const float A = rr.A, B = rr.B;
-        const int niter = uniform_int(rr.niter);
-        const int trow = uniform_int(rr.trow);
-        float M[NCH], E[NCH], st[NCH];
+        float st[NCH];
         SinCos32 sc[NCH];
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) M[c] = mean_anomaly32(o[c].tt, ph);
-        bool check = uniform_int(rr.check) != 0;
         if (tab != nullptr && trow >= 0) {
             // tabulated starting value (the paper's interpolated initial guess, Sec. 5.4):
             // bilinear in (e, |M|) within 3.7e-3 rad of the root, close enough for the
             // accurate last step alone (4.5e-11 rad in float64; scan in gen_tables.py)
             // (every chunk's reads are issued before any is used)
             const uint32_t *row = tab + trow * KEP_TAB_NM;
-            const float twe = rr.twe;
             float wm[NCH];
             uint32_t q0[NCH], q1[NCH];
 #pragma unroll
@@ -227,6 +222,7 @@ struct PolMixed {
                 if (__all(conv)) break;
             }
         }
+        if constexpr (!ROTATE) return;
         if (check) {   // a last step the schedule does not bound: evaluate afresh where it is large
             bool large = false;
 #pragma unroll
@@ -241,10 +237,31 @@ struct PolMixed {
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            float s = sc[c].s, omc = sc[c].omc;
-            rotate32(s, omc, st[c]);
-            float D = fmaf(k.e, omc, k.ome);           // 1 - e cos E
-            float num = fmaf(B, s, fmaf(-A, omc, A));  // A cos E + B sin E
+            s[c] = sc[c].s;
+            omc[c] = sc[c].omc;
+            rotate32(s[c], omc[c], st[c]);
+        }
+    }
+
+    // tab: the starting-value table in LDS (the words of kep_start_tab), or null
+    template <int NCH>
+    static __device__ __forceinline__ void add_planet(const Rec &rr, const Obs (&o)[NCH], ModelAcc (&m)[NCH],
+                                                      int max_iter, int /*fixed: already in rr.niter*/,
+                                                      const uint32_t *tab = nullptr)
+    {
+        // rr comes from an LDS broadcast: every lane holds the same values
+        const Phase64 ph = rr.ph;
+        const Ecc32 k = rr.k;
+        const float A = rr.A, B = rr.B;
+        float M[NCH], E[NCH], s[NCH], omc[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) M[c] = mean_anomaly32(o[c].tt, ph);
+        solve<NCH>(k, uniform_int(rr.niter), uniform_int(rr.check) != 0, uniform_int(rr.trow), rr.twe, M, E, s, omc,
+                   max_iter, tab);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            float D = fmaf(k.e, omc[c], k.ome);              // 1 - e cos E
+            float num = fmaf(B, s[c], fmaf(-A, omc[c], A));  // A cos E + B sin E
             m[c].k.add(num * rcp32(D));
         }
     }

@@ -116,19 +116,36 @@ def test_grad_chisq_equals_rv_chisq(dev):
     assert W.rel_err_chi2(c1.cpu().numpy(), c2.cpu().numpy()).max() <= 2e-5
 
 
-def test_autograd_function(dev):
-    """RVChiSq.backward returns grad_out * d chi2 / d theta."""
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autograd_function(dev, prec):
+    """RVChiSq.backward returns grad_out * d chi2 / d theta (the same launch's gradient,
+    so equal to rv_chisq_grad's bit for bit in either precision)."""
     wl = W.dense("c4", n_sys=50, n_pl=2, n_obs=40)
     g = W.to_gpu(wl, dev)
     leaves = [g[k].clone().requires_grad_(True) for k in ("P", "K", "e", "omega", "M0", "offset")]
-    chi2 = kp.RVChiSq.apply(*leaves, g["t"], g["v"], g["sigma"], None, 0.0, "fp64")
+    chi2 = kp.RVChiSq.apply(*leaves, g["t"], g["v"], g["sigma"], None, 0.0, prec)
     wts = torch.linspace(0.5, 2.0, wl.n_sys, dtype=torch.float64, device=dev)
     (chi2 * wts).sum().backward()
-    _, grad = kp.rv_chisq_grad(**g, prec="fp64")
+    _, grad = kp.rv_chisq_grad(**g, prec=prec)
     for j in range(2):
         for a in range(5):
-            assert torch.allclose(leaves[a].grad[j], grad[5 * j + a] * wts, rtol=1e-14, atol=0)
-    assert torch.allclose(leaves[5].grad, grad[-1] * wts, rtol=1e-14, atol=0)
+            assert torch.equal(leaves[a].grad[j], grad[5 * j + a] * wts)
+    assert torch.equal(leaves[5].grad, grad[-1] * wts)
+
+
+def test_autograd_function_without_offset_and_frozen_inputs(dev):
+    """offset=None and inputs that need no gradient get None from backward (no error)."""
+    wl = W.dense("c4", n_sys=30, n_pl=2, n_obs=40)
+    g = W.to_gpu(wl, dev)
+    P = g["P"].clone().requires_grad_(True)
+    K = g["K"].clone().requires_grad_(True)
+    chi2 = kp.RVChiSq.apply(P, K, g["e"], g["omega"], g["M0"], None, g["t"], g["v"], g["sigma"], None, 0.0,
+                            "mixed")
+    chi2.sum().backward()
+    _, grad = kp.rv_chisq_grad(g["t"], g["v"], g["sigma"], g["P"], g["K"], g["e"], g["omega"], g["M0"],
+                               prec="mixed")
+    assert torch.equal(P.grad, grad[0:10:5])
+    assert torch.equal(K.grad, grad[1:10:5])
 
 
 def test_grad_domain_nan(dev):
