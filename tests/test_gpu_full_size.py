@@ -1,8 +1,8 @@
 """Parity at the full sizes the benchmark times, in its launch configuration, on
 systems sampled across each batch (the oracle computes them one by one):
-c4 (262,144 x 4 x 256) gradient, likelihood and Gauss-Newton products, and the
-astrometric batch (1,048,576 x 2 x 128 epochs).  Tolerances as in the per-path
-tests."""
+c4 (262,144 x 4 x 256) gradient (|dg| <= 1e-6 max(|g|, S_r)), likelihood and
+Gauss-Newton products, and the astrometric batch (1,048,576 x 2 x 128 epochs).
+Tolerances as in the per-path tests."""
 import numpy as np
 import pytest
 
@@ -30,7 +30,7 @@ def test_c4_full_size_sampled(dev):
         i = int(i)
         c_ref, g_ref, s_r, s_1 = (x[..., i] for x in oracle.chisq_grad_scales(d, i, i + 1))
         worst["chi2"] = max(worst["chi2"], W.rel_err_chi2(chi2[i], c_ref))
-        worst["grad"] = max(worst["grad"], np.max(np.abs(grad[:, i] - g_ref) / (1e-3 * s_1 + 1e-5 * s_r)))
+        worst["grad"] = max(worst["grad"], np.max(np.abs(grad[:, i] - g_ref) / np.maximum(np.abs(g_ref), s_r)))
         n_ref, _ = (x[..., i] for x in oracle.nll_grad(d, i, i + 1))
         logs = np.sum(np.abs(np.log(wl.sigma ** 2 + wl.jitter[i] ** 2)))
         u = 2.0 ** -24
@@ -40,7 +40,7 @@ def test_c4_full_size_sampled(dev):
         scale = np.array([np.sqrt(diag[a] * diag[b]) for a in range(npar) for b in range(a, npar)])
         worst["jtwj"] = max(worst["jtwj"], np.max(np.abs(jtwj[:, i] - j_ref) / scale))
     print(f"[c4 full size, sampled] {worst}", flush=True)
-    assert worst["chi2"] <= 1e-5 and worst["grad"] <= 1.0 and worst["nll"] <= 1.0 and worst["jtwj"] <= 1e-5
+    assert worst["chi2"] <= 1e-5 and worst["grad"] <= 1e-6 and worst["nll"] <= 1.0 and worst["jtwj"] <= 1e-5
     assert np.all(np.isfinite(chi2)) and np.all(np.isfinite(jtwj))
     assert np.max(np.abs(c_gn - chi2) / np.maximum(chi2, 1.0)) <= 2e-5
 

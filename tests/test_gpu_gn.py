@@ -54,20 +54,24 @@ def test_gn_matches_oracle(dev, prec, tol, case):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_gn_jtwr_is_half_the_gradient(dev, prec):
-    """J^T W r is half the chi-square gradient.  In mixed precision the gradient kernel
-    starts its Kepler solve from the starting-value table and the Gauss-Newton kernel
-    from the paper's guess, so their binary32 E differ by rounding: the bound is each
-    path's own bound against the oracle (1e-5 of S_r)."""
+    """J^T W r is half the chi-square gradient.  Both mixed kernels correct the binary32
+    root and form the velocity in binary64, and the Gauss-Newton kernel sums the
+    binary32 products on the matrix cores: 2 J^T W r agrees with the gradient, and
+    with the oracle's gradient, to the stated gradient tolerance (1e-6 of
+    max(|g|, S_r))."""
     wl = W.dense("c4", n_sys=400, n_pl=2, n_obs=90)
     g = W.to_gpu(wl, dev)
     _, jtwr, _ = kp.rv_chisq_gn(**g, prec=prec)
     _, grad = kp.rv_chisq_grad(**g, prec=prec)
     jtwr, grad = jtwr.cpu().numpy(), grad.cpu().numpy()
-    _, _, s_r, _ = W.oracle_par(oracle.chisq_grad_scales, W.oracle_dense(wl), wl.n_sys)
-    tol = 1e-12 if prec == "fp64" else 1e-5
-    err = np.max(np.abs(2 * jtwr - grad) / (s_r + 1e-300))
-    print(f"[gn vs grad {prec}] max |2 J^T W r - g| / S_r = {err:.3e}", flush=True)
-    assert err <= tol
+    _, g_ref, s_r, _ = W.oracle_par(oracle.chisq_grad_scales, W.oracle_dense(wl), wl.n_sys)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    scale = np.maximum(np.abs(g_ref), s_r)
+    err = np.max(np.abs(2 * jtwr - grad) / scale)
+    err_ref = np.max(np.abs(2 * jtwr - g_ref) / scale)
+    print(f"[gn vs grad {prec}] max |2 J^T W r - g| / max(|g|, S_r) = {err:.3e}; vs the oracle {err_ref:.3e}",
+          flush=True)
+    assert err <= tol and err_ref <= max(tol, 1e-12)
 
 
 def test_gn_step_converges_on_noise_free_data(dev):

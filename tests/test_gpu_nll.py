@@ -7,8 +7,9 @@ Tolerances (u = 2^-24, n = n_obs, L = sum_k |ln(sigma_k^2 + s^2)|):
       2 s (sum w + sum w^2 r^2).
   mixed: nll within 1e-5 max(chi2, 1) + n 3u + 2u L (the chi-square bound plus a
       binary32 variance and logarithm per observation); planet and offset rows as
-      the mixed chi-square gradient; jitter row within
-      2 s (4u sum w + 2 dv sum w^2 |r| + 1e-5 sum w^2 r^2), dv = 1e-3 m/s.
+      the mixed chi-square gradient (|dg| <= 1e-6 max(|g|, S_r)); jitter row within
+      2 s (4u sum w + 1e-5 sum w^2 r^2) (binary32 weights; the residuals carry the
+      binary64 correction of the velocity).
 """
 import numpy as np
 import pytest
@@ -67,10 +68,9 @@ def test_nll_mixed_matches_oracle(dev, case):
     n = wl.t.size
     tol_nll = 1e-5 * np.maximum(ref["chi2"], 1.0) + n * 3 * U + 2 * U * ref["logs"]
     ratio = np.abs(nll - ref["nll"]) / tol_nll
-    tol = 1e-3 * ref["s_1"] + 1e-5 * ref["s_r"]
-    gratio = np.abs(grad[:-1] - ref["grad"][:-1]) / tol
+    gratio = np.abs(grad[:-1] - ref["grad"][:-1]) / (1e-6 * np.maximum(np.abs(ref["grad"][:-1]), ref["s_r"]))
     w, r = ref["w"], ref["r"]
-    tol_s = 2 * ref["jit"] * (4 * U * w.sum(1) + 2e-3 * np.sum(w * w * np.abs(r), 1) + 1e-5 * np.sum(w * w * r * r, 1))
+    tol_s = 2 * ref["jit"] * (4 * U * w.sum(1) + 1e-5 * np.sum(w * w * r * r, 1))
     sratio = np.abs(grad[-1] - ref["grad"][-1]) / np.maximum(tol_s, 1e-300)
     print(f"[nll mixed {case}] nll {ratio.max():.3e}  planet rows {gratio.max():.3e}  jitter row {sratio.max():.3e}",
           flush=True)
