@@ -286,6 +286,28 @@ kep_status rv_chisq_ragged(kep_plan *plan, double *chi2, void *stream);
 /* Same work launched directly, without the graph (for comparison). */
 kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the
+   chi-square of a ragged batch in one call, without a plan.  Allocates
+   nothing (no hipMalloc, hipFree or allocating library call) and does not
+   synchronise: two kernels on `stream`.  The first checks each system's
+   offsets on the device and writes the work order (systems by decreasing
+   planet count, index order within a count, so results are the same on every
+   call) into a static device work area of the library; the second is the
+   plan's persistent kernel at a fixed launch shape (256-thread blocks or
+   opts->block_threads, 16 systems per work item).
+   Arguments as kep_plan_ragged plus chi2[n_sys] (caller-owned device array).
+   Limit: n_sys <= 2,097,152 (the work area holds a 32-bit order entry per
+   system; 8 MiB + 256 bytes per GPU, held until the process ends); larger
+   batches return KEP_ERR_SHAPE.  Offsets are not read on the host: a system
+   whose offsets fall outside [0, n_obs_total] / [0, n_pl_total], decrease, or
+   give n_pl outside [1, KEP_MAX_PL] gets a NaN chi-square (other systems are
+   unaffected).  Every call on one GPU shares the work area: calls that
+   overlap in time on the same GPU (different streams, threads) race and
+   must not be made.  Only KEP_MIXED (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */
+kep_status rv_chisq_ragged_static(const kep_obs_csr *obs, const kep_params_csr *par, double *chi2, kep_prec prec,
+                                  const kep_options *opts, void *stream);
+
 typedef struct kep_plan_info {
     int64_t n_sys, n_obs_total, n_pl_total, triples;
     int32_t block_threads, blocks, sys_per_batch, tuned;

@@ -100,7 +100,7 @@ _LIB = None
 
 EXPORTS = ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_chisq_gn", "rv_planet_velocities",
            "rv_chisq_from_velocities", "rv_eccentric_anomalies", "kep_plan_ragged", "rv_chisq_ragged", "rv_chisq_ragged_direct",
-           "kep_plan_get_info", "kep_plan_destroy", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
+           "rv_chisq_ragged_static", "kep_plan_get_info", "kep_plan_destroy", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
            "kep_demc_plan_destroy", "astro_model", "astro_chisq", "kep_last_error", "kep_abi_version")
 
 
@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     L.kep_plan_ragged.argtypes = [P(KepObsCSR), P(KepParamsCSR), ctypes.c_int, P(KepOptions), _D, P(_D)]
     L.rv_chisq_ragged.argtypes = [_D, _D, _D]
     L.rv_chisq_ragged_direct.argtypes = [_D, _D, _D]
+    L.rv_chisq_ragged_static.argtypes = [P(KepObsCSR), P(KepParamsCSR), _D, ctypes.c_int, P(KepOptions), _D]
     L.kep_plan_get_info.argtypes = [_D, P(KepPlanInfo)]
     L.kep_plan_destroy.argtypes = [_D]
     L.kep_plan_destroy.restype = None
@@ -144,7 +145,7 @@ def load_library(path: str = LIB_PATH):
     L.kep_abi_version.restype = ctypes.c_int
     for name in ("kepler_solve", "rv_model", "rv_chisq", "rv_chisq_grad", "rv_nll_grad", "rv_chisq_gn",
                  "rv_planet_velocities", "rv_chisq_from_velocities", "rv_eccentric_anomalies", "kep_plan_ragged",
-                 "rv_chisq_ragged", "rv_chisq_ragged_direct",
+                 "rv_chisq_ragged", "rv_chisq_ragged_direct", "rv_chisq_ragged_static",
                  "kep_plan_get_info", "demc_chisq", "demc_generations", "kep_plan_demc", "demc_run",
                  "astro_model", "astro_chisq"):
         getattr(L, name).restype = ctypes.c_int
@@ -456,6 +457,31 @@ class RaggedPlan:
             self.close()
         except Exception:
             pass
+
+
+def rv_chisq_ragged_static(t, v, sigma, obs_off, P, K, e, omega, M0, pl_off, offset=None, jitter=None, t0=0.0,
+                           prec="mixed", out=None, opts=None):
+    """chi-square of a CSR batch in one call without a plan and without any
+    device allocation by the library (the offsets are checked and the systems
+    ordered on the device, in the library's static work area); n_sys <= 2^21.
+    Calls that overlap in time on one GPU must not be made."""
+    t, v, sigma = (_dev(x, n, 1) for x, n in ((t, "t"), (v, "v"), (sigma, "sigma")))
+    obs_off = _dev(obs_off, "obs_off", 1, torch.int64)
+    pl_off = _dev(pl_off, "pl_off", 1, torch.int64)
+    P, K, e, omega, M0 = (_dev(x, n, 1) for x, n in ((P, "P"), (K, "K"), (e, "e"), (omega, "omega"), (M0, "M0")))
+    n_sys = obs_off.numel() - 1
+    if pl_off.numel() != n_sys + 1:
+        raise ValueError("obs_off and pl_off must have the same length")
+    offset = _opt_dev(offset, "offset", n_sys)
+    jitter = _opt_dev(jitter, "jitter", n_sys)
+    dev = t.device
+    out = _out(out, "out", (n_sys,), dev)
+    obs = KepObsCSR(t.data_ptr(), v.data_ptr(), sigma.data_ptr(), obs_off.data_ptr(), t.numel(), float(t0))
+    par = KepParamsCSR(P.data_ptr(), K.data_ptr(), e.data_ptr(), omega.data_ptr(), M0.data_ptr(), pl_off.data_ptr(),
+                       _ptr(offset), _ptr(jitter), n_sys, P.numel())
+    _check(load_library().rv_chisq_ragged_static(ctypes.byref(obs), ctypes.byref(par), out.data_ptr(), _prec(prec),
+                                                 _opts(opts), _stream(dev)))
+    return out
 
 
 class DEMC:

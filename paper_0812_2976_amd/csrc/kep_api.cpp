@@ -606,6 +606,8 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     a.jitter = par->jitter;
     a.order = p->d_order;
     a.n_sys = n_sys;
+    a.n_obs_total = obs->n_obs_total;
+    a.n_pl_total = par->n_pl_total;
     a.queue = p->d_queue;
     a.out = nullptr;
     a.fixed_iter = o.fixed_iter;
@@ -720,6 +722,59 @@ kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream)
     hipError_t err = kep::launch_fill_u32(plan->d_queue, 0u, 1, st);
     if (err == hipSuccess) err = kep::launch_ragged(a, plan->shape, plan->grid, st);
     return launch_status(err, fn);
+}
+
+kep_status rv_chisq_ragged_static(const kep_obs_csr *obs, const kep_params_csr *par, double *chi2, kep_prec prec,
+                                  const kep_options *opts, void *stream)
+{
+    static const char *fn = "rv_chisq_ragged_static";
+    if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
+    if (kep_status s = check_prec(prec, fn)) return s;
+    if (prec != KEP_MIXED) return fail(KEP_ERR_UNSUPPORTED, "%s: only KEP_MIXED is implemented for ragged batches", fn);
+    Opts o;
+    if (kep_status s = parse_opts(opts, fn, o)) return s;
+    const int64_t n_sys = par->n_sys;
+    if (n_sys < 0) return fail(KEP_ERR_ARG, "%s: n_sys = %lld < 0", fn, (long long)n_sys);
+    if (n_sys > kep::kStaticMaxSys)
+        return fail(KEP_ERR_SHAPE, "%s: n_sys = %lld exceeds the %lld systems of the static work area (use a plan)",
+                    fn, (long long)n_sys, (long long)kep::kStaticMaxSys);
+    if (obs->n_obs_total < 0 || par->n_pl_total < 0) return fail(KEP_ERR_ARG, "%s: negative totals", fn);
+    if (n_sys == 0) return KEP_OK;
+    if (!chi2) return fail(KEP_ERR_ARG, "%s: chi2 is NULL", fn);
+    if (!obs->obs_off || !par->pl_off) return fail(KEP_ERR_ARG, "%s: obs_off and pl_off must not be NULL", fn);
+    if (obs->n_obs_total > 0 && (!obs->t || !obs->v || !obs->sigma))
+        return fail(KEP_ERR_ARG, "%s: t, v, sigma must not be NULL", fn);
+    if (par->n_pl_total > 0 && (!par->P || !par->K || !par->e || !par->omega || !par->M0))
+        return fail(KEP_ERR_ARG, "%s: a parameter array is NULL", fn);
+    if (kep_status s = check_device(fn)) return s;
+    kep::RaggedArgs a{};
+    a.t = obs->t;
+    a.v = obs->v;
+    a.sigma = obs->sigma;
+    a.obs_off = obs->obs_off;
+    a.t0 = obs->t0;
+    a.P = par->P;
+    a.K = par->K;
+    a.e = par->e;
+    a.w = par->omega;
+    a.M0 = par->M0;
+    a.pl_off = par->pl_off;
+    a.offset = par->offset;
+    a.jitter = par->jitter;
+    a.n_sys = n_sys;
+    a.n_obs_total = obs->n_obs_total;
+    a.n_pl_total = par->n_pl_total;
+    a.out = chi2;
+    a.fixed_iter = o.fixed_iter;
+    a.max_iter = o.max_iter;
+    // the launch shape the autotuner picks for the c3-like batches it has seen:
+    // 16 systems per work item, observation groups of up to four 64-lane chunks
+    a.sb = 16;
+    a.gmax = 4;
+    kep::LaunchShape shape = o.shape;
+    if (shape.block == 0) shape.block = 256;
+    if (!kep::ragged_shape_fits(shape.block, a.sb)) return fail(KEP_ERR_ARG, "%s: block_threads too large", fn);
+    return launch_status(kep::launch_ragged_static(a, shape, (hipStream_t)stream), fn);
 }
 
 kep_status kep_plan_get_info(const kep_plan *plan, kep_plan_info *info)

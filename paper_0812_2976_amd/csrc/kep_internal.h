@@ -40,6 +40,7 @@ struct RaggedArgs {
     unsigned int *queue;      // work-queue counter (reset before every launch)
     double *out;
     int fixed_iter, max_iter;
+    int64_t n_obs_total, n_pl_total;   // sizes of the CSR arrays (the allocation-free path checks against them)
 };
 
 // Astrometric batch (Thiele-Innes form): epochs t with measured offsets x
@@ -80,6 +81,11 @@ struct DemcArgs {
 constexpr int kMaxSB = 32;
 constexpr int kMaxPl = 8;
 
+// Allocation-free ragged path: a static device array holds the queue counter
+// (256 bytes) and the int32 work order of at most kStaticMaxSys systems.
+constexpr int64_t kStaticMaxSys = 1 << 21;
+constexpr size_t kStaticScratchBytes = 256 + sizeof(int32_t) * (size_t)kStaticMaxSys;
+
 enum class Prec { F64 = 0, Mixed = 1 };
 
 struct LaunchShape {
@@ -99,6 +105,10 @@ hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStrea
 hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
+// The allocation-free variant: checks and orders the systems on the device
+// (into the static scratch array), then runs the persistent kernel; a.order
+// and a.queue are set here.  a.sb and a.gmax must be set.  No allocation.
+hipError_t launch_ragged_static(RaggedArgs a, LaunchShape shape, hipStream_t st);
 bool ragged_shape_fits(int block, int sb);   // LDS of the persistent kernel (slices + table) within 64 KiB
 hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 // Gauss-Newton products: chi2 into a.out, J^T W r [np][n_sys], packed J^T W J

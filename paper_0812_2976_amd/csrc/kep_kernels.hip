@@ -453,14 +453,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         wave_sync_lds();
         int rem = 0;
         if (lane < nb) {
-            const int64_t sys = a.order[i0 + lane];
-            const int64_t p0 = a.pl_off[sys];
-            const int64_t o0 = a.obs_off[sys], n = a.obs_off[sys + 1] - o0;
-            meta[2 * lane] = (int)(a.pl_off[sys + 1] - p0);
-            meta[2 * lane + 1] = (int)sys;
-            pofs[lane] = p0;
-            rem = (int)(n & 63);
-            tail0[lane] = o0 + (n - rem);
+            const int32_t code = a.order[i0 + lane];
+            if (code >= 0) {
+                const int64_t sys = code;
+                const int64_t p0 = a.pl_off[sys];
+                const int64_t o0 = a.obs_off[sys], n = a.obs_off[sys + 1] - o0;
+                meta[2 * lane] = (int)(a.pl_off[sys + 1] - p0);
+                meta[2 * lane + 1] = (int)sys;
+                pofs[lane] = p0;
+                rem = (int)(n & 63);
+                tail0[lane] = o0 + (n - rem);
+            } else {
+                // a system whose offsets failed the on-device check (-1 - index):
+                // its offsets are not read again and its chi-square is NaN
+                meta[2 * lane] = 0;
+                meta[2 * lane + 1] = -1 - code;
+                pofs[lane] = 0;
+                tail0[lane] = 0;
+            }
             acc[lane] = 0.0;
             bad[lane] = 0;
         }
@@ -606,6 +616,133 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
             a.out[meta[2 * lane + 1]] = (code <= 0 || bad[lane] != 0) ? __builtin_nan("") : acc[lane];
         }
     }
+}
+
+// ------------------------------------------------------- ragged, no allocation
+// Device memory of the allocation-free ragged entry point: the work-queue
+// counter in the first 256 bytes, then the int32 work order of up to
+// kStaticMaxSys systems.  One copy per GPU, kept until the process ends; every
+// call on a GPU shares it (calls that overlap in time on one GPU race).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kPrepThreads = 1024;
+constexpr int kPrepKeys = kMaxPl + 1;      // planet counts 8 .. 1, then rejected systems
+
+// One block: zeroes the queue counter, checks every system's CSR offsets
+// (0 <= o0 <= o1 <= n_obs_total, 0 <= p0 < p1 <= n_pl_total, p1 - p0 <= kMaxPl)
+// and writes the work order: systems by decreasing planet count (so that the
+// systems of a work item share their planet count), index order within a
+// count (a stable counting sort: the order, and so every result, is the same
+// on every call), the rejected systems last as -1 - index.  Thread t owns the
+// contiguous run of systems [t c, (t + 1) c).
+__global__ void __launch_bounds__(kPrepThreads) k_ragged_static_order(const int64_t *__restrict__ obs_off,
+                                                                      const int64_t *__restrict__ pl_off,
+                                                                      int64_t n_sys, int64_t n_obs_total,
+                                                                      int64_t n_pl_total, int32_t *__restrict__ order,
+                                                                      unsigned int *__restrict__ queue)
+{
+    __shared__ int wtot[kPrepKeys][kPrepThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) *queue = 0u;
+    const int64_t c = (n_sys + kPrepThreads - 1) / kPrepThreads;
+    const int64_t i0 = min(n_sys, (int64_t)t * c), i1 = min(n_sys, i0 + c);
+    auto key_of = [&](int64_t i) {
+        const int64_t o0 = obs_off[i], o1 = obs_off[i + 1], p0 = pl_off[i], p1 = pl_off[i + 1];
+        const bool ok = o0 >= 0 && o0 <= o1 && o1 <= n_obs_total && p0 >= 0 && p0 < p1 && p1 <= n_pl_total &&
+                        p1 - p0 <= kMaxPl;
+        return ok ? kMaxPl - (int)(p1 - p0) : kMaxPl;      // 0 for 8 planets ... 7 for one, 8 rejected
+    };
+    int cnt[kPrepKeys];
+#pragma unroll
+    for (int k = 0; k < kPrepKeys; ++k) cnt[k] = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int k = key_of(i);
+#pragma unroll
+        for (int q = 0; q < kPrepKeys; ++q) cnt[q] += (q == k);
+    }
+    // exclusive prefix of every key's count over the threads (wave scans, then the waves)
+    int pre[kPrepKeys];
+#pragma unroll
+    for (int k = 0; k < kPrepKeys; ++k) {
+        int incl = cnt[k];
+        for (int d = 1; d < 64; d <<= 1) {
+            const int u = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += u;
+        }
+        pre[k] = incl - cnt[k];
+        if (lane == 63) wtot[k][w] = incl;
+    }
+    __syncthreads();
+    int64_t base = 0;
+#pragma unroll
+    for (int k = 0; k < kPrepKeys; ++k) {
+        int64_t tot = 0, before = 0;
+        for (int q = 0; q < kPrepThreads / 64; ++q) {
+            tot += wtot[k][q];
+            if (q < w) before += wtot[k][q];
+        }
+        cnt[k] = (int)(base + before + pre[k]);          // this thread's first slot for key k
+        base += tot;
+    }
+    for (int64_t i = i0; i < i1; ++i) {
+        const int k = key_of(i);
+        int slot = 0;
+#pragma unroll
+        for (int q = 0; q < kPrepKeys; ++q) {
+            if (q == k) {
+                slot = cnt[q];
+                cnt[q] += 1;
+            }
+        }
+        order[slot] = k < kMaxPl ? (int32_t)i : (int32_t)(-1 - i);
+    }
+}
+
+// The scratch array's device address on each GPU (host code must not use the
+// array's name: on the host it is a stand-in, not a device address).
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];
+
+hipError_t static_scratch(void **ptr)
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (err != hipSuccess) return err;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_ragged_static(RaggedArgs a, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_sys <= 0) return hipSuccess;
+    if (a.n_sys > kStaticMaxSys) return hipErrorInvalidValue;
+    void *base = nullptr;
+    hipError_t err = static_scratch(&base);
+    if (err != hipSuccess) return err;
+    unsigned int *queue = reinterpret_cast<unsigned int *>(base);
+    int32_t *order = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(base) + 256);
+    hipLaunchKernelGGL(k_ragged_static_order, dim3(1), dim3(kPrepThreads), 0, st, a.obs_off, a.pl_off, a.n_sys,
+                       a.n_obs_total, a.n_pl_total, order, queue);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    a.order = order;
+    a.queue = queue;
+    a.n_items = (a.n_sys + a.sb - 1) / a.sb;
+    const int block = shape.block > 0 ? shape.block : 256;
+    const int wpb = block / 64;
+    const int64_t need = (a.n_items + wpb - 1) / wpb;
+    const int64_t cap = ragged_max_grid(shape, a.sb, a.gmax);
+    const int grid = (int)(need < cap ? need : cap);
+    return launch_ragged(a, shape, grid, st);
 }
 
 // ------------------------------------------------------------------ launchers
