@@ -100,15 +100,21 @@ def early_steps(e_max, s2=0.8525, s3=0.975):
     return 2.0 * max(0.0, min(e_max, s3) - s2) / e_max
 
 
-def kernel_source_hash():
+# The sources each timed kernel is compiled from (its counter summaries under
+# profiles/ record their hash; a summary taken on other sources is not used).
+DENSE_FILES = ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_start_tab.h", "kep_grad.h")
+ADJOINT_FILES = ("kep_adjoint.hip", "kep_grad.h", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_start_tab.h")
+
+
+def kernel_source_hash(files=DENSE_FILES):
     h = hashlib.sha256()
-    for f in ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_start_tab.h", "kep_grad.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(name):
+def recorded_traffic(name, files=DENSE_FILES):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
     taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", f"{name}_traffic.md")
@@ -117,9 +123,74 @@ def recorded_traffic(name):
     txt = open(path).read()
     m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_h or not m_b or m_h.group(1) != kernel_source_hash():
+    if not m_h or not m_b or m_h.group(1) != kernel_source_hash(files):
         return None
     return float(m_b.group(1))
+
+
+# Algorithmic operations per (system, planet, observation) triple of the mixed
+# adjoint (kep_adjoint.hip), counted as for the chi-square above; binary64 ones
+# in the f64 class, hardware reciprocals in trans:
+#   pass 1: orbital phase with the correctly rounded quotient (product, exact
+#     remainder, correction, fraction, offset, fraction, scale) and the
+#     conversion 8 f64; starting value 10; last Danby step 33 (1 trans);
+#   binary64 correction: sin/cos of the binary32 root (reduction by n pi/2 4,
+#     square 1, degree-13 and degree-14 Taylor series 16; quadrant selects and
+#     signs 9 f32-class), residual of Kepler's equation 2, D 1 + its binary32
+#     reciprocal (1 trans), corrected step with the second-order term 5 f64
+#     + 6 f32, sin/cos carried to the corrected root 6 f64 + 2 f32, velocity
+#     8 f64 (1 trans), sin E and cos E - e for pass 2 3, planet sum 1:
+#     44 f64, 17 f32, 2 trans;
+#   pass 2: 1/D (1 trans), cos f, sin f, sin(w+f), df/dM and the five terms
+#     (two in their cancellation-free forms) 23, the quotient for dv/dP 2 f64,
+#     five weighted accumulations 5: 28 f32, 2 f64, 1 trans;
+#   per observation (/ n_pl): residual 2 f64, weight 2 f32 + 1 trans,
+#     chi-square 1 f64, 2 w r and the offset row 2 f32;
+#   per group of 64 NCH observations: the 5 n_pl + 1 lane sums reduced across
+#     the wavefront (R - 1 exchanges, two selects and an add each, R the next
+#     power of two), spread over the group's 64 NCH n_pl triples per lane.
+ADJ_F64, ADJ_F32, ADJ_TRANS = 8 + 44 + 2, 10 + 33 + 17 + 28, 1 + 2 + 1
+ADJ_OBS = {"f64": 3, "f32": 4, "trans": 1}
+
+
+def adjoint_op_classes(n_pl, nch):
+    r = 1
+    while r < 5 * n_pl + 1:
+        r *= 2
+    red = 3.0 * (r - 1) / (nch * n_pl)
+    return {"f32": ADJ_F32 + ADJ_OBS["f32"] / n_pl + red, "f64": ADJ_F64 + ADJ_OBS["f64"] / n_pl,
+            "trans": ADJ_TRANS + ADJ_OBS["trans"] / n_pl}
+
+
+def roofline_entry(kernel, classes, units, ms, traffic=None, unit_name="triple"):
+    """The VALU roofline of a kernel: classes are operations per unit by class,
+    units per launch, ms the mean launch time."""
+    per_unit = sum(classes.values())
+    achieved = per_unit * units / (ms * 1e-3) / 1e12
+    peak = mix_peak_ops_per_s(classes) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kernel,
+            f"ops_per_{unit_name}": round(per_unit, 2),
+            f"ops_per_{unit_name}_by_class": {c: round(n, 3) for c, n in classes.items()},
+            "units_per_launch": units, "launch_ms": round(ms, 4)}
+
+
+def cpu_threads():
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return max(1, min(cores, 16))
+
+
+def time_oracle(fn, n, cores):
+    """Wall seconds of fn(i0, i1) over [0, n) split across `cores` host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    bounds = np.linspace(0, n, cores * 4 + 1).astype(int)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda ab: fn(int(ab[0]), int(ab[1])), zip(bounds[:-1], bounds[1:])))
+    return time.perf_counter() - t0
 
 
 def timed(fn, steps, warmup, torch):
@@ -336,8 +407,13 @@ def main():
         useful = w4.n_sys * w4.t.size * (npar + 1) * (npar + 2)
         nb = (npar + 1 + 15) // 16
         issued = w4.n_sys * (w4.t.size // 4) * (nb * (nb + 1) // 2) * 2048
+        tri4 = w4.n_sys * w4.n_pl * w4.t.size
+        nch4 = 1 if w4.t.size <= 64 else (2 if (w4.n_pl > 4 or w4.t.size <= 128) else 4)
         result["gradient_c4"] = {"chi2_grad_per_s": w4.n_sys / (msg * 1e-3), "launch_ms": msg,
-                                 "triples_per_s": w4.n_sys * 1024 / (msg * 1e-3),
+                                 "triples_per_s": tri4 / (msg * 1e-3),
+                                 "roofline": roofline_entry(f"k_grad_obs<{w4.n_pl},{nch4}>",
+                                                            adjoint_op_classes(w4.n_pl, nch4), tri4, msg,
+                                                            recorded_traffic("rv_chisq_grad_mixed_c4", ADJOINT_FILES)),
                                  "nll_grad_launch_ms": msn,
                                  "gauss_newton": {"launch_ms_mixed": msgn, "launch_ms_fp64": msgn64,
                                                   "systems_per_s_mixed": w4.n_sys / (msgn * 1e-3),
@@ -346,6 +422,36 @@ def main():
                                                   "mfma_dtype_mixed": "f32 (binary64 sums per 64 observations)",
                                                   "mfma_f32_peak_tflops": 157.3,
                                                   "mfma_frac_mixed": issued / (msgn * 1e-3) / 157.3e12}}
+        if not args.no_cpu:
+            import oracle
+            # the oracle's sample has its own observed velocities (the oracle's model of
+            # the truth system + the same noise): no oracle input comes from the GPU path
+            cols = [np.asarray(w4.truth[k])[:, None] for k in ("P", "K", "e", "w", "M0")]
+            v4 = oracle.rv_model(oracle.Dense(w4.t, np.zeros_like(w4.t), w4.sigma, *cols, t0=w4.t0))[0] + w4.noise
+            n4 = min(args.cpu_sample // 4, w4.n_sys)
+            d4 = oracle.Dense(w4.t, v4, w4.sigma, *(np.ascontiguousarray(getattr(w4, a)[:, :n4])
+                                                    for a in ("P", "K", "e", "w", "M0")),
+                              w4.offset[:n4], None, w4.t0)
+            cores = cpu_threads()
+            oracle.lib()
+            res = {}
+            log(f"CPU oracle gradient on {n4} systems of c4 with {cores} threads")
+            dt = time_oracle(lambda i0, i1: res.__setitem__(i0, oracle.chisq_grad_scales(d4, i0, i1)), n4, cores)
+            result["gradient_c4"]["cpu_baseline"] = {
+                "value": n4 / dt, "unit": "chi2+gradient evals/s", "cores": cores, "kind": "oracle",
+                "sample": f"first {n4} systems of the same c4 batch ({n4 * 1024} triples), {dt:.2f} s wall"}
+            # accuracy of the mixed adjoint on the first 256 of them, the GPU given the
+            # oracle's observed velocities: |dg| / max(|g|, S_r) per component
+            m4 = min(256, n4)
+            part = {k: gpu(np.ascontiguousarray(getattr(w4, a)[:, :m4])) for k, a in
+                    (("P", "P"), ("K", "K"), ("e", "e"), ("omega", "w"), ("M0", "M0"))}
+            _, gg = kp.rv_chisq_grad(gpu(w4.t), gpu(v4), gpu(w4.sigma), **part, offset=gpu(w4.offset[:m4]),
+                                     t0=w4.t0, prec="mixed")
+            _, g_ref, s_r, _ = oracle.chisq_grad_scales(d4, 0, m4)
+            q13 = np.abs(gg.cpu().numpy() - g_ref[:, :m4]) / np.maximum(np.abs(g_ref[:, :m4]), s_r[:, :m4])
+            result["gradient_c4"]["accuracy_vs_oracle"] = {
+                "grad_q13_max": float(q13.max()), "grad_q13_median": float(np.median(q13)),
+                "sample": f"first {m4} systems of c4, |dg| / max(|g|, S_r), S_r = sum_k |2 w r dv/dtheta|"}
         del g4, o4, gr, gn, jit, jr, jj
 
     # ------------------------------------------------------------ ragged
@@ -357,11 +463,47 @@ def main():
         o3 = torch.empty(rw.n_sys, dtype=torch.float64, device=dev)
         msr, _ = timed(lambda: plan(o3), 10, 2, torch)
         info = plan.info()
+        # the formulation's operations summed over the batch: every triple as in the
+        # dense count, the per-observation work once per observation of each system
+        npl_i = np.diff(rw.pl_off)
+        nobs_i = np.diff(rw.obs_off)
+        core = {c: n - (F64_OBS if c == "f64" else (OPS_OBS - F64_OBS if c == "f32" else 0)) / 4
+                for c, n in mixed_op_classes(4, table_fraction(0.9), early_steps(0.9)).items()}
+        tri3 = int(np.sum(npl_i * nobs_i))
+        obs3 = int(np.sum(nobs_i))
+        cls3 = {c: core[c] + (F64_OBS if c == "f64" else (OPS_OBS - F64_OBS if c == "f32" else 0)) * obs3 / tri3
+                for c in core}
         result["ragged_c3"] = {"chi2_per_s": rw.n_sys / (msr * 1e-3), "launch_ms": msr,
                                "kepler_solves_per_s": info["triples"] / (msr * 1e-3), "triples": info["triples"],
+                               "roofline": roofline_entry(f"k_ragged_mixed<{info['group_chunks']}>", cls3, tri3, msr,
+                                                          recorded_traffic("rv_chisq_ragged_c3")),
+                               "hbm_GBps_algorithmic": (obs3 * 24 + int(rw.pl_off[-1]) * 40 + rw.n_sys * 24)
+                                                       / (msr * 1e-3) / 1e9,
                                "plan": {k: info[k] for k in ("block_threads", "blocks", "sys_per_batch", "group_chunks", "tuned")}}
         plan.close()
         del o3
+        if not args.no_cpu:
+            import oracle
+            n3 = min(args.cpu_sample, rw.n_sys)
+            o_end = int(rw.obs_off[n3])
+            p_end = int(rw.pl_off[n3])
+            # the sample's observed velocities from the oracle's model of the truth system
+            cols = [np.asarray(rw.truth[k])[:, None] for k in ("P", "K", "e", "w", "M0")]
+            t3 = rw.t[:o_end]
+            v3 = oracle.rv_model(oracle.Dense(t3, np.zeros_like(t3), np.ones_like(t3), *cols, t0=rw.t0))[0] \
+                + rw.noise[:o_end]
+            d3 = oracle.Ragged(t3, v3, rw.sigma[:o_end], rw.obs_off[:n3 + 1], rw.P[:p_end], rw.K[:p_end],
+                               rw.e[:p_end], rw.w[:p_end], rw.M0[:p_end], rw.pl_off[:n3 + 1], None, None, rw.t0)
+            out3 = np.full(n3, np.nan)
+            cores = cpu_threads()
+            oracle.lib()
+            log(f"CPU oracle ragged on {n3} systems of c3 with {cores} threads")
+            dt = time_oracle(lambda i0, i1: oracle.chisq_ragged(d3, i0, i1, out=out3), n3, cores)
+            tri_s = int(np.sum(npl_i[:n3] * nobs_i[:n3]))
+            result["ragged_c3"]["cpu_baseline"] = {
+                "value": n3 / dt, "unit": "chi2 evals/s", "cores": cores, "kind": "oracle",
+                "triples_per_s": tri_s / dt,
+                "sample": f"first {n3} systems of the same c3 batch ({tri_s} Kepler solves), {dt:.2f} s wall"}
 
     # ------------------------------------------------------------ DE-MC sampler
     if "demc" in rows:
