@@ -55,6 +55,18 @@ def test_recorded_traffic_requires_a_matching_source_hash(tmp_path, monkeypatch)
     (prof / "x_traffic.md").write_text(f"kernel_source_sha256: {h}\nhbm_bytes_per_launch: 1.5e+08\n")
     (prof / "y_traffic.md").write_text("kernel_source_sha256: 0000000000000000\nhbm_bytes_per_launch: 1.5e+08\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda files=bench.DENSE_FILES: h)
     assert bench.recorded_traffic("x") == 1.5e8
     assert bench.recorded_traffic("y") is None
+
+
+def test_adjoint_op_count_and_roofline_entry():
+    """The adjoint's count by class adds up, the cross-wavefront reduction shrinks with
+    more observation chunks, and a roofline entry reports achieved / peak."""
+    c4 = bench.adjoint_op_classes(4, 4)
+    c1 = bench.adjoint_op_classes(4, 1)
+    assert c1["f32"] > c4["f32"] and c1["f64"] == c4["f64"]
+    assert abs(c4["f64"] - (bench.ADJ_F64 + 3 / 4)) < 1e-12
+    e = bench.roofline_entry("k", c4, 1000, 1.0)
+    assert abs(e["achieved"] - sum(c4.values()) * 1000 / 1e-3 / 1e12) < 1e-3
+    assert abs(e["frac"] - e["achieved"] / e["peak"]) < 1e-3 and e["bound"] == "alu"
