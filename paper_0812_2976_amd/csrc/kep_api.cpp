@@ -355,6 +355,8 @@ struct kep_plan {
     int64_t *d_obs_off = nullptr;     // the checked CSR offsets (the plan's own copies)
     int64_t *d_pl_off = nullptr;
     unsigned int *d_queue = nullptr;
+    void *d_recs = nullptr;           // planet records in work order [n_sys][kMaxPl] (setup launch)
+    kep::RaggedSys *d_sys = nullptr;  // per-position system data (setup launch)
     double *bound_out = nullptr;      // output pointer recorded in the graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -428,12 +430,11 @@ save:
 
 kep_status plan_capture(kep_plan *p, hipStream_t user)
 {
-    (void)user;
     hipStream_t cap = nullptr;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
         return fail(KEP_ERR_DEVICE, "kep_plan_ragged: hipStreamCreate failed");
     hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (err == hipSuccess) err = kep::launch_fill_u32(p->d_queue, 0u, 1, cap);
+    if (err == hipSuccess) err = kep::launch_ragged_setup(p->args, cap);
     if (err == hipSuccess) err = kep::launch_ragged(p->args, p->shape, p->grid, cap);
     hipGraph_t g = nullptr;
     hipError_t err2 = hipStreamEndCapture(cap, &g);
@@ -446,6 +447,8 @@ kep_status plan_capture(kep_plan *p, hipStream_t user)
         (void)hipGraphDestroy(g);
         return fail(KEP_ERR_LAUNCH, "kep_plan_ragged: graph instantiation failed");
     }
+    // uploaded now: otherwise the first launches of the graph carry the upload
+    (void)hipGraphUpload(ex, user);
     // the kernel node that runs the persistent kernel (the last node of the chain)
     size_t n = 0;
     (void)hipGraphGetNodes(g, nullptr, &n);
@@ -473,14 +476,10 @@ double time_candidate(kep_plan *p, hipStream_t st, int reps)
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    // warm-up
-    (void)kep::launch_fill_u32(p->d_queue, 0u, 1, st);
+    // warm-up (the kernel leaves its queue counters at zero for the next launch)
     (void)kep::launch_ragged(p->args, p->shape, p->grid, st);
     (void)hipEventRecord(a, st);
-    for (int r = 0; r < reps; ++r) {
-        (void)kep::launch_fill_u32(p->d_queue, 0u, 1, st);
-        (void)kep::launch_ragged(p->args, p->shape, p->grid, st);
-    }
+    for (int r = 0; r < reps; ++r) (void)kep::launch_ragged(p->args, p->shape, p->grid, st);
     (void)hipEventRecord(b, st);
     (void)hipEventSynchronize(b);
     float ms = 0.0f;
@@ -500,6 +499,8 @@ void plan_free(kep_plan *p)
     if (p->d_obs_off) (void)hipFree(p->d_obs_off);
     if (p->d_pl_off) (void)hipFree(p->d_pl_off);
     if (p->d_queue) (void)hipFree(p->d_queue);
+    if (p->d_recs) (void)hipFree(p->d_recs);
+    if (p->d_sys) (void)hipFree(p->d_sys);
     delete p;
 }
 
@@ -586,11 +587,21 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot copy the CSR offsets", fn);
     }
-    if (hipMalloc(&p->d_queue, sizeof(unsigned int)) != hipSuccess) {
+    // the queue and exit counters start at zero; every launch leaves them at zero
+    if (hipMalloc(&p->d_queue, 2 * sizeof(unsigned int)) != hipSuccess ||
+        hipMemset(p->d_queue, 0, 2 * sizeof(unsigned int)) != hipSuccess) {
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work queue", fn);
     }
+    // the setup launch's outputs: records of every position's planet slots and its system data
+    if (n_sys > 0 && (hipMalloc(&p->d_recs, kep::ragged_record_bytes() * kep::kMaxPl * (size_t)n_sys) != hipSuccess ||
+                      hipMalloc(&p->d_sys, sizeof(kep::RaggedSys) * (size_t)n_sys) != hipSuccess)) {
+        plan_free(p);
+        return fail(KEP_ERR_DEVICE, "%s: cannot allocate the planet records", fn);
+    }
     kep::RaggedArgs &a = p->args;
+    a.recs_pre = p->d_recs;
+    a.sys_pre = p->d_sys;
     a.t = obs->t;
     a.v = obs->v;
     a.sigma = obs->sigma;
@@ -650,6 +661,12 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
                 return fail(KEP_ERR_DEVICE, "%s: cannot allocate tuning scratch", fn);
             }
             a.out = scratch;
+            // the records do not depend on the launch shape: built once for the tuning
+            if (kep::launch_ragged_setup(a, st) != hipSuccess) {
+                (void)hipFree(scratch);
+                plan_free(p);
+                return fail(KEP_ERR_LAUNCH, "%s: setup launch failed", fn);
+            }
             double best = 1e30;
             const int blocks[] = {64, 128, 256};
             const int sbs[] = {1, 2, 4, 8, 16, 32};
@@ -719,7 +736,7 @@ kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream)
     kep::RaggedArgs a = plan->args;
     a.out = chi2;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t err = kep::launch_fill_u32(plan->d_queue, 0u, 1, st);
+    hipError_t err = kep::launch_ragged_setup(a, st);
     if (err == hipSuccess) err = kep::launch_ragged(a, plan->shape, plan->grid, st);
     return launch_status(err, fn);
 }
@@ -976,6 +993,7 @@ kep_status kep_plan_demc(const kep_obs *obs, const kep_demc_state *st, const kep
             demc_plan_free(p);
             return fail(KEP_ERR_LAUNCH, "%s: graph instantiation failed", fn);
         }
+        (void)hipGraphUpload(exec, (hipStream_t)stream);   // else the first launches carry the upload
     }
     *out = p;
     return KEP_OK;

@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
         for (int j = 0; j < a.n_pl; ++j) {
             const float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) m[c].k.add(o[c].in ? row[c * 64 + lane] : 0.0f);
+            for (int c = 0; c < NCH; ++c) m[c].add(o[c].in ? row[c * 64 + lane] : 0.0f);
         }
         Kahan32 chi;
         chi.init();
@@ -281,12 +281,6 @@ __global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, c
             if (i < n) Ev[i] = E;
         }
     }
-}
-
-__global__ void k_fill_u32(unsigned int *p, unsigned int value, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = value;
 }
 
 // ------------------------------------------------------------------ gradient
@@ -362,24 +356,44 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 // one stream of lanes, each lane with its own system's planet records, and a
 // segmented scan over each group of 64 lanes returns every system's share: a
 // system's last partial group no longer leaves the rest of its wavefront idle.
-template <int NCH>
-__device__ __forceinline__ void ragged_group(const RaggedArgs &a, const RecMixed *recs, int npl, int64_t o0,
-                                             int64_t nrem, double gam, double jit, bool has_jit, Kahan32 &chi,
-                                             bool &bad_obs, const uint32_t *tab)
+// Observations of one unit of a system's whole groups (up to G groups of 64),
+// loaded raw so that the loads of the next unit can be issued before the
+// current one is evaluated.
+template <int G>
+struct RawObs {
+    double t[G], v[G], s[G];
+};
+
+template <int G>
+__device__ __forceinline__ void load_unit(const RaggedArgs &a, int64_t k0, int64_t left, RawObs<G> &r)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+        const int64_t k = c * 64 + lane;
+        const bool in = k < left;
+        r.t[c] = in ? a.t[k0 + k] : a.t0;
+        r.v[c] = in ? a.v[k0 + k] : 0.0;
+        r.s[c] = in ? a.sigma[k0 + k] : 1.0;
+    }
+}
+
+// One unit (the first NCH of its groups) of a system's whole groups, with the
+// lanes over its observations and uniform planet records.
+template <int NCH, int G>
+__device__ __forceinline__ void ragged_unit(const RaggedArgs &a, const RecMixed *recs, int npl, const RawObs<G> &r,
+                                            int64_t left, double gam, double jit, bool has_jit, Kahan32 &chi,
+                                            bool &bad_obs, const uint32_t *tab)
 {
     const int lane = __lane_id();
     ObsMixed o[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        const int64_t k = c * 64 + lane;
-        o[c].in = k < nrem;
-        double t = o[c].in ? a.t[o0 + k] : a.t0;
-        double v = o[c].in ? a.v[o0 + k] : 0.0;
-        double s = o[c].in ? a.sigma[o0 + k] : 1.0;
-        o[c].ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
-        o[c].tt = t - a.t0;
-        o[c].v = v;
-        o[c].s2 = (float)(s * s);
+        o[c].in = c * 64 + lane < left;
+        o[c].ok = isfinite(r.t[c]) && isfinite(r.v[c]) && isfinite(r.s[c]) && r.s[c] >= 0.0;
+        o[c].tt = r.t[c] - a.t0;
+        o[c].v = r.v[c];
+        o[c].s2 = (float)(r.s[c] * r.s[c]);
         o[c].w = rcp32(o[c].s2);
     }
     PolMixed::ModelAcc m[NCH];
@@ -409,15 +423,25 @@ __device__ __forceinline__ float ragged_vel_lane(const RecMixed &r, double tt, i
 
 // LDS of one wavefront for sb systems: planet records [sb][kMaxPl]; per
 // system the first planet offset, the global index of its first tail
-// observation and its chi-square so far; (code, system) pairs [sb][2], where
-// code is the planet count, negative for an invalid system; per-planet domain
-// flags [sb][kMaxPl]; prefix sums of the tail lengths [sb + 1]; bad-data flags [sb].
+// observation and its chi-square so far; its first observation and the
+// length of its whole groups [sb] each; its offset and jitter [sb][2];
+// (code, system) pairs [sb][2], where code is the planet count, negative for
+// an invalid system; per-planet domain flags [sb][kMaxPl]; prefix sums of the
+// tail lengths [sb + 1]; bad-data flags [sb].
 __host__ __device__ inline size_t ragged_lds_per_wave(int sb)
 {
     const size_t b = (size_t)sb * kMaxPl * sizeof(RecMixed) + (size_t)sb * 2 * sizeof(int64_t) +
-                     (size_t)sb * sizeof(double) + (size_t)sb * 2 * sizeof(int) + (size_t)sb * kMaxPl * sizeof(int) +
+                     (size_t)sb * sizeof(double) + (size_t)sb * 2 * sizeof(int64_t) + (size_t)sb * 2 * sizeof(double) +
+                     (size_t)sb * 2 * sizeof(int) + (size_t)sb * kMaxPl * sizeof(int) +
                      (size_t)(sb + 1) * sizeof(int) + (size_t)sb * sizeof(int);
     return (b + 15) & ~(size_t)15;
+}
+
+__device__ __forceinline__ int64_t uniform_i64(int64_t x)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return ((int64_t)hi << 32) | (uint32_t)lo;
 }
 
 // GMAX: largest observation group in 64-lane chunks (2 or 4): fewer chunks in
@@ -435,7 +459,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
     int64_t *pofs = reinterpret_cast<int64_t *>(recs + sb * kMaxPl);
     int64_t *tail0 = pofs + sb;
     double *acc = reinterpret_cast<double *>(tail0 + sb);
-    int *meta = reinterpret_cast<int *>(acc + sb);
+    int64_t *obs0 = reinterpret_cast<int64_t *>(acc + sb);
+    int64_t *nfl = obs0 + sb;
+    double *gj = reinterpret_cast<double *>(nfl + sb);
+    int *meta = reinterpret_cast<int *>(gj + 2 * sb);
     int *okpl = meta + 2 * sb;
     int *tpre = okpl + sb * kMaxPl;
     int *bad = tpre + sb + 1;
@@ -452,7 +479,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         const int nb = (int)min((int64_t)sb, a.n_sys - i0);
         wave_sync_lds();
         int rem = 0;
-        if (lane < nb) {
+        const bool pre = a.recs_pre != nullptr;
+        if (pre) {
+            // the plan's setup launch built the records and per-system data in work
+            // order: one contiguous block of this item's positions
+            if (lane < nb) {
+                const RaggedSys q = a.sys_pre[i0 + lane];
+                meta[2 * lane] = q.code;
+                meta[2 * lane + 1] = q.sys;
+                pofs[lane] = 0;
+                rem = (int)(q.nobs & 63);
+                tail0[lane] = q.o0 + (q.nobs - rem);
+                obs0[lane] = q.o0;
+                nfl[lane] = q.nobs - rem;
+                gj[2 * lane] = q.gam;
+                gj[2 * lane + 1] = q.jit;
+                acc[lane] = 0.0;
+                bad[lane] = 0;
+            }
+            const RecMixed *src = reinterpret_cast<const RecMixed *>(a.recs_pre) + i0 * kMaxPl;
+            for (int q = lane; q < nb * kMaxPl; q += 64) recs[q] = src[q];
+        } else if (lane < nb) {
             const int32_t code = a.order[i0 + lane];
             if (code >= 0) {
                 const int64_t sys = code;
@@ -463,6 +510,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 pofs[lane] = p0;
                 rem = (int)(n & 63);
                 tail0[lane] = o0 + (n - rem);
+                obs0[lane] = o0;
+                nfl[lane] = n - rem;
             } else {
                 // a system whose offsets failed the on-device check (-1 - index):
                 // its offsets are not read again and its chi-square is NaN
@@ -470,6 +519,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 meta[2 * lane + 1] = -1 - code;
                 pofs[lane] = 0;
                 tail0[lane] = 0;
+                obs0[lane] = 0;
+                nfl[lane] = 0;
             }
             acc[lane] = 0.0;
             bad[lane] = 0;
@@ -486,7 +537,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         wave_sync_lds();
         DenseArgs dummy;
         dummy.fixed_iter = a.fixed_iter;
-        for (int q = lane; q < nb * kMaxPl; q += 64) {
+        for (int q = lane; !pre && q < nb * kMaxPl; q += 64) {
             const int s = q / kMaxPl, j = q - s * kMaxPl;
             if (j < meta[2 * s]) {
                 const int64_t p = pofs[s] + j;
@@ -496,43 +547,67 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
             }
         }
         wave_sync_lds();
-        if (lane < nb) {
+        if (!pre && lane < nb) {
             const int npl = meta[2 * lane];
             const int64_t sys = meta[2 * lane + 1];
             bool ok = isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
             for (int j = 0; j < kMaxPl; ++j)
                 if (j < npl) ok = ok && okpl[lane * kMaxPl + j] != 0;
-            if (a.offset) ok = ok && isfinite(a.offset[sys]);
-            if (a.jitter) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
+            const double g = a.offset ? a.offset[sys] : 0.0;
+            const double sj = a.jitter ? a.jitter[sys] : 0.0;
+            if (a.offset) ok = ok && isfinite(g);
+            if (a.jitter) ok = ok && isfinite(sj) && sj >= 0.0;
+            gj[2 * lane] = g;
+            gj[2 * lane + 1] = sj;
             meta[2 * lane] = ok ? npl : -npl;
         }
         wave_sync_lds();
-        // whole groups of 64 observations, one system at a time
-        for (int s = 0; s < nb; ++s) {
-            const int code = uniform_int(meta[2 * s]);
-            if (code <= 0) continue;                   // invalid: NaN, nothing to evaluate
-            const int64_t sys = uniform_int(meta[2 * s + 1]);
-            const int64_t o0 = a.obs_off[sys];
-            const int64_t nfull = (a.obs_off[sys + 1] - o0) & ~(int64_t)63;
-            if (nfull == 0) continue;
-            const double gam = a.offset ? a.offset[sys] : 0.0;
-            const double jit = a.jitter ? a.jitter[sys] : 0.0;
-            const RecMixed *rs = recs + s * kMaxPl;
+        // whole groups of 64 observations, one system at a time, in units of up to
+        // GMAX groups; the next unit's observations (of this or the next system)
+        // are loaded before the current unit is evaluated, so that the wave does
+        // not wait for global memory at the start of every unit
+        {
+            auto has_units = [&](int q) { return uniform_int(meta[2 * q]) > 0 && uniform_i64(nfl[q]) > 0; };
+            int us = 0;
+            while (us < nb && !has_units(us)) ++us;
+            int64_t ug = 0;
+            RawObs<GMAX> cur, nxt;
+            if (us < nb) load_unit<GMAX>(a, uniform_i64(obs0[us]), uniform_i64(nfl[us]), cur);
             Kahan32 chi;
             chi.init();
             bool bad_obs = false;
-            for (int64_t g = 0; g < nfull; g += 64 * GMAX) {
-                const int64_t left = nfull - g;
-                if (left <= 64) ragged_group<1>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
-                else if (GMAX == 2 || left <= 128) ragged_group<2>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
-                else if (left <= 192) ragged_group<3>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
-                else ragged_group<GMAX>(a, rs, code, o0 + g, left, gam, jit, has_jit, chi, bad_obs, tab);
-            }
-            const double tot = wave_sum(chi.value());
-            const bool b = __any(bad_obs);
-            if (lane == 0) {
-                acc[s] = tot;
-                bad[s] = b ? 1 : 0;
+            while (us < nb) {
+                const int64_t nf = uniform_i64(nfl[us]);
+                int ns = us;
+                int64_t ng = ug + 64 * GMAX;
+                if (ng >= nf) {
+                    ns = us + 1;
+                    while (ns < nb && !has_units(ns)) ++ns;
+                    ng = 0;
+                }
+                if (ns < nb) load_unit<GMAX>(a, uniform_i64(obs0[ns]) + ng, uniform_i64(nfl[ns]) - ng, nxt);
+                const int64_t left = nf - ug;
+                const int code = uniform_int(meta[2 * us]);
+                const double gam = gj[2 * us], jit = gj[2 * us + 1];
+                const RecMixed *rs = recs + us * kMaxPl;
+                if (left <= 64) ragged_unit<1, GMAX>(a, rs, code, cur, left, gam, jit, has_jit, chi, bad_obs, tab);
+                else if (GMAX == 2 || left <= 128)
+                    ragged_unit<2, GMAX>(a, rs, code, cur, left, gam, jit, has_jit, chi, bad_obs, tab);
+                else if (left <= 192) ragged_unit<3, GMAX>(a, rs, code, cur, left, gam, jit, has_jit, chi, bad_obs, tab);
+                else ragged_unit<GMAX, GMAX>(a, rs, code, cur, left, gam, jit, has_jit, chi, bad_obs, tab);
+                if (ns != us) {
+                    const double tot = wave_sum(chi.value());
+                    const bool b = __any(bad_obs);
+                    if (lane == 0) {
+                        acc[us] = tot;
+                        bad[us] = b ? 1 : 0;
+                    }
+                    chi.init();
+                    bad_obs = false;
+                }
+                us = ns;
+                ug = ng;
+                cur = nxt;
             }
         }
         wave_sync_lds();
@@ -576,7 +651,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 const int npl = inc && code > 0 ? code : 0;
                 double x = 0.0;
                 if (npl > 0) {
-                    const int64_t sys = meta[2 * sc + 1];
                     ObsMixed o;
                     o.in = true;
                     o.ok = isfinite(tc) && isfinite(vc) && isfinite(sgc) && sgc >= 0.0;
@@ -587,9 +661,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                     PolMixed::ModelAcc m;
                     PolMixed::model_init(m);
                     const RecMixed *rs = recs + sc * kMaxPl;
-                    for (int j = 0; j < npl; ++j) m.k.add(ragged_vel_lane(rs[j], o.tt, a.max_iter, tab));
-                    const double gam = a.offset ? a.offset[sys] : 0.0;
-                    const double jit = a.jitter ? a.jitter[sys] : 0.0;
+                    for (int j = 0; j < npl; ++j) m.add(ragged_vel_lane(rs[j], o.tt, a.max_iter, tab));
+                    const double gam = gj[2 * sc], jit = gj[2 * sc + 1];
                     Kahan32 cx;
                     cx.init();
                     const bool okw = PolMixed::chi_add(cx, m, o, gam, jit, has_jit);
@@ -616,11 +689,85 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
             a.out[meta[2 * lane + 1]] = (code <= 0 || bad[lane] != 0) ? __builtin_nan("") : acc[lane];
         }
     }
+    // The last wave to leave resets both counters for the next launch, so no
+    // reset launch is needed between launches: every wave counts itself out
+    // after its last (failed) take from the queue, so when the count reaches
+    // the number of waves no wave of this launch touches the queue again.
+    if (lane == 0) {
+        const unsigned int n_waves = gridDim.x * (blockDim.x >> 6);
+        if (atomicAdd(a.queue + 1, 1u) == n_waves - 1) {
+            atomicExch(a.queue, 0u);
+            atomicExch(a.queue + 1, 0u);
+        }
+    }
 }
+
+// The plan's setup launch: one thread per (work-order position, planet slot);
+// the eight slots of a position are eight consecutive lanes, which combine
+// their domain flags.  Records of slots beyond the system's planet count are
+// not written (the persistent kernel never reads them).
+__global__ void __launch_bounds__(256) k_ragged_setup(RaggedArgs a)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = gid / kMaxPl;
+    const int j = (int)(gid % kMaxPl);
+    const bool live = i < a.n_sys;
+    int64_t sys = 0, p0 = 0, o0 = 0, o1 = 0;
+    int npl = 0;
+    if (live) {
+        sys = a.order[i];
+        p0 = a.pl_off[sys];
+        npl = (int)(a.pl_off[sys + 1] - p0);
+        o0 = a.obs_off[sys];
+        o1 = a.obs_off[sys + 1];
+    }
+    bool ok = true;
+    if (live && j < npl) {
+        DenseArgs dummy;
+        dummy.fixed_iter = a.fixed_iter;
+        RecMixed r;
+        ok = PolMixed::setup(dummy, a.P[p0 + j], a.K[p0 + j], a.e[p0 + j], a.w[p0 + j], a.M0[p0 + j], r);
+        reinterpret_cast<RecMixed *>(a.recs_pre)[i * kMaxPl + j] = r;
+    }
+    // every slot of the position joins in (kMaxPl = 8 consecutive lanes)
+    // (every lane takes part in every exchange: a shuffle read from a lane that
+    // skipped it returns no defined value)
+    bool all = ok;
+#pragma unroll
+    for (int d = 1; d < kMaxPl; d <<= 1) {
+        const int other = __shfl_xor(all ? 1 : 0, d, 64);
+        all = all && other != 0;
+    }
+    if (live && j == 0) {
+        const double g = a.offset ? a.offset[sys] : 0.0;
+        const double sj = a.jitter ? a.jitter[sys] : 0.0;
+        bool good = all && isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
+        if (a.offset) good = good && isfinite(g);
+        if (a.jitter) good = good && isfinite(sj) && sj >= 0.0;
+        RaggedSys q;
+        q.o0 = o0;
+        q.nobs = o1 - o0;
+        q.gam = g;
+        q.jit = sj;
+        q.sys = (int32_t)sys;
+        q.code = good ? npl : -npl;
+        a.sys_pre[i] = q;
+    }
+}
+
+hipError_t launch_ragged_setup(RaggedArgs a, hipStream_t st)
+{
+    if (a.n_sys <= 0 || !a.recs_pre || !a.sys_pre) return hipSuccess;
+    const int64_t threads = a.n_sys * kMaxPl;
+    hipLaunchKernelGGL(k_ragged_setup, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+size_t ragged_record_bytes() { return sizeof(RecMixed); }
 
 // ------------------------------------------------------- ragged, no allocation
 // Device memory of the allocation-free ragged entry point: the work-queue
-// counter in the first 256 bytes, then the int32 work order of up to
+// and exit counters in the first 256 bytes, then the int32 work order of up to
 // kStaticMaxSys systems.  One copy per GPU, kept until the process ends; every
 // call on a GPU shares it (calls that overlap in time on one GPU race).
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
@@ -628,7 +775,7 @@ static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 constexpr int kPrepThreads = 1024;
 constexpr int kPrepKeys = kMaxPl + 1;      // planet counts 8 .. 1, then rejected systems
 
-// One block: zeroes the queue counter, checks every system's CSR offsets
+// One block: zeroes the queue counters, checks every system's CSR offsets
 // (0 <= o0 <= o1 <= n_obs_total, 0 <= p0 < p1 <= n_pl_total, p1 - p0 <= kMaxPl)
 // and writes the work order: systems by decreasing planet count (so that the
 // systems of a work item share their planet count), index order within a
@@ -643,7 +790,10 @@ __global__ void __launch_bounds__(kPrepThreads) k_ragged_static_order(const int6
 {
     __shared__ int wtot[kPrepKeys][kPrepThreads / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    if (t == 0) *queue = 0u;
+    if (t == 0) {
+        queue[0] = 0u;
+        queue[1] = 0u;
+    }
     const int64_t c = (n_sys + kPrepThreads - 1) / kPrepThreads;
     const int64_t i0 = min(n_sys, (int64_t)t * c), i1 = min(n_sys, i0 + c);
     auto key_of = [&](int64_t i) {
@@ -780,14 +930,6 @@ int cached_occupancy(const void *kern, int block, size_t lds)
     std::lock_guard<std::mutex> lock(mu);
     if (cache.size() < 4096) cache.push_back(Entry{dev, kern, block, lds, occ});
     return occ;
-}
-
-hipError_t launch_fill_u32(unsigned int *p, unsigned int value, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, st, p, value, n);
-    return hipGetLastError();
 }
 
 hipError_t launch_kepler_solve(const double *M, const double *e, double *E, int64_t n, Prec prec, int fixed_iter,

@@ -109,7 +109,13 @@ struct PolMixed {
     static constexpr bool kMixed = true;
     using Rec = RecMixed;
     using Obs = ObsMixed;
-    struct ModelAcc { Kahan32 k; };
+    // the planet sum in binary64: each binary32 velocity is added exactly (two
+    // instructions a planet, where a Kahan pair takes four), so the sum carries
+    // only the rounding of the velocities themselves
+    struct ModelAcc {
+        double s;
+        __device__ __forceinline__ void add(float v) { s += (double)v; }
+    };
     using ChiAcc = Kahan32;
 
     static __device__ __forceinline__ bool setup(const DenseArgs &a, double P, double K, double e, double w,
@@ -262,19 +268,19 @@ struct PolMixed {
         for (int c = 0; c < NCH; ++c) {
             float D = fmaf(k.e, omc[c], k.ome);              // 1 - e cos E
             float num = fmaf(B, s[c], fmaf(-A, omc[c], A));  // A cos E + B sin E
-            m[c].k.add(num * rcp32(D));
+            m[c].add(num * rcp32(D));
         }
     }
 
-    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.k.init(); }
-    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.k.value(); }
+    static __device__ __forceinline__ void model_init(ModelAcc &m) { m.s = 0.0; }
+    static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.s; }
 
     static __device__ __forceinline__ void chi_init(ChiAcc &x) { x.init(); }
     // One observation's contribution; returns false if the weight is invalid.
     static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
                                                    double jit, bool has_jit)
     {
-        float r = (float)(((double)m.k.s - (double)m.k.c + gam) - o.v);   // residual formed in binary64
+        float r = (float)((m.s + gam) - o.v);   // residual formed in binary64
         float w = o.w;
         bool okw = true;
         if (has_jit) {
