@@ -31,7 +31,9 @@
    difference to the next eccentricity row) in kep_start_tab.h.  The scan checks that
    bilinear interpolation starts within a few 1e-3 rad of the root and that one Danby
    step from there lands within 1e-9 rad (float64), so the kernels that hold the table
-   take the last step only.
+   take the last step only.  A second scan finds the leading rows on which the
+   second-order step (Halley's correction) alone already lands within 1e-9 rad
+   (KEP_TAB_HALLEY_ROWS): there the kernels take that cheaper step instead.
 
 Run:  python gen_tables.py         (rewrites kep_tables.h and kep_start_tab.h)
       python gen_tables.py start   (kep_start_tab.h only)
@@ -208,10 +210,39 @@ def start_scan(pairs, emax, n_e=400):
     return far, err
 
 
+def _halley_step(E, e, M):
+    """Second-order member of Danby's family (Halley's correction), float64."""
+    s, c = np.sin(E), np.cos(E)
+    f = E - e * s - M
+    f1 = 1 - e * c
+    return E - f * f1 / (f1 * f1 - 0.5 * f * e * s)
+
+
+def halley_rows(pairs, emax, target=1e-9, n_e=60):
+    """Number of leading table rows (e_i <= e <= e_i+1, endpoints included) on which
+    one Halley step from the table start lands within `target` of the root (float64),
+    and the worst start distance and step error over those rows."""
+    M = np.concatenate([np.linspace(-np.pi, np.pi, 20001),
+                        np.outer([-1.0, 1.0], np.logspace(-10, 0, 2001)).ravel()])
+    rows, far, err = 0, 0.0, 0.0
+    for i in range(START_NE - 1):
+        row_far, row_err = 0.0, 0.0
+        for e in np.linspace(i * emax / (START_NE - 1), (i + 1) * emax / (START_NE - 1), n_e):
+            R = _root64(e, M)
+            E0 = start_lookup(pairs, emax, e, M)
+            row_far = max(row_far, float(np.max(np.abs(E0 - R))))
+            row_err = max(row_err, float(np.max(np.abs(_halley_step(E0, e, M) - R))))
+        if row_err > target:
+            break
+        rows, far, err = i + 1, max(far, row_far), max(err, row_err)
+    return rows, far, err
+
+
 def write_start_table(emax, out=START_OUT):
     pairs = start_table(emax)
     far, err = start_scan(pairs, emax)
     assert err <= 1e-9, err
+    h_rows, h_far, h_err = halley_rows(pairs, emax)
     lines = [
         "// Generated by gen_tables.py -- do not edit by hand.",
         "#pragma once",
@@ -226,6 +257,9 @@ def write_start_table(emax, out=START_OUT):
         f"#define KEP_TAB_NM {START_NM}",
         f"#define KEP_TAB_EMAX {emax!r}",
         f"#define KEP_TAB_MSCALE {float(np.float32(128 / np.pi))!r}f",
+        f"// On rows i < KEP_TAB_HALLEY_ROWS (e < {h_rows * emax / (START_NE - 1):.4f}) the start lies within {h_far:.2e} rad",
+        f"// of the root and one Halley step (second order) from it lands within {h_err:.1e} rad.",
+        f"#define KEP_TAB_HALLEY_ROWS {h_rows}",
         "",
         "static __device__ const unsigned int kep_start_tab[(KEP_TAB_NE - 1) * KEP_TAB_NM] = {",
     ]
@@ -237,7 +271,8 @@ def write_start_table(emax, out=START_OUT):
     lines.append("};")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
-    print(f"start table: far {far:.3e}, one step {err:.3e}")
+    print(f"start table: far {far:.3e}, one step {err:.3e}; Halley rows {h_rows} (far {h_far:.3e}, "
+          f"one step {h_err:.3e})")
 
 
 def main():

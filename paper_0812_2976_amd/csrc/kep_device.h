@@ -209,6 +209,37 @@ __device__ __forceinline__ float danby_step32(float &E, float M, const Ecc32 &k,
     return step;
 }
 
+// The second-order member of Danby's family (Halley's correction) on the same
+// cancellation-free f: d = -f / (f' + d1 f''/2) with d1 = -f/f', which is
+// -f f' / (f'^2 - f f''/2).  Its error is about (f''^2/(4 f'^2) - f'''/(6 f')) d0^3
+// for a start d0 from the root, so it replaces the quartic step only where the
+// start is close enough (the table rows of KEP_TAB_HALLEY_ROWS: within 1e-9 rad
+// after the step).  Six operations and one reciprocal where the quartic step
+// takes thirteen.  Returns the step (E becomes E + step) and leaves sin E,
+// 1 - cos E of the iterate it started from in `sc`.
+template <bool WIDE>
+__device__ __forceinline__ float halley_step32(float &E, float M, const Ecc32 &k, SinCos32 &sc)
+{
+    sc = WIDE ? sincos32_wide(E) : sincos32(E);
+    const float f = fmaf(k.ome, E, fmaf(k.e, sc.xms, -M));
+    const float f1 = fmaf(k.e, sc.omc, k.ome);
+    const float N = fmaf(f1, f1, -f * (k.eh * sc.s));
+    const float step = -(f * f1) * rcp32(N);
+    E += step;
+    return step;
+}
+
+// rotate32 for steps |d| <= 2e-3 (the Halley band of the table): sin d = d and
+// 1 - cos d = d^2/2, whose dropped terms d^3/6 and d^4/24 are below 1.4e-9.
+__device__ __forceinline__ void rotate32_small(float &s, float &omc, float d)
+{
+    const float omcd = (0.5f * d) * d;
+    const float s_new = fmaf(-s, omcd, fmaf(-omc, d, s + d));
+    const float omc_new = fmaf(s, d, fmaf(-omc, omcd, omc + omcd));
+    s = s_new;
+    omc = omc_new;
+}
+
 // sin and 1 - cos at E + d from their values at E, with sin d and 1 - cos d
 // from their Taylor series to d^3 and d^4 (after the first Kepler step |d| is
 // below 0.05, so the dropped terms are below 1e-9): replaces a fresh

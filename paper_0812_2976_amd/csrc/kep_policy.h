@@ -169,8 +169,9 @@ struct PolMixed {
     }
 
     // Kepler solve of NCH chunks of one planet (wave-uniform constants): E, and
-    // sin E, 1 - cos E at E.  From the starting-value table (one accurate Danby
-    // step) where the planet has a table row, else the paper's guess and the
+    // sin E, 1 - cos E at E.  From the starting-value table where the planet has
+    // a table row (one accurate step: Halley's correction on the rows of
+    // KEP_TAB_HALLEY_ROWS, Danby's quartic one above them), else the paper's guess and the
     // eccentricity schedule (or a caller-fixed count, or the convergence-tested
     // loop).  tab: the starting-value table in LDS (the words of kep_start_tab), or null.
     // ROTATE = false: E only (s and omc are left unset).
@@ -197,6 +198,20 @@ struct PolMixed {
             }
 #pragma unroll
             for (int c = 0; c < NCH; ++c) E[c] = start_value(q0[c], q1[c], twe, wm[c], M[c]);
+            if (trow < KEP_TAB_HALLEY_ROWS) {
+                // rows whose start lies within 1.5e-3 rad: the second-order step
+                // suffices (1e-9 rad), and the rotation by it needs two terms
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const float d = halley_step32<true>(E[c], M[c], k, sc[c]);
+                    if constexpr (ROTATE) {
+                        s[c] = sc[c].s;
+                        omc[c] = sc[c].omc;
+                        rotate32_small(s[c], omc[c], d);
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int c = 0; c < NCH; ++c) st[c] = danby_step32<false, true>(E[c], M[c], k, 0.0f, 0.0f, sc[c]);
         } else if (niter > 0) {

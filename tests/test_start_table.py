@@ -6,7 +6,8 @@ E(e_i, M_j)) on e_i = i emax / (NE - 1), M_j = j pi / 128.  The tests read the
 header, check every entry against the oracle's root rounded to binary16, and check
 the property the kernels rely on: the bilinear start lies within 4e-3 rad of the
 root, and one Danby step (Sec. 4.3's quartic correction, float64) from there lands
-within 1e-9 rad, over e <= emax and a dense grid of M including M -> 0 and |M| -> pi.
+within 1e-9 rad, over e <= emax and a dense grid of M including M -> 0 and |M| -> pi;
+on the leading rows the header names, the second-order step alone does.
 """
 import math
 import os
@@ -88,6 +89,43 @@ def test_start_and_one_step(tab):
     print(f"start {far:.3e} rad, after one step {err:.3e} rad")
     assert far <= 4e-3
     assert err <= 1e-9
+
+
+def _halley(E, e, M):
+    """One step of the second-order member of Danby's family (Halley's correction,
+    Sec. 4.3's d2 = -f / (f' + d1 f''/2) with d1 = -f / f'), float64."""
+    f = E - e * np.sin(E) - M
+    f1, f2 = 1 - e * np.cos(E), e * np.sin(E)
+    d1 = -f / f1
+    return E - f / (f1 + d1 * f2 / 2)
+
+
+def test_halley_rows(tab):
+    """On the leading KEP_TAB_HALLEY_ROWS rows the kernels take the second-order step
+    instead of the quartic one: from the bilinear start it lands within 1e-9 rad of the
+    oracle's root, and the start lies within 2e-3 rad (the range of the shortened
+    rotation); the next row needs the quartic step (the band is as wide as it can be)."""
+    ne, nm, emax, T, D, mscale = tab
+    rows = int(re.search(r"#define KEP_TAB_HALLEY_ROWS (\d+)", open(HEADER).read()).group(1))
+    assert 1 <= rows < ne - 1
+    M = np.concatenate([np.linspace(-math.pi, math.pi, 8001),
+                        np.outer([-1.0, 1.0], np.logspace(-9, 0, 400)).ravel(),
+                        [math.pi - 1e-7, -math.pi + 1e-7]])
+    h = emax / (ne - 1)
+
+    def worst(lo, hi, n):
+        far, err = 0.0, 0.0
+        for e in np.linspace(lo, hi, n):
+            R = oracle.kepler(M, np.full(M.size, e))
+            E0 = _start(tab, e, M)
+            far = max(far, float(np.max(np.abs(E0 - R))))
+            err = max(err, float(np.max(np.abs(_halley(E0, e, M) - R))))
+        return far, err
+
+    far, err = worst(0.0, rows * h * (1 - 1e-12), 6 * rows + 1)
+    print(f"Halley band e < {rows * h:.4f}: start {far:.3e} rad, after one step {err:.3e} rad")
+    assert far <= 2e-3 and err <= 1e-9
+    assert worst(rows * h, (rows + 1) * h * (1 - 1e-12), 13)[1] > 1e-9
 
 
 def test_header_is_what_the_generator_writes(tmp_path):
