@@ -53,34 +53,50 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 #     step before the last: scale, hardware sin and cos 3, f and its
 #     three derivatives 5, three corrections with one reciprocal 11,
 #     update 1                                                            20  [3 trans]
-#   last Danby step: sin, 1 - cos, E - sin E from the unfolded polynomials
-#     on |E| <= 3.25 (square 1, two degree-5 polynomials 10, cube, three
-#     products 4) 15, f and its three derivatives 5, three corrections
-#     with one reciprocal 11, update and step 2                            33  [1 trans]
-#   sin/1-cos carried to the final E 11, velocity 5, Kahan planet sum 4   20  [1 trans]
-#   per observation: binary64 residual 6, weighted square 2,
-#     Kahan chi-square 4 -> 12 / n_pl                                          [6 f64]
-# With e ~ U[0, 0.9] a fraction 0.8525 / 0.9 = 0.9472 of the planets start from
-# the table; the others (0.8525 < e <= 0.975 on the eccentricity schedule) take
-# two steps before the last: 2 (0.9 - 0.8525) / 0.9 = 0.1056 early steps per
-# triple on average.
-OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST, OPS_LAST, OPS_VEL, OPS_OBS = 4, 10, 2, 20, 33, 20, 12
-F64_PHASE, F64_OBS = 4, 6
+#   last step on the table's leading rows (KEP_TAB_HALLEY_ROWS, e < 0.6927):
+#     Halley's correction: sin, 1 - cos, E - sin E from the unfolded
+#     polynomials on |E| <= 3.25 (square 1, two degree-5 polynomials 10,
+#     cube, three products 4) 15, f and f' 3, f f''/2 2, denominator 1,
+#     reciprocal 1, numerator 1, step and update 2                         25  [1 trans]
+#   last step elsewhere: Danby's quartic correction: polynomials 15, f and
+#     its three derivatives 5, three corrections with one reciprocal 11,
+#     update and step 2                                                   33  [1 trans]
+#   sin/1-cos carried to the final E: two-term rotation after the Halley
+#     step 8, the full one 11; velocity 5 (D, numerator 2, reciprocal,
+#     product); planet sum in binary64 (convert, add) 2                    [1 trans, 2 f64]
+#   per observation: binary64 residual (two adds, convert) 3, weighted
+#     square 2, Kahan chi-square 4 -> 9 / n_pl                                  [3 f64]
+# With e ~ U[0, e_max] the planets split into the three bands by their share of
+# [0, e_max]; beyond the table (0.8525 < e <= 0.975 on the eccentricity
+# schedule) a planet takes two steps before the last.
+OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST = 4, 10, 2, 20
+OPS_HALLEY, OPS_LAST, OPS_ROT_SMALL, OPS_ROT = 25, 33, 8, 11
+OPS_VEL, OPS_SUM, OPS_OBS = 5, 2, 9
+F64_PHASE, F64_SUM, F64_OBS = 4, 2, 3
 TRANS_FAST, TRANS_LAST, TRANS_VEL = 3, 1, 1
 
 
-def mixed_ops_per_triple(n_pl, f_table, early):
-    """f_table: fraction of the planets started from the table; early: mean Danby
-    steps before the last per triple."""
-    return (OPS_PHASE + f_table * OPS_TABLE + (1.0 - f_table) * OPS_START + OPS_FAST * early + OPS_LAST + OPS_VEL
-            + OPS_OBS / n_pl)
+def start_table_bands():
+    """(table e range, e below which the Halley step is taken) from kep_start_tab.h."""
+    txt = open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", "kep_start_tab.h")).read()
+    d = dict(re.findall(r"#define (KEP_TAB_\w+) ([0-9.eE+-]+)f?", txt))
+    emax, ne, rows = float(d["KEP_TAB_EMAX"]), int(d["KEP_TAB_NE"]), int(d["KEP_TAB_HALLEY_ROWS"])
+    return emax, rows * emax / (ne - 1)
 
 
-def mixed_op_classes(n_pl, f_table, early):
+def mixed_ops_per_triple(n_pl, f_table, early, f_halley=0.0):
+    """f_table: fraction of the planets started from the table (f_halley of them on
+    the Halley rows); early: mean Danby steps before the last per triple."""
+    return (OPS_PHASE + f_table * OPS_TABLE + (1.0 - f_table) * OPS_START + OPS_FAST * early
+            + f_halley * (OPS_HALLEY + OPS_ROT_SMALL) + (1.0 - f_halley) * (OPS_LAST + OPS_ROT)
+            + OPS_VEL + OPS_SUM + OPS_OBS / n_pl)
+
+
+def mixed_op_classes(n_pl, f_table, early, f_halley=0.0):
     """The operations of mixed_ops_per_triple by class: binary64, transcendental, binary32."""
-    f64 = F64_PHASE + F64_OBS / n_pl
+    f64 = F64_PHASE + F64_SUM + F64_OBS / n_pl
     trans = TRANS_FAST * early + TRANS_LAST + TRANS_VEL
-    return {"f32": mixed_ops_per_triple(n_pl, f_table, early) - f64 - trans, "f64": f64, "trans": trans}
+    return {"f32": mixed_ops_per_triple(n_pl, f_table, early, f_halley) - f64 - trans, "f64": f64, "trans": trans}
 
 
 def mix_peak_ops_per_s(classes):
@@ -92,6 +108,11 @@ def mix_peak_ops_per_s(classes):
 def table_fraction(e_max, s_table=0.8525):
     """Fraction of e ~ U[0, e_max] inside the starting-value table's range."""
     return min(e_max, s_table) / e_max
+
+
+def halley_fraction(e_max):
+    """Fraction of e ~ U[0, e_max] on the table rows that take the Halley step."""
+    return min(e_max, start_table_bands()[1]) / e_max
 
 
 def early_steps(e_max, s2=0.8525, s3=0.975):
@@ -133,7 +154,8 @@ def recorded_traffic(name, files=DENSE_FILES):
 # in the f64 class, hardware reciprocals in trans:
 #   pass 1: orbital phase with the correctly rounded quotient (product, exact
 #     remainder, correction, fraction, offset, fraction, scale) and the
-#     conversion 8 f64; starting value 10; last Danby step 33 (1 trans);
+#     conversion 8 f64; starting value 10; last step 25 on the Halley rows of
+#     the table, 33 (Danby's quartic) above them (1 trans);
 #   binary64 correction: sin/cos of the binary32 root (reduction by n pi/2 4,
 #     square 1, degree-13 and degree-14 Taylor series 16; quadrant selects and
 #     signs 9 f32-class), residual of Kepler's equation 2, D 1 + its binary32
@@ -149,16 +171,19 @@ def recorded_traffic(name, files=DENSE_FILES):
 #   per group of 64 NCH observations: the 5 n_pl + 1 lane sums reduced across
 #     the wavefront (R - 1 exchanges, two selects and an add each, R the next
 #     power of two), spread over the group's 64 NCH n_pl triples per lane.
-ADJ_F64, ADJ_F32, ADJ_TRANS = 8 + 44 + 2, 10 + 33 + 17 + 28, 1 + 2 + 1
+ADJ_F64, ADJ_F32, ADJ_TRANS = 8 + 44 + 2, 10 + 17 + 28, 1 + 2 + 1
 ADJ_OBS = {"f64": 3, "f32": 4, "trans": 1}
 
 
-def adjoint_op_classes(n_pl, nch):
+def adjoint_op_classes(n_pl, nch, f_halley=0.0):
+    """f_halley: fraction of the planets whose last step is Halley's (the rest take
+    Danby's quartic one; the adjoint's batches all lie within the table)."""
     r = 1
     while r < 5 * n_pl + 1:
         r *= 2
     red = 3.0 * (r - 1) / (nch * n_pl)
-    return {"f32": ADJ_F32 + ADJ_OBS["f32"] / n_pl + red, "f64": ADJ_F64 + ADJ_OBS["f64"] / n_pl,
+    last = f_halley * OPS_HALLEY + (1.0 - f_halley) * OPS_LAST
+    return {"f32": ADJ_F32 + last + ADJ_OBS["f32"] / n_pl + red, "f64": ADJ_F64 + ADJ_OBS["f64"] / n_pl,
             "trans": ADJ_TRANS + ADJ_OBS["trans"] / n_pl}
 
 
@@ -305,9 +330,9 @@ def main():
     if not np.all(np.isfinite(chi2)):
         raise RuntimeError("non-finite chi-square in the benchmark batch")
 
-    f_table, early = table_fraction(0.9), early_steps(0.9)
-    ops = mixed_ops_per_triple(wl.n_pl, f_table, early) * triples
-    classes = mixed_op_classes(wl.n_pl, f_table, early)
+    f_table, early, f_halley = table_fraction(0.9), early_steps(0.9), halley_fraction(0.9)
+    ops = mixed_ops_per_triple(wl.n_pl, f_table, early, f_halley) * triples
+    classes = mixed_op_classes(wl.n_pl, f_table, early, f_halley)
     achieved = ops / (ms * 1e-3) / 1e12
     peak = mix_peak_ops_per_s(classes) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
@@ -412,7 +437,8 @@ def main():
         result["gradient_c4"] = {"chi2_grad_per_s": w4.n_sys / (msg * 1e-3), "launch_ms": msg,
                                  "triples_per_s": tri4 / (msg * 1e-3),
                                  "roofline": roofline_entry(f"k_grad_obs<{w4.n_pl},{nch4}>",
-                                                            adjoint_op_classes(w4.n_pl, nch4), tri4, msg,
+                                                            adjoint_op_classes(w4.n_pl, nch4, halley_fraction(0.8)),
+                                                            tri4, msg,
                                                             recorded_traffic("rv_chisq_grad_mixed_c4", ADJOINT_FILES)),
                                  "nll_grad_launch_ms": msn,
                                  "gauss_newton": {"launch_ms_mixed": msgn, "launch_ms_fp64": msgn64,
@@ -468,7 +494,7 @@ def main():
         npl_i = np.diff(rw.pl_off)
         nobs_i = np.diff(rw.obs_off)
         core = {c: n - (F64_OBS if c == "f64" else (OPS_OBS - F64_OBS if c == "f32" else 0)) / 4
-                for c, n in mixed_op_classes(4, table_fraction(0.9), early_steps(0.9)).items()}
+                for c, n in mixed_op_classes(4, table_fraction(0.9), early_steps(0.9), halley_fraction(0.9)).items()}
         tri3 = int(np.sum(npl_i * nobs_i))
         obs3 = int(np.sum(nobs_i))
         cls3 = {c: core[c] + (F64_OBS if c == "f64" else (OPS_OBS - F64_OBS if c == "f32" else 0)) * obs3 / tri3
