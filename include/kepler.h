@@ -285,7 +285,7 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
 
 /* Chi-square of every system of the plan's batch into chi2[n_sys] (one graph
    launch on `stream`; does not allocate or synchronise).  Calls on one plan
-   must not overlap in time (they share the plan's work-queue counter). */
+   must not overlap in time (they share the plan's work-queue counters). */
 kep_status rv_chisq_ragged(kep_plan *plan, double *chi2, void *stream);
 
 /* Same work launched directly, without the graph (for comparison). */
@@ -303,7 +303,8 @@ kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream);
    opts->block_threads, 16 systems per work item).
    Arguments as kep_plan_ragged plus chi2[n_sys] (caller-owned device array).
    Limit: n_sys <= 2,097,152 (the work area holds a 32-bit order entry per
-   system; 8 MiB + 256 bytes per GPU, held until the process ends); larger
+   system after 2 KiB of work-queue counters; 8 MiB + 2 KiB per GPU, held
+   until the process ends); larger
    batches return KEP_ERR_SHAPE.  Offsets are not read on the host: a system
    whose offsets fall outside [0, n_obs_total] / [0, n_pl_total], decrease, or
    give n_pl outside [1, KEP_MAX_PL] gets a NaN chi-square (other systems are

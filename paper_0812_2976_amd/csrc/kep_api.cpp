@@ -352,6 +352,7 @@ struct kep_plan {
     double tuned_ms = 0.0;
     int64_t n_obs_total = 0, n_pl_total = 0, triples = 0;
     int32_t *d_order = nullptr;
+    int32_t *d_pos = nullptr;         // work-order position of every system (inverse of the order)
     int64_t *d_obs_off = nullptr;     // the checked CSR offsets (the plan's own copies)
     int64_t *d_pl_off = nullptr;
     unsigned int *d_queue = nullptr;
@@ -496,6 +497,7 @@ void plan_free(kep_plan *p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_pos) (void)hipFree(p->d_pos);
     if (p->d_obs_off) (void)hipFree(p->d_obs_off);
     if (p->d_pl_off) (void)hipFree(p->d_pl_off);
     if (p->d_queue) (void)hipFree(p->d_queue);
@@ -573,8 +575,12 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     p->n_obs_total = obs->n_obs_total;
     p->n_pl_total = par->n_pl_total;
     p->triples = triples;
+    std::vector<int32_t> pos(n_sys);
+    for (int64_t i = 0; i < n_sys; ++i) pos[order[i]] = (int32_t)i;
     if (n_sys > 0 && (hipMalloc(&p->d_order, sizeof(int32_t) * n_sys) != hipSuccess ||
-                      hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess)) {
+                      hipMalloc(&p->d_pos, sizeof(int32_t) * n_sys) != hipSuccess ||
+                      hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess ||
+                      hipMemcpy(p->d_pos, pos.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess)) {
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work order", fn);
     }
@@ -588,8 +594,8 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
         return fail(KEP_ERR_DEVICE, "%s: cannot copy the CSR offsets", fn);
     }
     // the queue and exit counters start at zero; every launch leaves them at zero
-    if (hipMalloc(&p->d_queue, 2 * sizeof(unsigned int)) != hipSuccess ||
-        hipMemset(p->d_queue, 0, 2 * sizeof(unsigned int)) != hipSuccess) {
+    if (hipMalloc(&p->d_queue, kep::kQueueWords * sizeof(unsigned int)) != hipSuccess ||
+        hipMemset(p->d_queue, 0, kep::kQueueWords * sizeof(unsigned int)) != hipSuccess) {
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work queue", fn);
     }
@@ -616,6 +622,7 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     a.offset = par->offset;
     a.jitter = par->jitter;
     a.order = p->d_order;
+    a.pos = p->d_pos;
     a.n_sys = n_sys;
     a.n_obs_total = obs->n_obs_total;
     a.n_pl_total = par->n_pl_total;

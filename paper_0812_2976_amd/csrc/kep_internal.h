@@ -45,7 +45,8 @@ struct RaggedArgs {
     int64_t n_items;          // number of work items = ceil(n_sys / sb)
     int sb;                   // systems per work item
     int gmax;                 // largest observation group, in 64-lane chunks (2 or 4)
-    unsigned int *queue;      // [0]: work-queue counter, [1]: waves done (both zero at launch; the kernel leaves them zero)
+    unsigned int *queue;      // kQueueWords counters (kRaggedQueues work queues, waves done); zero at
+                              // launch, and the kernel leaves them zero
     double *out;
     int fixed_iter, max_iter;
     int64_t n_obs_total, n_pl_total;   // sizes of the CSR arrays (the allocation-free path checks against them)
@@ -54,7 +55,17 @@ struct RaggedArgs {
     // builds both itself at the start of every work item.
     void *recs_pre;
     RaggedSys *sys_pre;
+    const int32_t *pos;       // work-order position of every system (the plan's setup launch)
 };
+
+// Work queues of the persistent ragged kernel: one counter per XCD (blocks go
+// to the XCDs round-robin), each on its own 128-byte line, queue q handing out
+// items q, q + kRaggedQueues, ...; a wave drains its own XCD's queue first,
+// then the others.  The waves-done counter follows the queues.
+constexpr int kRaggedQueues = 8;
+constexpr int kQueueStride = 32;                              // words between counters
+constexpr int kQueueDone = kRaggedQueues * kQueueStride;      // index of the waves-done counter
+constexpr int kQueueWords = kQueueDone + 1;
 
 // Astrometric batch (Thiele-Innes form): epochs t with measured offsets x
 // (RA*cos Dec) and y (Dec), uncertainties sx, sy; planes P, e, M0, A, B, F, G
@@ -94,10 +105,13 @@ struct DemcArgs {
 constexpr int kMaxSB = 32;
 constexpr int kMaxPl = 8;
 
-// Allocation-free ragged path: a static device array holds the queue counter
-// (256 bytes) and the int32 work order of at most kStaticMaxSys systems.
+// Allocation-free ragged path: a static device array holds the queue counters
+// (the first kStaticQueueBytes) and the int32 work order of at most
+// kStaticMaxSys systems.
 constexpr int64_t kStaticMaxSys = 1 << 21;
-constexpr size_t kStaticScratchBytes = 256 + sizeof(int32_t) * (size_t)kStaticMaxSys;
+constexpr size_t kStaticQueueBytes = 2048;
+static_assert(sizeof(unsigned int) * kQueueWords <= kStaticQueueBytes, "queue counters exceed their area");
+constexpr size_t kStaticScratchBytes = kStaticQueueBytes + sizeof(int32_t) * (size_t)kStaticMaxSys;
 
 enum class Prec { F64 = 0, Mixed = 1 };
 

@@ -470,12 +470,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
     __shared__ uint32_t tab[kTabWords];    // Kepler starting values
     load_start_table(tab);
 
+    // this block's XCD queue first (blocks go to the XCDs round-robin), then the others
+    const int home = (int)(blockIdx.x % kRaggedQueues);
+    int tried = 0;
     for (;;) {
-        unsigned int item = 0;
-        if (lane == 0) item = atomicAdd(a.queue, 1u);
-        item = (unsigned int)uniform_int((int)__shfl(item, 0, 64));
-        if ((int64_t)item >= a.n_items) break;
-        const int64_t i0 = (int64_t)item * sb;
+        int64_t item = -1;
+        while (tried < kRaggedQueues) {               // uniform: every lane takes part in the shuffle
+            const int q = (home + tried) % kRaggedQueues;
+            unsigned int k = 0;
+            if (lane == 0) k = atomicAdd(a.queue + q * kQueueStride, 1u);
+            k = (unsigned int)uniform_int(__shfl((int)k, 0, 64));
+            const int64_t it = (int64_t)k * kRaggedQueues + q;
+            if (it < a.n_items) {
+                item = it;
+                break;
+            }
+            ++tried;
+        }
+        if (item < 0) break;
+        const int64_t i0 = item * sb;
         const int nb = (int)min((int64_t)sb, a.n_sys - i0);
         wave_sync_lds();
         int rem = 0;
@@ -497,8 +510,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 acc[lane] = 0.0;
                 bad[lane] = 0;
             }
+            // only the slots of each system's planets (the others were not written)
+            const int npl_lane = lane < nb ? abs(meta[2 * lane]) : 0;
             const RecMixed *src = reinterpret_cast<const RecMixed *>(a.recs_pre) + i0 * kMaxPl;
-            for (int q = lane; q < nb * kMaxPl; q += 64) recs[q] = src[q];
+            for (int q0 = 0; q0 < nb * kMaxPl; q0 += 64) {   // uniform trip count (shuffle)
+                const int q = q0 + lane;
+                const int np_q = __shfl(npl_lane, min(q / kMaxPl, 63), 64);
+                if (q < nb * kMaxPl && q % kMaxPl < np_q) recs[q] = src[q];
+            }
         } else if (lane < nb) {
             const int32_t code = a.order[i0 + lane];
             if (code >= 0) {
@@ -695,27 +714,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
     // the number of waves no wave of this launch touches the queue again.
     if (lane == 0) {
         const unsigned int n_waves = gridDim.x * (blockDim.x >> 6);
-        if (atomicAdd(a.queue + 1, 1u) == n_waves - 1) {
-            atomicExch(a.queue, 0u);
-            atomicExch(a.queue + 1, 0u);
+        if (atomicAdd(a.queue + kQueueDone, 1u) == n_waves - 1) {
+            for (int q = 0; q < kRaggedQueues; ++q) atomicExch(a.queue + q * kQueueStride, 0u);
+            atomicExch(a.queue + kQueueDone, 0u);
         }
     }
 }
 
-// The plan's setup launch: one thread per (work-order position, planet slot);
-// the eight slots of a position are eight consecutive lanes, which combine
-// their domain flags.  Records of slots beyond the system's planet count are
-// not written (the persistent kernel never reads them).
+// The plan's setup launch: one thread per (system, planet slot) in system
+// order, so that the CSR offsets and parameter planes are read in runs; each
+// system's records and data go to its work-order position a.pos[sys].  The
+// eight slots of a system are eight consecutive lanes, which combine their
+// domain flags.  Records of slots beyond the system's planet count are not
+// written (the persistent kernel never reads them).
 __global__ void __launch_bounds__(256) k_ragged_setup(RaggedArgs a)
 {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = gid / kMaxPl;
+    const int64_t sys = gid / kMaxPl;
     const int j = (int)(gid % kMaxPl);
-    const bool live = i < a.n_sys;
-    int64_t sys = 0, p0 = 0, o0 = 0, o1 = 0;
+    const bool live = sys < a.n_sys;
+    int64_t i = 0, p0 = 0, o0 = 0, o1 = 0;
     int npl = 0;
     if (live) {
-        sys = a.order[i];
+        i = a.pos[sys];
         p0 = a.pl_off[sys];
         npl = (int)(a.pl_off[sys + 1] - p0);
         o0 = a.obs_off[sys];
@@ -729,7 +750,7 @@ __global__ void __launch_bounds__(256) k_ragged_setup(RaggedArgs a)
         ok = PolMixed::setup(dummy, a.P[p0 + j], a.K[p0 + j], a.e[p0 + j], a.w[p0 + j], a.M0[p0 + j], r);
         reinterpret_cast<RecMixed *>(a.recs_pre)[i * kMaxPl + j] = r;
     }
-    // every slot of the position joins in (kMaxPl = 8 consecutive lanes)
+    // every slot of the system joins in (kMaxPl = 8 consecutive lanes)
     // (every lane takes part in every exchange: a shuffle read from a lane that
     // skipped it returns no defined value)
     bool all = ok;
@@ -790,10 +811,7 @@ __global__ void __launch_bounds__(kPrepThreads) k_ragged_static_order(const int6
 {
     __shared__ int wtot[kPrepKeys][kPrepThreads / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    if (t == 0) {
-        queue[0] = 0u;
-        queue[1] = 0u;
-    }
+    for (int q = t; q < kQueueWords; q += kPrepThreads) queue[q] = 0u;
     const int64_t c = (n_sys + kPrepThreads - 1) / kPrepThreads;
     const int64_t i0 = min(n_sys, (int64_t)t * c), i1 = min(n_sys, i0 + c);
     auto key_of = [&](int64_t i) {
@@ -879,7 +897,7 @@ hipError_t launch_ragged_static(RaggedArgs a, LaunchShape shape, hipStream_t st)
     hipError_t err = static_scratch(&base);
     if (err != hipSuccess) return err;
     unsigned int *queue = reinterpret_cast<unsigned int *>(base);
-    int32_t *order = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(base) + 256);
+    int32_t *order = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(base) + kStaticQueueBytes);
     hipLaunchKernelGGL(k_ragged_static_order, dim3(1), dim3(kPrepThreads), 0, st, a.obs_off, a.pl_off, a.n_sys,
                        a.n_obs_total, a.n_pl_total, order, queue);
     err = hipGetLastError();
