@@ -95,16 +95,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         if (lane < nb) {
             const int64_t sys = s0 + lane;
             bool ok = isfinite(a.t0);
-#pragma nounroll
-            for (int j = 0; j < NPL; ++j) {
-                const int64_t p = (int64_t)j * a.n_sys + sys;
-                RecGrad r;
-                ok = grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r) && ok;
-                recs[lane * NPL + j] = r;
-            }
             if (a.offset) ok = ok && isfinite(a.offset[sys]);
             if (has_jit) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
             sysbad[lane] = ok ? 0 : 1;
+        }
+        wave_sync_lds();
+        // planet records with the lanes over the batch's (planet, system) pairs,
+        // planet-major (each parameter plane read in one run)
+#pragma nounroll
+        for (int q = lane; q < nb * NPL; q += 64) {
+            const int j = q / nb, sq = q - j * nb;
+            const int64_t p = (int64_t)j * a.n_sys + s0 + sq;
+            RecGrad r;
+            if (!grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r)) sysbad[sq] = 1;
+            recs[sq * NPL + j] = r;
         }
         wave_sync_lds();
 

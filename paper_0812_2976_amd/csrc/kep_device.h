@@ -45,20 +45,6 @@ __device__ __forceinline__ double wave_sum(double x)
 
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Kahan compensated accumulation (Sec. 4.4): the sum is s - c.
-struct Kahan32 {
-    float s, c;
-    __device__ __forceinline__ void init() { s = 0.0f; c = 0.0f; }
-    __device__ __forceinline__ void add(float x)
-    {
-        float y = x - c;
-        float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
-};
-
 // ----------------------------------------------------------------- binary32
 // sin x, 1 - cos x and x - sin x for |x| <= 3 pi / 2.  Arguments beyond pi/2
 // are folded with pi - |x| (pi split in two floats, exact subtraction); on

@@ -101,15 +101,19 @@ k_dense(DenseArgs a)
         if (lane < nb) {
             const int64_t sys = s0 + lane;
             bool ok = isfinite(a.t0);
-            for (int j = 0; j < a.n_pl; ++j) {
-                const int64_t p = (int64_t)j * a.n_sys + sys;
-                Rec r;
-                ok = Pol::setup(a, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r) && ok;
-                recs[lane * a.n_pl + j] = r;
-            }
             if (a.offset) ok = ok && isfinite(a.offset[sys]);
             if (a.jitter) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
             sysbad[lane] = ok ? 0 : 1;
+        }
+        wave_sync_lds();
+        // planet records with the lanes over the batch's (planet, system) pairs,
+        // planet-major (each parameter plane read in one run)
+        for (int q = lane; q < nb * a.n_pl; q += 64) {
+            const int j = q / nb, sq = q - j * nb;
+            const int64_t p = (int64_t)j * a.n_sys + s0 + sq;
+            Rec r;
+            if (!Pol::setup(a, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r)) sysbad[sq] = 1;
+            recs[sq * a.n_pl + j] = r;
         }
         wave_sync_lds();
         }
@@ -190,8 +194,8 @@ k_dense(DenseArgs a)
     }
 }
 
-// Second kernel of the separate-function form: planet sums (Kahan), residuals
-// and the compensated chi-square from the velocities written by kPlanets.
+// Second kernel of the separate-function form: planet sums, residuals and the
+// chi-square (binary64 sums) from the velocities written by kPlanets.
 template <int NCH>
 __global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
 {
@@ -215,8 +219,8 @@ __global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
 #pragma unroll
             for (int c = 0; c < NCH; ++c) m[c].add(o[c].in ? row[c * 64 + lane] : 0.0f);
         }
-        Kahan32 chi;
-        chi.init();
+        PolMixed::ChiAcc chi;
+        PolMixed::chi_init(chi);
         bool bad_obs = false;
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
@@ -225,7 +229,7 @@ __global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
                 bad_obs = bad_obs || !okw || !o[c].ok;
             }
         }
-        const double tot = wave_sum(chi.value());
+        const double tot = wave_sum(PolMixed::chi_value(chi));
         bad = bad || __any(bad_obs);
         if (lane == 0) a.out[sys] = bad ? __builtin_nan("") : tot;
     }
@@ -382,7 +386,7 @@ __device__ __forceinline__ void load_unit(const RaggedArgs &a, int64_t k0, int64
 // lanes over its observations and uniform planet records.
 template <int NCH, int G>
 __device__ __forceinline__ void ragged_unit(const RaggedArgs &a, const RecMixed *recs, int npl, const RawObs<G> &r,
-                                            int64_t left, double gam, double jit, bool has_jit, Kahan32 &chi,
+                                            int64_t left, double gam, double jit, bool has_jit, PolMixed::ChiAcc &chi,
                                             bool &bad_obs, const uint32_t *tab)
 {
     const int lane = __lane_id();
@@ -592,8 +596,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
             int64_t ug = 0;
             RawObs<GMAX> cur, nxt;
             if (us < nb) load_unit<GMAX>(a, uniform_i64(obs0[us]), uniform_i64(nfl[us]), cur);
-            Kahan32 chi;
-            chi.init();
+            PolMixed::ChiAcc chi;
+            PolMixed::chi_init(chi);
             bool bad_obs = false;
             while (us < nb) {
                 const int64_t nf = uniform_i64(nfl[us]);
@@ -615,13 +619,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 else if (left <= 192) ragged_unit<3, GMAX>(a, rs, code, cur, left, gam, jit, has_jit, chi, bad_obs, tab);
                 else ragged_unit<GMAX, GMAX>(a, rs, code, cur, left, gam, jit, has_jit, chi, bad_obs, tab);
                 if (ns != us) {
-                    const double tot = wave_sum(chi.value());
+                    const double tot = wave_sum(PolMixed::chi_value(chi));
                     const bool b = __any(bad_obs);
                     if (lane == 0) {
                         acc[us] = tot;
                         bad[us] = b ? 1 : 0;
                     }
-                    chi.init();
+                    PolMixed::chi_init(chi);
                     bad_obs = false;
                 }
                 us = ns;
@@ -682,10 +686,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                     const RecMixed *rs = recs + sc * kMaxPl;
                     for (int j = 0; j < npl; ++j) m.add(ragged_vel_lane(rs[j], o.tt, a.max_iter, tab));
                     const double gam = gj[2 * sc], jit = gj[2 * sc + 1];
-                    Kahan32 cx;
-                    cx.init();
+                    PolMixed::ChiAcc cx;
+                    PolMixed::chi_init(cx);
                     const bool okw = PolMixed::chi_add(cx, m, o, gam, jit, has_jit);
-                    x = cx.value();
+                    x = PolMixed::chi_value(cx);
                     if (!okw || !o.ok) bad[sc] = 1;     // every writer stores the same value
                 }
                 // segmented scan: a lane adds only partial sums that start inside

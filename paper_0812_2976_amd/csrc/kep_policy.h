@@ -116,7 +116,10 @@ struct PolMixed {
         double s;
         __device__ __forceinline__ void add(float v) { s += (double)v; }
     };
-    using ChiAcc = Kahan32;
+    // the chi-square terms w r^2 (binary32 weight times the binary64 residual)
+    // summed in binary64: no less accurate than the compensated binary32 sum of
+    // Sec. 4.4 and two instructions fewer per observation
+    struct ChiAcc { double s; };
 
     static __device__ __forceinline__ bool setup(const DenseArgs &a, double P, double K, double e, double w,
                                                  double M0, Rec &r)
@@ -290,12 +293,12 @@ struct PolMixed {
     static __device__ __forceinline__ void model_init(ModelAcc &m) { m.s = 0.0; }
     static __device__ __forceinline__ double model_value(const ModelAcc &m) { return m.s; }
 
-    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x.init(); }
+    static __device__ __forceinline__ void chi_init(ChiAcc &x) { x.s = 0.0; }
     // One observation's contribution; returns false if the weight is invalid.
     static __device__ __forceinline__ bool chi_add(ChiAcc &x, const ModelAcc &m, const Obs &o, double gam,
                                                    double jit, bool has_jit)
     {
-        float r = (float)((m.s + gam) - o.v);   // residual formed in binary64
+        const double r = (m.s + gam) - o.v;   // residual formed in binary64
         float w = o.w;
         bool okw = true;
         if (has_jit) {
@@ -305,10 +308,10 @@ struct PolMixed {
         } else {
             okw = o.s2 > 0.0f;
         }
-        x.add(w * r * r);
+        x.s = fma((double)(w * (float)r), r, x.s);
         return okw;
     }
-    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x.value(); }
+    static __device__ __forceinline__ double chi_value(const ChiAcc &x) { return x.s; }
 };
 
 // ------------------------------------------------------------------ binary64
