@@ -64,15 +64,16 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 #   sin/1-cos carried to the final E: two-term rotation after the Halley
 #     step 8, the full one 11; velocity 5 (D, numerator 2, reciprocal,
 #     product); planet sum in binary64 (convert, add) 2                    [1 trans, 2 f64]
-#   per observation: binary64 residual (two adds, convert) 3, weighted
-#     square 2, Kahan chi-square 4 -> 9 / n_pl                                  [3 f64]
+#   per observation: binary64 residual (two adds) and its binary32 copy 3,
+#     weighted residual 1, binary64 accumulation of w r^2 (convert, fused
+#     multiply-add) 2 -> 6 / n_pl                                                [5 f64]
 # With e ~ U[0, e_max] the planets split into the three bands by their share of
 # [0, e_max]; beyond the table (0.8525 < e <= 0.975 on the eccentricity
 # schedule) a planet takes two steps before the last.
 OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST = 4, 10, 2, 20
 OPS_HALLEY, OPS_LAST, OPS_ROT_SMALL, OPS_ROT = 25, 33, 8, 11
-OPS_VEL, OPS_SUM, OPS_OBS = 5, 2, 9
-F64_PHASE, F64_SUM, F64_OBS = 4, 2, 3
+OPS_VEL, OPS_SUM, OPS_OBS = 5, 2, 6
+F64_PHASE, F64_SUM, F64_OBS = 4, 2, 5
 TRANS_FAST, TRANS_LAST, TRANS_VEL = 3, 1, 1
 
 

@@ -21,28 +21,28 @@ def test_operation_count_of_the_mixed_formulation():
     """phase 4 + table start 10 for the 0.8525 / 0.9 of planets inside the table's range,
     else the paper's start 2 and two early steps of 20; last step with its rotation:
     Halley's 25 + 8 on the leading table rows (e < 13 x 0.8525 / 16), Danby's quartic
-    33 + 11 elsewhere; velocity 5 + binary64 planet sum 2 + 9 per observation shared by
+    33 + 11 elsewhere; velocity 5 + binary64 planet sum 2 + 6 per observation shared by
     4 planets."""
     emax, e_h = bench.start_table_bands()
     assert emax == 0.8525 and abs(e_h - 13 * 0.8525 / 16) < 1e-12
     f, early, h = bench.table_fraction(0.9), bench.early_steps(0.9), bench.halley_fraction(0.9)
     assert abs(f - 0.8525 / 0.9) < 1e-12 and abs(early - 2 * (1 - f)) < 1e-12 and abs(h - e_h / 0.9) < 1e-12
-    want = 4 + f * 10 + (1 - f) * (2 + 2 * 20) + h * (25 + 8) + (1 - h) * (33 + 11) + 5 + 2 + 9 / 4
+    want = 4 + f * 10 + (1 - f) * (2 + 2 * 20) + h * (25 + 8) + (1 - h) * (33 + 11) + 5 + 2 + 6 / 4
     assert abs(bench.mixed_ops_per_triple(4, f, early, h) - want) < 1e-12
     # without the table (e beyond its range) the count is the schedule's
-    assert abs(bench.mixed_ops_per_triple(4, 0.0, 2.0) - (4 + 2 + 40 + 33 + 11 + 5 + 2 + 9 / 4)) < 1e-12
+    assert abs(bench.mixed_ops_per_triple(4, 0.0, 2.0) - (4 + 2 + 40 + 33 + 11 + 5 + 2 + 6 / 4)) < 1e-12
 
 
 def test_mix_peak_of_the_formulation():
     """The classes add up to the operation count; a pure binary32 mix peaks at the
     FP32 vector rate (157.3 TFLOP/s / 2 flops per operation), a pure binary64 one at
-    half of it, and the formulation's mix (binary32, 4 + 2 + 3/4 binary64 and 3 per
+    half of it, and the formulation's mix (binary32, 4 + 2 + 5/4 binary64 and 3 per
     early step + 2 transcendental operations per triple) at its operations over
     n32/32 + n64/16 + ntr/8 SIMD cycles."""
     f, early, h = bench.table_fraction(0.9), bench.early_steps(0.9), bench.halley_fraction(0.9)
     c = bench.mixed_op_classes(4, f, early, h)
     assert abs(sum(c.values()) - bench.mixed_ops_per_triple(4, f, early, h)) < 1e-12
-    assert abs(c["f64"] - 6.75) < 1e-12 and abs(c["trans"] - (3 * early + 2)) < 1e-12
+    assert abs(c["f64"] - 7.25) < 1e-12 and abs(c["trans"] - (3 * early + 2)) < 1e-12
     assert abs(bench.mix_peak_ops_per_s({"f32": 1.0}) - 157.3e12 / 2) < 0.1e12
     assert abs(bench.mix_peak_ops_per_s({"f64": 1.0}) - 78.6e12 / 2) < 0.1e12
     cycles = c["f32"] / 32 + c["f64"] / 16 + c["trans"] / 8
