@@ -45,16 +45,16 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 # in brackets the binary64 and transcendental ones, the rest binary32):
 #   orbital phase in binary64: (t - t0)/P + phase offset as one fused
 #     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4  [4 f64]
-#   starting value at e <= 0.8525 (the table of kep_start_tab.h): |M|
-#     scaled and clamped 2, knot index and fraction 2, address 1, two
+#   starting value at e <= 0.9 (the table of kep_start_tab.h): |M|
+#     clamped and scaled 2, knot index and fraction 2, address 1, two
 #     interpolations in e 2 (binary16 operands widened inside the
 #     multiply-add), one in |M| 2, sign of M 1                             10  [one LDS read]
-#   at e > 0.8525 instead: the paper's starting guess 2, and each Danby
+#   at e > 0.9 instead: the paper's starting guess 2, and each Danby
 #     step before the last: scale, hardware sin and cos 3, f and its
 #     three derivatives 5, three corrections with one reciprocal 11,
 #     update 1                                                            20  [3 trans]
-#   last step on the table's leading rows (KEP_TAB_HALLEY_ROWS, e < 0.6927):
-#     Halley's correction: sin, 1 - cos, E - sin E from the unfolded
+#   last step in the table's Halley bands (e < 0.85): Halley's
+#     correction: sin, 1 - cos, E - sin E from the unfolded
 #     polynomials on |E| <= 3.25 (square 1, two degree-5 polynomials 10,
 #     cube, three products 4) 15, f and f' 3, f f''/2 2, denominator 1,
 #     reciprocal 1, numerator 1, step and update 2                         25  [1 trans]
@@ -67,9 +67,9 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 #   per observation: binary64 residual (two adds) and its binary32 copy 3,
 #     weighted residual 1, binary64 accumulation of w r^2 (convert, fused
 #     multiply-add) 2 -> 6 / n_pl                                                [5 f64]
-# With e ~ U[0, e_max] the planets split into the three bands by their share of
-# [0, e_max]; beyond the table (0.8525 < e <= 0.975 on the eccentricity
-# schedule) a planet takes two steps before the last.
+# With e ~ U[0, e_max] the planets split into the three kinds by their share of
+# [0, e_max]; beyond the table (0.9 < e <= 0.975 on the eccentricity schedule)
+# a planet takes two steps before the last.
 OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST = 4, 10, 2, 20
 OPS_HALLEY, OPS_LAST, OPS_ROT_SMALL, OPS_ROT = 25, 33, 8, 11
 OPS_VEL, OPS_SUM, OPS_OBS = 5, 2, 6
@@ -78,11 +78,10 @@ TRANS_FAST, TRANS_LAST, TRANS_VEL = 3, 1, 1
 
 
 def start_table_bands():
-    """(table e range, e below which the Halley step is taken) from kep_start_tab.h."""
+    """The starting-value table's bands from kep_start_tab.h: (e0, e1, Halley step)."""
     txt = open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", "kep_start_tab.h")).read()
-    d = dict(re.findall(r"#define (KEP_TAB_\w+) ([0-9.eE+-]+)f?", txt))
-    emax, ne, rows = float(d["KEP_TAB_EMAX"]), int(d["KEP_TAB_NE"]), int(d["KEP_TAB_HALLEY_ROWS"])
-    return emax, rows * emax / (ne - 1)
+    arr = {k: [float(x) for x in v.split(",")] for k, v in re.findall(r"#define (KEP_TAB_\w+) \{([^}]*)\}", txt)}
+    return list(zip(arr["KEP_TAB_BAND_E0"], arr["KEP_TAB_BAND_E1"], (h == 1 for h in arr["KEP_TAB_BAND_HALLEY"])))
 
 
 def mixed_ops_per_triple(n_pl, f_table, early, f_halley=0.0):
@@ -106,20 +105,20 @@ def mix_peak_ops_per_s(classes):
     return sum(classes.values()) / cycles * SIMDS * CLOCK_HZ
 
 
-def table_fraction(e_max, s_table=0.8525):
+def table_fraction(e_max):
     """Fraction of e ~ U[0, e_max] inside the starting-value table's range."""
-    return min(e_max, s_table) / e_max
+    return min(e_max, start_table_bands()[-1][1]) / e_max
 
 
 def halley_fraction(e_max):
-    """Fraction of e ~ U[0, e_max] on the table rows that take the Halley step."""
-    return min(e_max, start_table_bands()[1]) / e_max
+    """Fraction of e ~ U[0, e_max] in the table bands that take the Halley step."""
+    return sum(max(0.0, min(e_max, e1) - e0) for e0, e1, h in start_table_bands() if h) / e_max
 
 
-def early_steps(e_max, s2=0.8525, s3=0.975):
+def early_steps(e_max, s3=0.975):
     """Mean Danby steps before the last per planet at e ~ U[0, e_max <= s3]: planets
     beyond the table's range follow the schedule, two early steps up to s3."""
-    return 2.0 * max(0.0, min(e_max, s3) - s2) / e_max
+    return 2.0 * max(0.0, min(e_max, s3) - start_table_bands()[-1][1]) / e_max
 
 
 # The sources each timed kernel is compiled from (its counter summaries under

@@ -99,10 +99,13 @@ typedef struct kep_params {
                     eccentricity schedule (2 iterations for e <= 0.8525, 3 up to
                     0.975, 4 up to 0.9955, 5 up to 0.999, then a convergence
                     test), derived offline for a 1e-9 rad worst-case error.
-                    Every KEP_MIXED path except rv_chisq_gn and kepler_solve starts
-                    a planet with e <= 0.8525 from a tabulated E(e, M) (bilinear,
-                    within 3.7e-3 rad; the tabulated guess of Sec. 5.4) and takes
-                    the last iteration only (worst error 4.5e-11 rad in float64).
+                    Every KEP_MIXED path except kepler_solve starts a planet
+                    with e <= 0.9 from a tabulated E(e, M) (bilinear, within
+                    2e-3 rad; the tabulated guess of Sec. 5.4) and takes one
+                    step: Halley's correction (the second-order member of
+                    Danby's family) for e < 0.85 in the kernels that evaluate
+                    one planet across a wavefront, Danby's quartic one
+                    otherwise (worst error 1e-9 rad in float64).
                < 0: early exit in both precisions (schedule, then convergence test).
    max_iter    cap of the convergence-tested iteration (default 10, Sec. 4.3).
    block_threads, blocks_per_cu: launch shape (multiples of 64 / >= 1); 0 = tuned or built-in default. */

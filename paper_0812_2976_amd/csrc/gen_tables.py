@@ -26,14 +26,14 @@
    binary32 rounding (a few ulp of the step) would exceed the target.
 
 3. Starting values for the binary32 Kepler solve (the paper's interpolated initial
-   guess, Sec. 5.4) on the two-step band e <= KEP_S32_E2: E(e_i, M_j) on 17
-   eccentricities and 130 knots M_j = j pi / 128, stored as binary16 pairs (value,
+   guess, Sec. 5.4) for e <= 0.9, in three bands of eccentricity: E(e_i, M_j) on
+   rows of e and knots M_j = j pi / N (N = 128 up to e = 0.7, 256 above, where the
+   root bends more sharply near periapsis), stored as binary16 pairs (value,
    difference to the next eccentricity row) in kep_start_tab.h.  The scan checks that
-   bilinear interpolation starts within a few 1e-3 rad of the root and that one Danby
-   step from there lands within 1e-9 rad (float64), so the kernels that hold the table
-   take the last step only.  A second scan finds the leading rows on which the
-   second-order step (Halley's correction) alone already lands within 1e-9 rad
-   (KEP_TAB_HALLEY_ROWS): there the kernels take that cheaper step instead.
+   bilinear interpolation starts within a few 1e-3 rad of the root and that one step
+   from there lands within 1e-9 rad (float64): the second-order step (Halley's
+   correction) in the first two bands, Danby's quartic one in the last; the kernels
+   that hold the table take that one step only.
 
 Run:  python gen_tables.py         (rewrites kep_tables.h and kep_start_tab.h)
       python gen_tables.py start   (kep_start_tab.h only)
@@ -156,8 +156,13 @@ def schedule(target, n_list=(2, 3, 4, 5), step=1.0 / 2000):
 
 
 START_OUT = os.path.join(HERE, "kep_start_tab.h")
-START_NE = 17          # eccentricity rows e_i = i emax / 16
-START_NM = 130         # knots M_j = j pi / 128, j = 0 .. 129 (two beyond pi: |M| may round past it)
+# Bands of the starting-value table: (e_lo, e_hi, rows, knots, last step).  Rows
+# e_i = e_lo + i (e_hi - e_lo) / rows; knots M_j = j pi / knots, j = 0 .. knots + 1
+# (two beyond pi: |M| may round past it).  The knots are denser where the root
+# bends more sharply in M (near periapsis at high e); the last step is Halley's
+# (second order) where the start is close enough for it, Danby's quartic above.
+START_BANDS = ((0.0, 0.7, 14, 128, "halley"), (0.7, 0.85, 6, 256, "halley"), (0.85, 0.9, 2, 256, "quartic"))
+STEP_TARGET = 1e-9
 
 
 def _root64(e, M):
@@ -170,46 +175,6 @@ def _root64(e, M):
     return E
 
 
-def start_table(emax):
-    """Rows i < NE - 1 of binary16 pairs (E(e_i, M_j), E(e_i+1, M_j) - E(e_i, M_j)), knots
-    over M >= 0; the difference is taken between the rounded values."""
-    M = np.arange(START_NM) * (np.pi / 128)
-    T = np.array([_root64(i * emax / (START_NE - 1), M) for i in range(START_NE)]).astype(np.float16)
-    pairs = np.empty((START_NE - 1, START_NM, 2), dtype=np.float16)
-    pairs[:, :, 0] = T[:-1]
-    pairs[:, :, 1] = (T[1:].astype(np.float64) - T[:-1]).astype(np.float16)
-    return pairs
-
-
-def start_lookup(pairs, emax, e, M):
-    """The kernels' starting value: bilinear in (e, |M|) from the binary16 pairs, sign of M
-    (the interpolation itself in float64)."""
-    fi = np.float64(e) * ((START_NE - 1) / emax)
-    i = min(int(fi), START_NE - 2)
-    we = fi - i
-    fj = np.abs(M) * (128 / np.pi)
-    j = fj.astype(int)
-    wm = fj - j
-    p = pairs.astype(np.float64)
-    r0 = p[i, j, 0] + we * p[i, j, 1]
-    r1 = p[i, j + 1, 0] + we * p[i, j + 1, 1]
-    return np.copysign(r0 + wm * (r1 - r0), M)
-
-
-def start_scan(pairs, emax, n_e=400):
-    """Worst distance of the table start from the root, and worst error after one
-    Danby step from it (float64), over e in [0, emax] and a dense M grid."""
-    M = np.concatenate([np.linspace(-np.pi, np.pi, 20001),
-                        np.outer([-1.0, 1.0], np.logspace(-10, 0, 2001)).ravel()])
-    far, err = 0.0, 0.0
-    for e in np.linspace(0.0, emax, n_e):
-        R = _root64(e, M)
-        E0 = start_lookup(pairs, emax, e, M)
-        far = max(far, float(np.max(np.abs(E0 - R))))
-        err = max(err, float(np.max(np.abs(_danby_step(E0, e, M) - R))))
-    return far, err
-
-
 def _halley_step(E, e, M):
     """Second-order member of Danby's family (Halley's correction), float64."""
     s, c = np.sin(E), np.cos(E)
@@ -218,61 +183,100 @@ def _halley_step(E, e, M):
     return E - f * f1 / (f1 * f1 - 0.5 * f * e * s)
 
 
-def halley_rows(pairs, emax, target=1e-9, n_e=60):
-    """Number of leading table rows (e_i <= e <= e_i+1, endpoints included) on which
-    one Halley step from the table start lands within `target` of the root (float64),
-    and the worst start distance and step error over those rows."""
+def band_table(e_lo, e_hi, rows, knots):
+    """Rows of binary16 pairs (E(e_i, M_j), E(e_i+1, M_j) - E(e_i, M_j)) over M >= 0; the
+    difference is taken between the rounded values.  Shape (rows, knots + 2, 2)."""
+    M = np.arange(knots + 2) * (np.pi / knots)
+    T = np.array([_root64(e_lo + i * (e_hi - e_lo) / rows, M) for i in range(rows + 1)]).astype(np.float16)
+    pairs = np.empty((rows, knots + 2, 2), dtype=np.float16)
+    pairs[:, :, 0] = T[:-1]
+    pairs[:, :, 1] = (T[1:].astype(np.float64) - T[:-1]).astype(np.float16)
+    return pairs
+
+
+def band_lookup(pairs, band, e, M):
+    """The kernels' starting value: bilinear in (e, |M|) from a band's binary16 pairs,
+    sign of M (the interpolation itself in float64)."""
+    e_lo, e_hi, rows, knots, _ = band
+    fi = (np.float64(e) - e_lo) * (rows / (e_hi - e_lo))
+    i = min(int(fi), rows - 1)
+    we = fi - i
+    fj = np.abs(M) * (knots / np.pi)
+    j = fj.astype(int)
+    wm = fj - j
+    p = pairs.astype(np.float64)
+    r0 = p[i, j, 0] + we * p[i, j, 1]
+    r1 = p[i, j + 1, 0] + we * p[i, j + 1, 1]
+    return np.copysign(r0 + wm * (r1 - r0), M)
+
+
+def band_scan(pairs, band, n_per_row=16):
+    """Worst distance of a band's start from the root, and worst error after its last
+    step (float64), over the band's e range (both ends) and a dense M grid."""
+    e_lo, e_hi, rows, _, step = band
     M = np.concatenate([np.linspace(-np.pi, np.pi, 20001),
                         np.outer([-1.0, 1.0], np.logspace(-10, 0, 2001)).ravel()])
-    rows, far, err = 0, 0.0, 0.0
-    for i in range(START_NE - 1):
-        row_far, row_err = 0.0, 0.0
-        for e in np.linspace(i * emax / (START_NE - 1), (i + 1) * emax / (START_NE - 1), n_e):
-            R = _root64(e, M)
-            E0 = start_lookup(pairs, emax, e, M)
-            row_far = max(row_far, float(np.max(np.abs(E0 - R))))
-            row_err = max(row_err, float(np.max(np.abs(_halley_step(E0, e, M) - R))))
-        if row_err > target:
-            break
-        rows, far, err = i + 1, max(far, row_far), max(err, row_err)
-    return rows, far, err
+    far, err = 0.0, 0.0
+    for e in np.linspace(e_lo, e_hi, n_per_row * rows + 1):
+        R = _root64(e, M)
+        E0 = band_lookup(pairs, band, e, M)
+        E1 = _halley_step(E0, e, M) if step == "halley" else _danby_step(E0, e, M)
+        far = max(far, float(np.max(np.abs(E0 - R))))
+        err = max(err, float(np.max(np.abs(E1 - R))))
+    return far, err
 
 
-def write_start_table(emax, out=START_OUT):
-    pairs = start_table(emax)
-    far, err = start_scan(pairs, emax)
-    assert err <= 1e-9, err
-    h_rows, h_far, h_err = halley_rows(pairs, emax)
+def write_start_table(bands=START_BANDS, out=START_OUT):
+    tables, scans, offs = [], [], []
+    off = 0
+    for b in bands:
+        pairs = band_table(*b[:4])
+        far, err = band_scan(pairs, b)
+        assert err <= STEP_TARGET, (b, err)
+        tables.append(pairs)
+        scans.append((far, err))
+        offs.append(off)
+        off += pairs.shape[0] * pairs.shape[1]
     lines = [
         "// Generated by gen_tables.py -- do not edit by hand.",
         "#pragma once",
         "",
-        "// Starting values for the binary32 Kepler solve at e <= KEP_TAB_EMAX.  With",
-        f"// e_i = i KEP_TAB_EMAX / {START_NE - 1} and M_j = j pi / 128, word [i][j] holds the binary16",
-        "// pair (E(e_i, M_j), E(e_i+1, M_j) - E(e_i, M_j)) (first value in the low half),",
-        "// i < KEP_TAB_NE - 1, j < KEP_TAB_NM.  Bilinear interpolation in (e, |M|) with the sign",
-        f"// of M starts at most {far:.2e} rad from the root; one Danby step from there lands",
-        f"// within {err:.1e} rad (float64 scan over e and M).",
-        f"#define KEP_TAB_NE {START_NE}",
-        f"#define KEP_TAB_NM {START_NM}",
-        f"#define KEP_TAB_EMAX {emax!r}",
-        f"#define KEP_TAB_MSCALE {float(np.float32(128 / np.pi))!r}f",
-        f"// On rows i < KEP_TAB_HALLEY_ROWS (e < {h_rows * emax / (START_NE - 1):.4f}) the start lies within {h_far:.2e} rad",
-        f"// of the root and one Halley step (second order) from it lands within {h_err:.1e} rad.",
-        f"#define KEP_TAB_HALLEY_ROWS {h_rows}",
-        "",
-        "static __device__ const unsigned int kep_start_tab[(KEP_TAB_NE - 1) * KEP_TAB_NM] = {",
+        "// Starting values for the binary32 Kepler solve at e <= KEP_TAB_EMAX, in bands of",
+        "// eccentricity.  In band b, row i (e_i = e0 + i (e1 - e0) / rows) and knot",
+        "// M_j = j pi / knots (j = 0 .. knots + 1), word KEP_TAB_BAND_OFF[b] + i (knots + 2) + j",
+        "// holds the binary16 pair (E(e_i, M_j), E(e_i+1, M_j) - E(e_i, M_j)) (first value in",
+        "// the low half).  Bilinear interpolation in (e, |M|) with the sign of M, then one",
+        "// step: Halley's where KEP_TAB_BAND_HALLEY[b] is 1, Danby's quartic where it is 0.",
+        "// float64 scan over each band's e range and M:",
     ]
-    bits = pairs.view(np.uint16).astype(np.uint32)
-    words = (bits[:, :, 0] | (bits[:, :, 1] << 16)).ravel()
-    flat = [f"0x{int(w):08x}u" for w in words]
+    for b, (far, err) in zip(bands, scans):
+        lines.append(f"//   e in [{b[0]}, {b[1]}], {b[2]} rows, {b[3]} knots: start within {far:.2e} rad, "
+                     f"{b[4]} step within {err:.1e} rad")
+    fmt = lambda xs: "{" + ", ".join(xs) + "}"
+    lines += [
+        f"#define KEP_TAB_EMAX {bands[-1][1]!r}",
+        f"#define KEP_TAB_NBANDS {len(bands)}",
+        f"#define KEP_TAB_BAND_E0 {fmt(repr(float(b[0])) for b in bands)}",
+        f"#define KEP_TAB_BAND_E1 {fmt(repr(float(b[1])) for b in bands)}",
+        f"#define KEP_TAB_BAND_ROWS {fmt(str(b[2]) for b in bands)}",
+        f"#define KEP_TAB_BAND_KNOTS {fmt(str(b[3]) for b in bands)}",
+        f"#define KEP_TAB_BAND_OFF {fmt(str(o) for o in offs)}",
+        f"#define KEP_TAB_BAND_HALLEY {fmt('1' if b[4] == 'halley' else '0' for b in bands)}",
+        f"#define KEP_TAB_WORDS {off}",
+        "",
+        "static __device__ const unsigned int kep_start_tab[KEP_TAB_WORDS] = {",
+    ]
+    flat = []
+    for pairs in tables:
+        bits = pairs.view(np.uint16).astype(np.uint32)
+        flat += [f"0x{int(w):08x}u" for w in (bits[:, :, 0] | (bits[:, :, 1] << 16)).ravel()]
     for k in range(0, len(flat), 8):
         lines.append("    " + ", ".join(flat[k:k + 8]) + ",")
     lines.append("};")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
-    print(f"start table: far {far:.3e}, one step {err:.3e}; Halley rows {h_rows} (far {h_far:.3e}, "
-          f"one step {h_err:.3e})")
+    for b, (far, err) in zip(bands, scans):
+        print(f"start table band {b}: far {far:.3e}, one step {err:.3e}")
 
 
 def main():
@@ -323,12 +327,12 @@ def main():
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(open(OUT).read())
-    write_start_table(s32[2])
+    write_start_table()
 
 
 if __name__ == "__main__":
     import sys
     if sys.argv[1:] == ["start"]:
-        write_start_table(0.8525)
+        write_start_table()
     else:
         main()

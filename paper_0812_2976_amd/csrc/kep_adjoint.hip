@@ -143,8 +143,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
                         M64[c] = mean_anomaly64_exact(o[c].tt, ph);
                         M[c] = (float)M64[c];
                     }
-                    PolMixed::solve<NCH, false>(k, uniform_int(rr.niter), uniform_int(rr.check) != 0,
-                                                uniform_int(rr.trow), rr.twe, M, E, sv, omc, a.max_iter, tab);
+                    PolMixed::solve<NCH, false>(k, uniform_int(rr.niter), uniform_int(rr.check) != 0, rr.tp, M, E,
+                                                sv, omc, a.max_iter, tab);
 #pragma unroll
                     for (int c = 0; c < NCH; ++c) model[c] += refine_velocity(rr, E[c], M64[c], sj[c], cj[c]);
 #pragma unroll

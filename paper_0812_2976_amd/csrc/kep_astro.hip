@@ -28,6 +28,7 @@ struct AstroRec {          // one per (system, planet)
     double M0, e, b;       // b = sqrt(1 - e^2)
     double A, B, F, G;
     Ecc32 k;
+    TabPlace tp;           // place in the starting-value table (toff -1: the paper's guess)
     int niter, check;
 };
 
@@ -53,6 +54,7 @@ __device__ __forceinline__ bool astro_setup(const AstroArgs &a, int64_t p, Astro
     r.k = make_ecc32(e);
     r.niter = a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e);
     r.check = a.fixed_iter > 0 ? 1 : 0;
+    r.tp = table_place(e, a.fixed_iter <= 0);
     return ok;
 }
 
@@ -69,7 +71,7 @@ __device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int
     const double u = __builtin_amdgcn_fract(__builtin_amdgcn_fract(q) + r.ph.m0h);
     const double M = fma(u, kTwoPi, -kPi);
     float s32, omc32;
-    const double E0 = (double)kepler32_start((float)M, r.k, tab, r.niter, max_iter, r.check != 0, s32, omc32);
+    const double E0 = (double)kepler32_start((float)M, r.k, r.tp, tab, r.niter, max_iter, r.check != 0, s32, omc32);
     double s, c;
     sincos_reduced(E0, s, c);
     const double d = -(E0 - r.e * s - M) / (1.0 - r.e * c);

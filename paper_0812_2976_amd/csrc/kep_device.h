@@ -199,9 +199,9 @@ __device__ __forceinline__ float danby_step32(float &E, float M, const Ecc32 &k,
 // cancellation-free f: d = -f / (f' + d1 f''/2) with d1 = -f/f', which is
 // -f f' / (f'^2 - f f''/2).  Its error is about (f''^2/(4 f'^2) - f'''/(6 f')) d0^3
 // for a start d0 from the root, so it replaces the quartic step only where the
-// start is close enough (the table rows of KEP_TAB_HALLEY_ROWS: within 1e-9 rad
-// after the step).  Six operations and one reciprocal where the quartic step
-// takes thirteen.  Returns the step (E becomes E + step) and leaves sin E,
+// start is close enough (the table bands marked for it: within 1e-9 rad after
+// the step).  Six operations and one reciprocal where the quartic step takes
+// thirteen.  Returns the step (E becomes E + step) and leaves sin E,
 // 1 - cos E of the iterate it started from in `sc`.
 template <bool WIDE>
 __device__ __forceinline__ float halley_step32(float &E, float M, const Ecc32 &k, SinCos32 &sc)
@@ -215,7 +215,7 @@ __device__ __forceinline__ float halley_step32(float &E, float M, const Ecc32 &k
     return step;
 }
 
-// rotate32 for steps |d| <= 2e-3 (the Halley band of the table): sin d = d and
+// rotate32 for steps |d| <= 2e-3 (the Halley bands of the table): sin d = d and
 // 1 - cos d = d^2/2, whose dropped terms d^3/6 and d^4/24 are below 1.4e-9.
 __device__ __forceinline__ void rotate32_small(float &s, float &omc, float d)
 {
@@ -349,7 +349,21 @@ __device__ __forceinline__ Phase64 make_phase64(double P, double M0)
 // largest epochs of the workloads (q ~ 2.5e6 cycles) that is 4.4e-9 rad, well
 // below binary32's resolution of M (1.2e-7 rad near pi), so no correction
 // step is spent on it.
-__device__ __forceinline__ float mean_anomaly32(double tt, const Phase64 &p)
+// The same without P, for records that only need the centred phase.
+struct PhaseM {
+    double rP, m0h;
+};
+
+__device__ __forceinline__ PhaseM make_phasem(double P, double M0)
+{
+    PhaseM p;
+    p.rP = 1.0 / P;
+    p.m0h = __builtin_amdgcn_fract(fma(M0, kInvTwoPi, 0.5));
+    return p;
+}
+
+template <class Ph>
+__device__ __forceinline__ float mean_anomaly32(double tt, const Ph &p)
 {
     return (float)fma(__builtin_amdgcn_fract(fma(tt, p.rP, p.m0h)), kTwoPi, -kPi);
 }

@@ -239,8 +239,8 @@ __global__ void __launch_bounds__(256) k_gn32(DenseArgs a, double *jtwr, double 
                     const RecGrad &q = pl[j];
                     const double M64 = mean_anomaly64_exact(tt, q.ph);
                     float M[1] = {(float)M64}, E[1], sv[1], omc[1];
-                    PolMixed::solve<1, false>(q.k, uniform_int(q.niter), uniform_int(q.check) != 0,
-                                              uniform_int(q.trow), q.twe, M, E, sv, omc, a.max_iter, kep_start_tab);
+                    PolMixed::solve<1, false>(q.k, uniform_int(q.niter), uniform_int(q.check) != 0, q.tp, M, E, sv,
+                                              omc, a.max_iter, kep_start_tab);
                     float sE, cme, x[5];
                     model += refine_velocity(q, E[0], M64, sE, cme);
                     grad_terms_ce(q, sE, cme, (float)(tt * q.ph.rP), x);

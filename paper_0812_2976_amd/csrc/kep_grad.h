@@ -95,10 +95,10 @@ struct RecGrad {
     Ecc32 k;                       // binary32 e, 1 - e, e/2, e/6
     float b, rb, b2, c0;           // b, 1/b, 1 - e^2, 2 - 2 e^2
     float cw, sw, bcw, bsw;        // cos w, sin w, b cos w, b sin w
-    float twe;                     // weight of table row trow + 1
+    TabPlace tp;                   // place in the starting-value table (toff -1: the paper's guess)
     int16_t niter;                 // Danby steps from the paper's guess (0: convergence test)
     int8_t check;                  // 1 if the step count is fixed by the caller
-    int8_t trow;                   // row of the starting-value table, -1: the paper's guess
+    int8_t pad;
 };
 
 __device__ __forceinline__ bool grad_setup_rec(int fixed_iter, double P, double K, double e, double w, double M0,
@@ -126,14 +126,8 @@ __device__ __forceinline__ bool grad_setup_rec(int fixed_iter, double P, double 
     r.bsw = (float)(b * sw);
     r.niter = (int16_t)(fixed_iter > 0 ? fixed_iter : sched32(r.k.e));
     r.check = fixed_iter > 0 ? 1 : 0;
-    r.trow = -1;
-    r.twe = 0.0f;
-    if (fixed_iter <= 0 && e <= KEP_TAB_EMAX) {
-        const double fi = e * ((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
-        const int i = min((int)fi, KEP_TAB_NE - 2);
-        r.trow = (int8_t)i;
-        r.twe = (float)(fi - i);
-    }
+    r.pad = 0;
+    r.tp = table_place(e, fixed_iter <= 0);
     return ok;
 }
 

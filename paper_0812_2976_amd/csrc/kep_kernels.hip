@@ -129,18 +129,20 @@ k_dense(DenseArgs a)
             for (int g = g_first; g < g_end; ++g) {
                 if (n_groups > 1) load_group(g);
                 if constexpr (MODE == kAnomalies) {
+                    // the same solve as the velocities' (so E is the root the model uses)
                     for (int j = 0; j < a.n_pl; ++j) {
                         const Rec &rr = recs[s * a.n_pl + j];
-                        const int niter = uniform_int(rr.niter);
                         float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
+                        float M[NCH], E[NCH], sv[NCH], omc[NCH];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) M[c] = mean_anomaly32(o[c].tt, rr.ph);
+                        PolMixed::solve<NCH, false>(rr.k, uniform_int(rr.niter), uniform_int(rr.check) != 0, rr.tp, M,
+                                                    E, sv, omc, a.max_iter, tab);
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) {
-                            float sE, omcE;
-                            const float E = kepler32_start(mean_anomaly32(o[c].tt, rr.ph), rr.k, tab, niter,
-                                                           a.max_iter, rr.check != 0, sE, omcE);
                             if (o[c].in) {
                                 const int64_t k = (int64_t)g * 64 * NCH + c * 64 + lane;
-                                row[k] = (sbad || !o[c].ok) ? __builtin_nanf("") : E;
+                                row[k] = (sbad || !o[c].ok) ? __builtin_nanf("") : E[c];
                             }
                         }
                     }
@@ -419,7 +421,7 @@ __device__ __forceinline__ float ragged_vel_lane(const RecMixed &r, double tt, i
 {
     const float M = mean_anomaly32(tt, r.ph);
     float s, omc;
-    kepler32_start(M, r.k, tab, r.niter, max_iter, r.check != 0, s, omc);
+    kepler32_start(M, r.k, r.tp, tab, r.niter, max_iter, r.check != 0, s, omc);
     const float D = fmaf(r.k.e, omc, r.k.ome);           // 1 - e cos E
     const float num = fmaf(r.B, s, fmaf(-r.A, omc, r.A));  // A cos E + B sin E
     return num * rcp32(D);

@@ -33,8 +33,54 @@ __device__ __forceinline__ float half_hi(uint32_t w)
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
 }
 
-// The starting-value table (Sec. 5.4's interpolated guess; kep_start_tab.h).
-constexpr int kTabWords = (KEP_TAB_NE - 1) * KEP_TAB_NM;
+// The starting-value table (Sec. 5.4's interpolated guess; kep_start_tab.h):
+// bands of eccentricity, each with its rows, knots in |M| and last step.
+constexpr int kTabWords = KEP_TAB_WORDS;
+constexpr int kTabBands = KEP_TAB_NBANDS;
+constexpr double kTabE0[kTabBands] = KEP_TAB_BAND_E0;
+constexpr double kTabE1[kTabBands] = KEP_TAB_BAND_E1;
+constexpr int kTabRows[kTabBands] = KEP_TAB_BAND_ROWS;
+constexpr int kTabKnots[kTabBands] = KEP_TAB_BAND_KNOTS;
+constexpr int kTabOff[kTabBands] = KEP_TAB_BAND_OFF;
+constexpr int kTabHalley[kTabBands] = KEP_TAB_BAND_HALLEY;
+
+// A planet's place in the table: the word offset of its row, the weight of the
+// next eccentricity row, the band's knots per radian of |M| and its last step.
+struct TabPlace {
+    float twe;       // weight of the next eccentricity row
+    float mscale;    // knots / pi
+    int16_t toff;    // word offset of the row; -1: outside the table
+    int8_t halley;   // 1: Halley's step from the start, 0: Danby's quartic one
+    int8_t pad;
+};
+
+// The table place of eccentricity e (binary64, as given); outside the table, or
+// when the caller fixes the step count (use = false), toff is -1.
+__device__ __forceinline__ TabPlace table_place(double e, bool use)
+{
+    TabPlace t;
+    t.twe = 0.0f;
+    t.mscale = 0.0f;
+    t.toff = -1;
+    t.halley = 0;
+    t.pad = 0;
+    if (!use || !(e >= 0.0 && e <= KEP_TAB_EMAX)) return t;
+    int band = 0;
+#pragma unroll
+    for (int b = 1; b < kTabBands; ++b) band = e >= kTabE0[b] ? b : band;
+#pragma unroll
+    for (int b = 0; b < kTabBands; ++b) {
+        if (b == band) {
+            const double fi = (e - kTabE0[b]) * (kTabRows[b] / (kTabE1[b] - kTabE0[b]));
+            const int i = min((int)fi, kTabRows[b] - 1);
+            t.twe = (float)(fi - i);
+            t.mscale = (float)(kTabKnots[b] / kPi);
+            t.toff = (int16_t)(kTabOff[b] + i * (kTabKnots[b] + 2));
+            t.halley = (int8_t)kTabHalley[b];
+        }
+    }
+    return t;
+}
 
 // Copy of the table into a block's LDS; every thread of the block calls it
 // before any wave reads the table (it ends with the block barrier).
@@ -44,11 +90,12 @@ __device__ __forceinline__ void load_start_table(uint32_t *dst)
     __syncthreads();
 }
 
-// Knot of |M| and its fraction: j in [0, 128] (a NaN clamps to the last knot, so
-// the two words j, j + 1 read after it stay inside the row).
-__device__ __forceinline__ int start_knot(float M, float &wm)
+// Knot of |M| and its fraction for mscale = knots / pi: |M| is clamped to pi
+// (binary32 pi, so j <= knots; a NaN clamps there too), so the two words j,
+// j + 1 read after it stay inside the row of knots + 2 words.
+__device__ __forceinline__ int start_knot(float M, float mscale, float &wm)
 {
-    const float fj = fminf(fabsf(M) * KEP_TAB_MSCALE, 128.0f);
+    const float fj = fminf(fabsf(M), KEP_PI_HI_F) * mscale;
     wm = __builtin_amdgcn_fractf(fj);
     return (int)fj;
 }
@@ -63,18 +110,16 @@ __device__ __forceinline__ float start_value(uint32_t w0, uint32_t w1, float twe
 }
 
 // Kepler solve of one lane for kernels whose lanes hold different planets: from
-// the LDS starting-value table (row and weight from the binary32 e) and the
-// accurate last step alone where e <= KEP_TAB_EMAX and the step count is the
-// schedule's, else kepler32.  Returns E and sin E, 1 - cos E.
-__device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const uint32_t *tab, int niter,
-                                                int max_iter, bool check, float &sinE, float &omcE)
+// the LDS starting-value table at the planet's place and Danby's quartic step
+// (valid in every band; the cheaper Halley step would split the wavefront),
+// else kepler32.  Returns E and sin E, 1 - cos E.
+__device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const TabPlace &tp, const uint32_t *tab,
+                                                int niter, int max_iter, bool check, float &sinE, float &omcE)
 {
-    if (tab != nullptr && !check && k.e <= (float)KEP_TAB_EMAX) {
-        const float fi = k.e * (float)((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
-        const int i = min((int)fi, KEP_TAB_NE - 2);
+    if (tab != nullptr && tp.toff >= 0) {
         float wm;
-        const uint32_t *q = tab + i * KEP_TAB_NM + start_knot(M, wm);
-        float E = start_value(q[0], q[1], fi - (float)i, wm, M);
+        const uint32_t *q = tab + tp.toff + start_knot(M, tp.mscale, wm);
+        float E = start_value(q[0], q[1], tp.twe, wm, M);
         SinCos32 sc;
         const float st = danby_step32<false, true>(E, M, k, 0.0f, 0.0f, sc);
         sinE = sc.s;
@@ -87,14 +132,15 @@ __device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const u
 
 // ------------------------------------------------------------------ mixed
 struct RecMixed {          // 56 bytes, one per (system, planet)
-    Phase64 ph;            // P, 1/P, fract(M0/(2 pi) + 1/2)
+    PhaseM ph;             // 1/P, fract(M0/(2 pi) + 1/2)
     Ecc32 k;               // e, 1 - e, e/2, e/6
     float A, B;            // K b^2 cos w, -K b sin w  (b = sqrt(1 - e^2))
-    float twe;             // weight of row trow + 1 of the starting-value table
+    TabPlace tp;           // place in the starting-value table (toff -1: the paper's guess)
     int16_t niter;         // Danby steps from the paper's guess (0: convergence test)
     int8_t check;          // 1 if the step count is fixed by the caller
-    int8_t trow;           // row of the starting-value table, -1: the paper's guess only
+    int8_t pad;
 };
+static_assert(sizeof(RecMixed) == 56, "planet record size");
 
 struct ObsMixed {
     double tt;   // t - t0
@@ -126,7 +172,7 @@ struct PolMixed {
     {
         bool ok = planet_ok(P, K, e, w, M0);
         if (!ok) { P = 1.0; K = 0.0; e = 0.0; w = 0.0; M0 = 0.0; }
-        r.ph = make_phase64(P, M0);
+        r.ph = make_phasem(P, M0);
         r.k = make_ecc32(e);
         const double b2 = (1.0 - e) * (1.0 + e);
         double sw, cw;
@@ -135,15 +181,9 @@ struct PolMixed {
         r.B = (float)(-K * sqrt(b2) * sw);
         r.niter = (int16_t)(a.fixed_iter > 0 ? a.fixed_iter : sched32(r.k.e));
         r.check = a.fixed_iter > 0 ? 1 : 0;
-        // kernels that hold the table start from it (one Danby step) at e <= KEP_TAB_EMAX
-        r.trow = -1;
-        r.twe = 0.0f;
-        if (a.fixed_iter <= 0 && e <= KEP_TAB_EMAX) {
-            const double fi = e * ((KEP_TAB_NE - 1) / KEP_TAB_EMAX);
-            const int i = min((int)fi, KEP_TAB_NE - 2);
-            r.trow = (int8_t)i;
-            r.twe = (float)(fi - i);
-        }
+        r.pad = 0;
+        // kernels that hold the table start from it (one step) at e <= KEP_TAB_EMAX
+        r.tp = table_place(e, a.fixed_iter <= 0);
         return ok;
     }
 
@@ -173,36 +213,37 @@ struct PolMixed {
 
     // Kepler solve of NCH chunks of one planet (wave-uniform constants): E, and
     // sin E, 1 - cos E at E.  From the starting-value table where the planet has
-    // a table row (one accurate step: Halley's correction on the rows of
-    // KEP_TAB_HALLEY_ROWS, Danby's quartic one above them), else the paper's guess and the
+    // a place in it (one accurate step: Halley's correction in the bands marked
+    // for it, Danby's quartic one in the others), else the paper's guess and the
     // eccentricity schedule (or a caller-fixed count, or the convergence-tested
     // loop).  tab: the starting-value table in LDS (the words of kep_start_tab), or null.
     // ROTATE = false: E only (s and omc are left unset).
     template <int NCH, bool ROTATE = true>
-    static __device__ __forceinline__ void solve(const Ecc32 &k, int niter, bool check, int trow, float twe,
+    static __device__ __forceinline__ void solve(const Ecc32 &k, int niter, bool check, const TabPlace &tp,
                                                  const float (&M)[NCH], float (&E)[NCH], float (&s)[NCH],
                                                  float (&omc)[NCH], int max_iter, const uint32_t *tab)
     {
         float st[NCH];
         SinCos32 sc[NCH];
-        if (tab != nullptr && trow >= 0) {
+        const int toff = uniform_int(tp.toff);
+        if (tab != nullptr && toff >= 0) {
             // tabulated starting value (the paper's interpolated initial guess, Sec. 5.4):
             // bilinear in (e, |M|) within 3.7e-3 rad of the root, close enough for the
             // accurate last step alone (4.5e-11 rad in float64; scan in gen_tables.py)
             // (every chunk's reads are issued before any is used)
-            const uint32_t *row = tab + trow * KEP_TAB_NM;
+            const uint32_t *row = tab + toff;
             float wm[NCH];
             uint32_t q0[NCH], q1[NCH];
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
-                const uint32_t *q = row + start_knot(M[c], wm[c]);
+                const uint32_t *q = row + start_knot(M[c], tp.mscale, wm[c]);
                 q0[c] = q[0];                          // binary16 (E_i, E_i+1 - E_i) at knot j
                 q1[c] = q[1];
             }
 #pragma unroll
-            for (int c = 0; c < NCH; ++c) E[c] = start_value(q0[c], q1[c], twe, wm[c], M[c]);
-            if (trow < KEP_TAB_HALLEY_ROWS) {
-                // rows whose start lies within 1.5e-3 rad: the second-order step
+            for (int c = 0; c < NCH; ++c) E[c] = start_value(q0[c], q1[c], tp.twe, wm[c], M[c]);
+            if (uniform_int(tp.halley) != 0) {
+                // bands whose start lies within 1.3e-3 rad: the second-order step
                 // suffices (1e-9 rad), and the rotation by it needs two terms
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
@@ -274,14 +315,13 @@ struct PolMixed {
                                                       const uint32_t *tab = nullptr)
     {
         // rr comes from an LDS broadcast: every lane holds the same values
-        const Phase64 ph = rr.ph;
+        const PhaseM ph = rr.ph;
         const Ecc32 k = rr.k;
         const float A = rr.A, B = rr.B;
         float M[NCH], E[NCH], s[NCH], omc[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) M[c] = mean_anomaly32(o[c].tt, ph);
-        solve<NCH>(k, uniform_int(rr.niter), uniform_int(rr.check) != 0, uniform_int(rr.trow), rr.twe, M, E, s, omc,
-                   max_iter, tab);
+        solve<NCH>(k, uniform_int(rr.niter), uniform_int(rr.check) != 0, rr.tp, M, E, s, omc, max_iter, tab);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             float D = fmaf(k.e, omc[c], k.ome);              // 1 - e cos E

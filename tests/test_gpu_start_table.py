@@ -1,12 +1,13 @@
 """GPU parity at the edges of the Kepler starting-value table (Sec. 5.4's tabulated
-guess, used by the mixed kernels for e <= 0.8525).
+guess, used by the mixed kernels for e <= 0.9, in bands of eccentricity).
 
-Eccentricities on every table row, at 0, just inside and just outside the table's
-range; observation times that put the mean anomaly exactly on the M knots j pi / 128,
-at 0, at +-pi and a hair either side of them.  The eccentric anomalies of the
-Kepler-only entry point must meet the same bound as elsewhere (binary32 Kepler bound
-plus the two binary64 phases, modulo 2 pi) and the model velocities the mixed
-velocity tolerance, 1e-3 m/s; in binary64 the velocities agree to 1e-9 m/s.
+Eccentricities on every row of every band, at 0, at the band edges, just inside and
+just outside the table's range; observation times that put the mean anomaly exactly
+on the M knots j pi / N of each band (N = 128 and 256), at 0, at +-pi and a hair
+either side of them.  The eccentric anomalies must meet the same bound as elsewhere
+(binary32 Kepler bound plus the two binary64 phases, modulo 2 pi) and the model
+velocities the mixed velocity tolerance, 1e-3 m/s; in binary64 the velocities agree
+to 1e-9 m/s.
 """
 import math
 
@@ -17,18 +18,19 @@ import torch
 import oracle
 import paper_0812_2976_amd as kp
 from tests import workloads as W
+from tests.test_start_table import _read_header
 
 pytestmark = pytest.mark.gpu
 
-EMAX = 0.8525
-
 
 def _edge_case():
-    es = ([0.0, 1e-12] + [i * EMAX / 16 for i in range(17)]
-          + [EMAX * (1 - 1e-12), float(np.nextafter(EMAX, 1.0)), EMAX + 1e-9, 0.86, 0.95])
+    emax, _, bands = _read_header()
+    rows = sorted({bd["e0"] + i * (bd["e1"] - bd["e0"]) / bd["rows"] for bd in bands for i in range(bd["rows"] + 1)})
+    es = ([0.0, 1e-12] + rows + [float(np.nextafter(bd["e0"], 0.0)) for bd in bands[1:]]
+          + [emax * (1 - 1e-12), float(np.nextafter(emax, 1.0)), emax + 1e-9, 0.92, 0.95])
     n_sys = len(es)
     P = 10.0
-    knots = np.arange(129) * (math.pi / 128)
+    knots = np.unique(np.concatenate([np.arange(bd["knots"] + 1) * (math.pi / bd["knots"]) for bd in bands]))
     M = np.concatenate([knots, -knots[1:], [math.pi - 1e-7, -math.pi + 1e-7, 1e-7, -1e-7, 1e-3, -1e-3]])
     M = np.concatenate([M, np.random.default_rng(5).uniform(-math.pi, math.pi, 300)])
     t = np.sort(P * (M / (2 * math.pi)))                 # t0 = 0, M0 = 0: M(t) = 2 pi t / P
