@@ -274,12 +274,9 @@ typedef struct kep_plan kep_plan;   /* opaque; owned by the library */
    item x observation group size on this batch unless opts fixes
    block_threads; results are cached per device and shape class, and kept in
    the text file named by the environment variable KEP_TUNE_CACHE if set), and
-   records a HIP graph of two launches: a setup kernel that writes each
-   system's planet records (binary32 constants of the Kepler solve and the
-   velocity, checked against the parameter domain) into a plan-owned device
-   array, and the persistent kernel that reads them (it leaves its work-queue
-   counters at zero for the next launch, so no reset is recorded).  May
-   allocate and synchronises `stream`.  The plan keeps the
+   records the persistent kernel as a HIP graph (the kernel leaves its
+   work-queue counters at zero for the next launch, so no reset is
+   recorded).  May allocate and synchronises `stream`.  The plan keeps the
    other input pointers: their contents may change between calls, their
    addresses and sizes may not.  Only KEP_MIXED is implemented for ragged batches
    (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */

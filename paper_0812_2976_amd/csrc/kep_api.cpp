@@ -352,12 +352,9 @@ struct kep_plan {
     double tuned_ms = 0.0;
     int64_t n_obs_total = 0, n_pl_total = 0, triples = 0;
     int32_t *d_order = nullptr;
-    int32_t *d_pos = nullptr;         // work-order position of every system (inverse of the order)
     int64_t *d_obs_off = nullptr;     // the checked CSR offsets (the plan's own copies)
     int64_t *d_pl_off = nullptr;
     unsigned int *d_queue = nullptr;
-    void *d_recs = nullptr;           // planet records in work order [n_sys][kMaxPl] (setup launch)
-    kep::RaggedSys *d_sys = nullptr;  // per-position system data (setup launch)
     double *bound_out = nullptr;      // output pointer recorded in the graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -435,7 +432,6 @@ kep_status plan_capture(kep_plan *p, hipStream_t user)
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
         return fail(KEP_ERR_DEVICE, "kep_plan_ragged: hipStreamCreate failed");
     hipError_t err = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (err == hipSuccess) err = kep::launch_ragged_setup(p->args, cap);
     if (err == hipSuccess) err = kep::launch_ragged(p->args, p->shape, p->grid, cap);
     hipGraph_t g = nullptr;
     hipError_t err2 = hipStreamEndCapture(cap, &g);
@@ -497,12 +493,9 @@ void plan_free(kep_plan *p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->d_order) (void)hipFree(p->d_order);
-    if (p->d_pos) (void)hipFree(p->d_pos);
     if (p->d_obs_off) (void)hipFree(p->d_obs_off);
     if (p->d_pl_off) (void)hipFree(p->d_pl_off);
     if (p->d_queue) (void)hipFree(p->d_queue);
-    if (p->d_recs) (void)hipFree(p->d_recs);
-    if (p->d_sys) (void)hipFree(p->d_sys);
     delete p;
 }
 
@@ -575,12 +568,8 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     p->n_obs_total = obs->n_obs_total;
     p->n_pl_total = par->n_pl_total;
     p->triples = triples;
-    std::vector<int32_t> pos(n_sys);
-    for (int64_t i = 0; i < n_sys; ++i) pos[order[i]] = (int32_t)i;
     if (n_sys > 0 && (hipMalloc(&p->d_order, sizeof(int32_t) * n_sys) != hipSuccess ||
-                      hipMalloc(&p->d_pos, sizeof(int32_t) * n_sys) != hipSuccess ||
-                      hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess ||
-                      hipMemcpy(p->d_pos, pos.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess)) {
+                      hipMemcpy(p->d_order, order.data(), sizeof(int32_t) * n_sys, hipMemcpyHostToDevice) != hipSuccess)) {
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work order", fn);
     }
@@ -599,15 +588,7 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
         plan_free(p);
         return fail(KEP_ERR_DEVICE, "%s: cannot allocate the work queue", fn);
     }
-    // the setup launch's outputs: records of every position's planet slots and its system data
-    if (n_sys > 0 && (hipMalloc(&p->d_recs, kep::ragged_record_bytes() * kep::kMaxPl * (size_t)n_sys) != hipSuccess ||
-                      hipMalloc(&p->d_sys, sizeof(kep::RaggedSys) * (size_t)n_sys) != hipSuccess)) {
-        plan_free(p);
-        return fail(KEP_ERR_DEVICE, "%s: cannot allocate the planet records", fn);
-    }
     kep::RaggedArgs &a = p->args;
-    a.recs_pre = p->d_recs;
-    a.sys_pre = p->d_sys;
     a.t = obs->t;
     a.v = obs->v;
     a.sigma = obs->sigma;
@@ -622,7 +603,6 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     a.offset = par->offset;
     a.jitter = par->jitter;
     a.order = p->d_order;
-    a.pos = p->d_pos;
     a.n_sys = n_sys;
     a.n_obs_total = obs->n_obs_total;
     a.n_pl_total = par->n_pl_total;
@@ -668,12 +648,6 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
                 return fail(KEP_ERR_DEVICE, "%s: cannot allocate tuning scratch", fn);
             }
             a.out = scratch;
-            // the records do not depend on the launch shape: built once for the tuning
-            if (kep::launch_ragged_setup(a, st) != hipSuccess) {
-                (void)hipFree(scratch);
-                plan_free(p);
-                return fail(KEP_ERR_LAUNCH, "%s: setup launch failed", fn);
-            }
             double best = 1e30;
             const int blocks[] = {64, 128, 256};
             const int sbs[] = {1, 2, 4, 8, 16, 32};
@@ -743,8 +717,7 @@ kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream)
     kep::RaggedArgs a = plan->args;
     a.out = chi2;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t err = kep::launch_ragged_setup(a, st);
-    if (err == hipSuccess) err = kep::launch_ragged(a, plan->shape, plan->grid, st);
+    hipError_t err = kep::launch_ragged(a, plan->shape, plan->grid, st);
     return launch_status(err, fn);
 }
 

@@ -24,14 +24,6 @@ struct DenseArgs {
     int max_iter;      // cap of the convergence-tested loop
 };
 
-// One system of a ragged batch at its work-order position, as the plan's
-// setup launch leaves it for the persistent kernel.
-struct RaggedSys {
-    int64_t o0, nobs;     // first observation, observation count
-    double gam, jit;      // offset and jitter (0 where not given)
-    int32_t sys, code;    // system index; planet count, negated if the system is outside the domain
-};
-
 // Ragged (CSR) batch, one persistent launch.
 struct RaggedArgs {
     const double *t, *v, *sigma;
@@ -50,12 +42,6 @@ struct RaggedArgs {
     double *out;
     int fixed_iter, max_iter;
     int64_t n_obs_total, n_pl_total;   // sizes of the CSR arrays (the allocation-free path checks against them)
-    // With a plan: planet records [work-order position][kMaxPl] (RecMixed, built by
-    // launch_ragged_setup) and RaggedSys [position]; null: the persistent kernel
-    // builds both itself at the start of every work item.
-    void *recs_pre;
-    RaggedSys *sys_pre;
-    const int32_t *pos;       // work-order position of every system (the plan's setup launch)
 };
 
 // Work queues of the persistent ragged kernel: one counter per XCD (blocks go
@@ -130,10 +116,6 @@ hipError_t launch_grad_mixed(DenseArgs a, bool nll, LaunchShape shape, hipStream
 hipError_t launch_planet_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_chisq_from_velocities(DenseArgs a, LaunchShape shape, hipStream_t st);
 hipError_t launch_ragged(RaggedArgs a, LaunchShape shape, int grid, hipStream_t st);
-// Planet records and per-system data of every work-order position into
-// a.recs_pre / a.sys_pre (one thread per planet slot); bytes of one record.
-hipError_t launch_ragged_setup(RaggedArgs a, hipStream_t st);
-size_t ragged_record_bytes();
 int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 // The allocation-free variant: checks and orders the systems on the device
 // (into the static scratch array), then runs the persistent kernel; a.order

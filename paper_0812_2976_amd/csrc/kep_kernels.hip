@@ -498,33 +498,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         const int nb = (int)min((int64_t)sb, a.n_sys - i0);
         wave_sync_lds();
         int rem = 0;
-        const bool pre = a.recs_pre != nullptr;
-        if (pre) {
-            // the plan's setup launch built the records and per-system data in work
-            // order: one contiguous block of this item's positions
-            if (lane < nb) {
-                const RaggedSys q = a.sys_pre[i0 + lane];
-                meta[2 * lane] = q.code;
-                meta[2 * lane + 1] = q.sys;
-                pofs[lane] = 0;
-                rem = (int)(q.nobs & 63);
-                tail0[lane] = q.o0 + (q.nobs - rem);
-                obs0[lane] = q.o0;
-                nfl[lane] = q.nobs - rem;
-                gj[2 * lane] = q.gam;
-                gj[2 * lane + 1] = q.jit;
-                acc[lane] = 0.0;
-                bad[lane] = 0;
-            }
-            // only the slots of each system's planets (the others were not written)
-            const int npl_lane = lane < nb ? abs(meta[2 * lane]) : 0;
-            const RecMixed *src = reinterpret_cast<const RecMixed *>(a.recs_pre) + i0 * kMaxPl;
-            for (int q0 = 0; q0 < nb * kMaxPl; q0 += 64) {   // uniform trip count (shuffle)
-                const int q = q0 + lane;
-                const int np_q = __shfl(npl_lane, min(q / kMaxPl, 63), 64);
-                if (q < nb * kMaxPl && q % kMaxPl < np_q) recs[q] = src[q];
-            }
-        } else if (lane < nb) {
+        if (lane < nb) {
             const int32_t code = a.order[i0 + lane];
             if (code >= 0) {
                 const int64_t sys = code;
@@ -562,7 +536,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         wave_sync_lds();
         DenseArgs dummy;
         dummy.fixed_iter = a.fixed_iter;
-        for (int q = lane; !pre && q < nb * kMaxPl; q += 64) {
+        for (int q = lane; q < nb * kMaxPl; q += 64) {
             const int s = q / kMaxPl, j = q - s * kMaxPl;
             if (j < meta[2 * s]) {
                 const int64_t p = pofs[s] + j;
@@ -572,7 +546,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
             }
         }
         wave_sync_lds();
-        if (!pre && lane < nb) {
+        if (lane < nb) {
             const int npl = meta[2 * lane];
             const int64_t sys = meta[2 * lane + 1];
             bool ok = isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
@@ -726,71 +700,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         }
     }
 }
-
-// The plan's setup launch: one thread per (system, planet slot) in system
-// order, so that the CSR offsets and parameter planes are read in runs; each
-// system's records and data go to its work-order position a.pos[sys].  The
-// eight slots of a system are eight consecutive lanes, which combine their
-// domain flags.  Records of slots beyond the system's planet count are not
-// written (the persistent kernel never reads them).
-__global__ void __launch_bounds__(256) k_ragged_setup(RaggedArgs a)
-{
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t sys = gid / kMaxPl;
-    const int j = (int)(gid % kMaxPl);
-    const bool live = sys < a.n_sys;
-    int64_t i = 0, p0 = 0, o0 = 0, o1 = 0;
-    int npl = 0;
-    if (live) {
-        i = a.pos[sys];
-        p0 = a.pl_off[sys];
-        npl = (int)(a.pl_off[sys + 1] - p0);
-        o0 = a.obs_off[sys];
-        o1 = a.obs_off[sys + 1];
-    }
-    bool ok = true;
-    if (live && j < npl) {
-        DenseArgs dummy;
-        dummy.fixed_iter = a.fixed_iter;
-        RecMixed r;
-        ok = PolMixed::setup(dummy, a.P[p0 + j], a.K[p0 + j], a.e[p0 + j], a.w[p0 + j], a.M0[p0 + j], r);
-        reinterpret_cast<RecMixed *>(a.recs_pre)[i * kMaxPl + j] = r;
-    }
-    // every slot of the system joins in (kMaxPl = 8 consecutive lanes)
-    // (every lane takes part in every exchange: a shuffle read from a lane that
-    // skipped it returns no defined value)
-    bool all = ok;
-#pragma unroll
-    for (int d = 1; d < kMaxPl; d <<= 1) {
-        const int other = __shfl_xor(all ? 1 : 0, d, 64);
-        all = all && other != 0;
-    }
-    if (live && j == 0) {
-        const double g = a.offset ? a.offset[sys] : 0.0;
-        const double sj = a.jitter ? a.jitter[sys] : 0.0;
-        bool good = all && isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
-        if (a.offset) good = good && isfinite(g);
-        if (a.jitter) good = good && isfinite(sj) && sj >= 0.0;
-        RaggedSys q;
-        q.o0 = o0;
-        q.nobs = o1 - o0;
-        q.gam = g;
-        q.jit = sj;
-        q.sys = (int32_t)sys;
-        q.code = good ? npl : -npl;
-        a.sys_pre[i] = q;
-    }
-}
-
-hipError_t launch_ragged_setup(RaggedArgs a, hipStream_t st)
-{
-    if (a.n_sys <= 0 || !a.recs_pre || !a.sys_pre) return hipSuccess;
-    const int64_t threads = a.n_sys * kMaxPl;
-    hipLaunchKernelGGL(k_ragged_setup, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, a);
-    return hipGetLastError();
-}
-
-size_t ragged_record_bytes() { return sizeof(RecMixed); }
 
 // ------------------------------------------------------- ragged, no allocation
 // Device memory of the allocation-free ragged entry point: the work-queue
