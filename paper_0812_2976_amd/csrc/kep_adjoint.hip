@@ -28,29 +28,6 @@ namespace kep {
 
 namespace {
 
-struct ObsG {
-    double tt, v;   // t - t0, observed velocity
-    float s2;       // sigma^2
-    bool in, ok;    // a real observation; t, v, sigma finite and sigma >= 0
-};
-
-__device__ __forceinline__ void load_obs_g(const DenseArgs &a, int64_t k, ObsG &o)
-{
-    o.in = k < a.n_obs;
-    const double t = o.in ? a.t[k] : a.t0;
-    const double v = o.in ? a.v[k] : 0.0;
-    const double s = o.in ? a.sigma[k] : 1.0;
-    o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
-    o.tt = t - a.t0;
-    o.v = v;
-    o.s2 = (float)(s * s);
-}
-
-// A compiler barrier: the planet records are read from LDS where they are
-// used, instead of every planet's record being held in registers across both
-// passes.
-__device__ __forceinline__ void lds_reload_barrier() { __asm__ volatile("" ::: "memory"); }
-
 constexpr int pow2_at_least(int n) { return n <= 1 ? 1 : 2 * pow2_at_least((n + 1) / 2); }
 
 __host__ __device__ inline size_t adj_table_offset(int wpb, int sb, int npl)

@@ -13,9 +13,9 @@
 // product.  The augmented column gives J^T W r and chi2 from the same products.
 //
 // binary64 path (k_gn64): rows in binary64, v_mfma_f64_16x16x4_f64.
-// Mixed path (k_gn32): rows in binary32 (the derivative terms are binary32
-// already), v_mfma_f32_16x16x4_f32 over each group of 64 observations, and
-// each group's sums added into binary64 accumulators, so one rounding error
+// Mixed path (k_gn_obs): rows in binary32 (the derivative terms are binary32
+// already), v_mfma_f32_16x16x4_f32 over each chunk of 64 observations, and
+// each chunk's sums added into binary64 accumulators, so one rounding error
 // spans at most 64 terms.  The binary32 tile halves the LDS per wavefront
 // (more resident wavefronts) and the binary32 products issue at twice the
 // binary64 rate.
@@ -164,149 +164,269 @@ __global__ void __launch_bounds__(256) k_gn64(DenseArgs a, double *jtwr, double 
 
 // ------------------------------------------------------------------ mixed
 
-// The tile is column-major, T[c * kGn32Col + obs]: a lane writes its row with
-// unit stride across the wavefront, and the matrix operands are read as runs
-// of four consecutive observations (128-bit loads).  Observation 16 g + s of
-// the group feeds step s of lane group g = l/16: the Gram matrix sums over all
-// observations, so any fixed assignment of observations to (step, k) slots,
-// the same for both operands, gives the same products.
-constexpr int kGn32Col = 68;   // 64 observations + 4: consecutive columns start 4 banks apart
+// Mixed path (k_gn_obs): the observations of a system in NCH chunks of 64
+// per lane, like the mixed adjoint (kep_adjoint.hip): pass 1 over the chunks
+// (binary64 phase, binary32 Kepler solve from the starting-value table,
+// binary64 correction of E and the velocity) gives every chunk's sin E and
+// cos E - e per planet and its binary64 residual; then, one chunk at a time,
+// each lane writes its row of sqrt(w) [J | 1 | r] (the derivative terms of the
+// corrected root) into the wavefront's tile and the tile's Gram matrix is
+// accumulated with v_mfma_f32_16x16x4_f32, each chunk's sums added into
+// binary64 accumulators.  The tile is column-major, T[c * kGnCol + obs]: a
+// lane writes its row with unit stride across the wavefront, and the matrix
+// operands are read as runs of four consecutive observations (128-bit loads).
+// Observation 16 g + 4 s + u of the chunk feeds step u of lane group g = l/16
+// in the s-th run: the Gram matrix sums over all observations, so any fixed
+// assignment of observations to (step, k) slots, the same for both operands,
+// gives the same products.  Only the 5 n_pl + 2 live columns are stored; the
+// operands of the padding columns are zeros.
+constexpr int kGnCol = 68;   // 64 observations + 4: consecutive columns start 4 banks apart
 
-template <int NB>
-__host__ __device__ inline size_t gn32_lds_per_wave()
+template <int NPL>
+__host__ __device__ constexpr int gn_cols() { return 5 * NPL + 2; }
+
+template <int NPL>
+__host__ __device__ inline size_t gn_obs_lds_per_wave(int sb)
 {
-    const size_t b = (size_t)16 * NB * kGn32Col * sizeof(float) + (size_t)kMaxPl * sizeof(RecGrad);
+    const size_t b = (size_t)gn_cols<NPL>() * kGnCol * sizeof(float) + (size_t)sb * NPL * sizeof(RecGrad) +
+                     (size_t)sb * sizeof(int);
     return (b + 15) & ~(size_t)15;
 }
 
-template <int NB>
-__global__ void __launch_bounds__(256) k_gn32(DenseArgs a, double *jtwr, double *jtwj)
+template <int NPL, int NCH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gn_obs(DenseArgs a, double *jtwr,
+                                                                                       double *jtwj)
 {
-    constexpr int NCOL = 16 * NB;
+    constexpr int NC = gn_cols<NPL>();       // parameters, offset, residual
+    constexpr int NP = NC - 1;               // parameters and offset
+    constexpr int NB = (NC + 15) / 16;       // 16-column blocks
     constexpr int NPAIR = NB * (NB + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = __lane_id();
     const int wpb = blockDim.x >> 6;
     const int wib = uniform_int(threadIdx.x >> 6);
-    unsigned char *mine = smem + (size_t)wib * gn32_lds_per_wave<NB>();
+    unsigned char *mine = smem + (size_t)wib * gn_obs_lds_per_wave<NPL>(a.sb);
     float *T = reinterpret_cast<float *>(mine);
-    RecGrad *pl = reinterpret_cast<RecGrad *>(mine + (size_t)NCOL * kGn32Col * sizeof(float));
+    RecGrad *recs = reinterpret_cast<RecGrad *>(mine + (size_t)NC * kGnCol * sizeof(float));
+    int *sysbad = reinterpret_cast<int *>(recs + (size_t)a.sb * NPL);
 
-    const int npl = a.n_pl;
-    const int np = 5 * npl + 1;
-    const bool has_jit = a.jitter != nullptr;
-    const int n_chunks = (int)((a.n_obs + 63) / 64);
+    const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
     const int64_t n_waves = (int64_t)gridDim.x * wpb;
+    const int64_t n_batches = (a.n_sys + a.sb - 1) / a.sb;
+    const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
+    const bool has_jit = a.jitter != nullptr;
     const double nan = __builtin_nan("");
-    float *col = T + lane;                       // this lane's observation in column 0
-    // padding columns np + 1 .. NCOL - 1 stay zero for the whole launch
-    for (int c = np + 1; c < NCOL; ++c) col[c * kGn32Col] = 0.0f;
+    float *col = T + lane;                   // this lane's observation in column 0
+    // operand columns of this lane: 16 b + l%16 in block b (clamped into the tile;
+    // zeros beyond the live columns)
+    const float *src[NB];
+    bool live[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int c = 16 * b + (lane & 15);
+        live[b] = c < NC;
+        src[b] = T + (live[b] ? c : NC - 1) * kGnCol + 16 * (lane >> 4);
+    }
 
-    for (int64_t sys = (int64_t)blockIdx.x * wpb + wib; sys < a.n_sys; sys += n_waves) {
+    ObsG o[NCH];
+    auto load_group = [&](int g) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) load_obs_g(a, (int64_t)g * 64 * NCH + c * 64 + lane, o[c]);
+    };
+    if (n_groups <= 1) load_group(0);
+
+    for (int64_t bt = gw; bt < n_batches; bt += n_waves) {
+        const int64_t s0 = bt * a.sb;
+        const int nb = (int)min((int64_t)a.sb, a.n_sys - s0);
         wave_sync_lds();
-        bool pok = true;
-        if (lane < npl) {
-            const int64_t p = (int64_t)lane * a.n_sys + sys;
-            RecGrad q;
-            pok = grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], q);
-            pl[lane] = q;
+        if (lane < nb) {
+            const int64_t sys = s0 + lane;
+            bool ok = isfinite(a.t0);
+            if (a.offset) ok = ok && isfinite(a.offset[sys]);
+            if (has_jit) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
+            sysbad[lane] = ok ? 0 : 1;
         }
-        const double gam = a.offset ? a.offset[sys] : 0.0;
-        const double jit = has_jit ? a.jitter[sys] : 0.0;
-        bool ok = isfinite(a.t0) && !__any(!pok);
-        if (a.offset) ok = ok && isfinite(gam);
-        if (has_jit) ok = ok && isfinite(jit) && jit >= 0.0;
+        wave_sync_lds();
+        // planet records with the lanes over the batch's (planet, system) pairs
+#pragma nounroll
+        for (int q = lane; q < nb * NPL; q += 64) {
+            const int j = q / nb, sq = q - j * nb;
+            const int64_t p = (int64_t)j * a.n_sys + s0 + sq;
+            RecGrad r;
+            if (!grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r)) sysbad[sq] = 1;
+            recs[sq * NPL + j] = r;
+        }
         wave_sync_lds();
 
-        d4 acc[NPAIR];
+        for (int s = 0; s < nb; ++s) {
+            const int64_t sys = s0 + s;
+            const double gam = a.offset ? a.offset[sys] : 0.0;
+            const double jit = has_jit ? a.jitter[sys] : 0.0;
+            const float jit2 = (float)(jit * jit);
+            const bool sbad = uniform_int(sysbad[s]) != 0;
+            const RecGrad *rs = recs + s * NPL;
+            d4 acc[NPAIR];
 #pragma unroll
-        for (int p = 0; p < NPAIR; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
-        bool bad_obs = false;
-        for (int ch = 0; ch < n_chunks; ++ch) {
-            const int64_t k = (int64_t)ch * 64 + lane;
-            if (k < a.n_obs) {
-                const double t = a.t[k], vo = a.v[k], sg = a.sigma[k];
-                const double var = sg * sg + jit * jit;
-                bool ook = isfinite(t) && isfinite(vo) && isfinite(sg) && sg >= 0.0 && var > 0.0;
-                const float sw = ook ? __builtin_amdgcn_rsqf((float)var) : 0.0f;   // sqrt(w)
-                const double tt = t - a.t0;
-                // per planet: the binary32 Kepler solve from the starting-value
-                // table (read through the cache) or the schedule, the binary64
-                // correction of E and binary64 velocity, the derivative terms of the
-                // corrected root (as the mixed adjoint: kep_grad.h)
-                double model = 0.0;
-                for (int j = 0; j < npl; ++j) {
-                    const RecGrad &q = pl[j];
-                    const double M64 = mean_anomaly64_exact(tt, q.ph);
-                    float M[1] = {(float)M64}, E[1], sv[1], omc[1];
-                    PolMixed::solve<1, false>(q.k, uniform_int(q.niter), uniform_int(q.check) != 0, q.tp, M, E, sv,
-                                              omc, a.max_iter, kep_start_tab);
-                    float sE, cme, x[5];
-                    model += refine_velocity(q, E[0], M64, sE, cme);
-                    grad_terms_ce(q, sE, cme, (float)(tt * q.ph.rP), x);
-                    const float fK = (float)q.fK;
-                    float *c = col + 5 * j * kGn32Col;
-                    c[0 * kGn32Col] = sw * ((float)q.fP * x[0]);
-                    c[1 * kGn32Col] = sw * x[1];
-                    c[2 * kGn32Col] = sw * (fK * x[2]);
-                    c[3 * kGn32Col] = -sw * (fK * x[3]);
-                    c[4 * kGn32Col] = -sw * (fK * x[4]);
-                }
-                const double r = (model + gam) - vo;   // residual in binary64
-                col[(np - 1) * kGn32Col] = sw;
-                col[np * kGn32Col] = sw * (float)r;
-                bad_obs = bad_obs || !ook;
-            } else {
-                for (int c = 0; c <= np; ++c) col[c * kGn32Col] = 0.0f;   // rows past the last observation
-            }
-            wave_sync_lds();
-            // A operand of step s, lane l: column 16 bi + l%16, observation 16 (l/16) + s;
-            // the B operand reads the same pattern for bj.
-            const float *src = T + (lane & 15) * kGn32Col + 16 * (lane >> 4);
-            f4 accf[NPAIR];
+            for (int p = 0; p < NPAIR; ++p) acc[p] = d4{0.0, 0.0, 0.0, 0.0};
+            bool bad_obs = false;
+            for (int g = 0; g < n_groups; ++g) {
+                if (n_groups > 1) load_group(g);
+                // pass 1 (as the mixed adjoint): corrected velocities; sin E and
+                // cos E - e kept per planet and chunk
+                double model[NCH];
+                float sE[NPL][NCH], cme[NPL][NCH];
 #pragma unroll
-            for (int p = 0; p < NPAIR; ++p) accf[p] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+                for (int c = 0; c < NCH; ++c) model[c] = gam;
+#pragma nounroll
+                for (int j = 0; j < NPL; ++j) {
+                    const RecGrad &rr = rs[j];
+                    double M64[NCH];
+                    float M[NCH], E[NCH], sv[NCH], omc[NCH], sj[NCH], cj[NCH];
 #pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                f4 av[NB];
+                    for (int c = 0; c < NCH; ++c) {
+                        M64[c] = mean_anomaly64_exact(o[c].tt, rr.ph);
+                        M[c] = (float)M64[c];
+                    }
+                    PolMixed::solve<NCH, false>(rr.k, uniform_int(rr.niter), uniform_int(rr.check) != 0, rr.tp, M, E,
+                                                sv, omc, a.max_iter, kep_start_tab);
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    av[b] = *reinterpret_cast<const f4 *>(src + 16 * b * kGn32Col + 4 * s4);
+                    for (int c = 0; c < NCH; ++c) model[c] += refine_velocity(rr, E[c], M64[c], sj[c], cj[c]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    int p = 0;
+                    for (int jj = 0; jj < NPL; ++jj) {
+                        if (jj == j) {
 #pragma unroll
-                    for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-                        for (int bj = bi; bj < NB; ++bj) {
-                            accf[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi][u], av[bj][u], accf[p], 0, 0, 0);
-                            ++p;
+                            for (int c = 0; c < NCH; ++c) {
+                                sE[jj][c] = sj[c];
+                                cme[jj][c] = cj[c];
+                            }
                         }
                     }
                 }
+                // pass 2, one chunk at a time: the rows of sqrt(w) [J | 1 | r] into
+                // the tile, then the tile's Gram matrix
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const float var = o[c].s2 + jit2;
+                    const bool use = o[c].in && o[c].ok && var > 0.0f;
+                    if (o[c].in) bad_obs = bad_obs || !o[c].ok || !(var > 0.0f);
+                    const float sw = use ? __builtin_amdgcn_rsqf(var) : 0.0f;   // sqrt(w)
+                    const double r = model[c] - o[c].v;                          // residual in binary64
+#pragma unroll
+                    for (int j = 0; j < NPL; ++j) {
+                        lds_reload_barrier();
+                        const RecGrad &rr = rs[j];
+                        float x[5];
+                        grad_terms_ce(rr, sE[j][c], cme[j][c], (float)(o[c].tt * rr.ph.rP), x);
+                        const float fK = (float)rr.fK;
+                        float *cj = col + 5 * j * kGnCol;
+                        cj[0 * kGnCol] = sw * ((float)rr.fP * x[0]);
+                        cj[1 * kGnCol] = sw * x[1];
+                        cj[2 * kGnCol] = sw * (fK * x[2]);
+                        cj[3 * kGnCol] = -sw * (fK * x[3]);
+                        cj[4 * kGnCol] = -sw * (fK * x[4]);
+                    }
+                    col[(NP - 1) * kGnCol] = sw;
+                    col[NP * kGnCol] = use ? sw * (float)r : 0.0f;
+                    wave_sync_lds();
+                    f4 accf[NPAIR];
+#pragma unroll
+                    for (int p = 0; p < NPAIR; ++p) accf[p] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        f4 av[NB];
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) {
+                            const f4 v = *reinterpret_cast<const f4 *>(src[b] + 4 * s4);
+                            av[b] = live[b] ? v : f4{0.0f, 0.0f, 0.0f, 0.0f};
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            int p = 0;
+#pragma unroll
+                            for (int bi = 0; bi < NB; ++bi) {
+#pragma unroll
+                                for (int bj = bi; bj < NB; ++bj) {
+                                    accf[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi][u], av[bj][u], accf[p], 0,
+                                                                                    0, 0);
+                                    ++p;
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int p = 0; p < NPAIR; ++p)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[p][q] += (double)accf[p][q];
+                    wave_sync_lds();
+                }
             }
+            const bool ok = !sbad && !__any(bad_obs);
+            // lane l holds entry (16 bi + 4 (l/16) + q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
+            // (the binary32 16x16x4 product keeps four consecutive output rows per lane)
+            int p = 0;
 #pragma unroll
-            for (int p = 0; p < NPAIR; ++p)
+            for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] += (double)accf[p][q];
-            wave_sync_lds();
+                for (int bj = bi; bj < NB; ++bj) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        gn_store(a, jtwr, jtwj, sys, NP, 16 * bi + 4 * (lane >> 4) + q, 16 * bj + (lane & 15),
+                                 ok ? acc[p][q] : nan);
+                    ++p;
+                }
+            }
         }
-        ok = ok && !__any(bad_obs);
+    }
+}
 
-        // lane l holds entry (16 bi + 4 (l/16) + q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
-        // (the binary32 16x16x4 product keeps four consecutive output rows per lane)
-        int p = 0;
-#pragma unroll
-        for (int bi = 0; bi < NB; ++bi) {
-#pragma unroll
-            for (int bj = bi; bj < NB; ++bj) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    gn_store(a, jtwr, jtwj, sys, np, 16 * bi + 4 * (lane >> 4) + q, 16 * bj + (lane & 15),
-                             ok ? acc[p][q] : nan);
-                ++p;
-            }
-        }
+template <int NPL, int NCH>
+hipError_t launch_gn_obs_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+{
+    const int block = shape.block > 0 ? shape.block : 256;
+    const int wpb = block / 64;
+    // systems per setup batch: tiles and records within 40 KiB per block (four
+    // blocks of four wavefronts on a CU's 160 KiB), at most kMaxSB
+    int sb_cap = kMaxSB;
+    while (sb_cap > 1 && (size_t)wpb * gn_obs_lds_per_wave<NPL>(sb_cap) > 40 * 1024) --sb_cap;
+    void (*kern)(DenseArgs, double *, double *) = k_gn_obs<NPL, NCH>;
+    int per_cu = shape.blocks_per_cu;
+    if (per_cu <= 0) per_cu = cached_occupancy((const void *)kern, block, (size_t)wpb * gn_obs_lds_per_wave<NPL>(sb_cap));
+    const int64_t max_waves = (int64_t)device_cu_count() * per_cu * wpb;
+    int64_t sb = (a.n_sys + max_waves - 1) / (max_waves > 0 ? max_waves : 1);
+    sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
+    a.sb = (int)sb;
+    const size_t lds = (size_t)wpb * gn_obs_lds_per_wave<NPL>(a.sb);
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
+    const int64_t n_batches = (a.n_sys + sb - 1) / sb;
+    int64_t grid = (n_batches + wpb - 1) / wpb;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    if (grid > cap) grid = cap;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(block), lds, st, a, jtwr, jtwj);
+    return hipGetLastError();
+}
+
+// Observation chunks per lane: one for n_obs <= 64, else two (at c4, 262,144 x 4
+// x 256: one chunk 2.74 ms, two 2.50 ms, four 2.65 ms).
+template <int NPL>
+hipError_t launch_gn_obs_npl(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+{
+    if (a.n_obs <= 64) return launch_gn_obs_t<NPL, 1>(a, jtwr, jtwj, shape, st);
+    return launch_gn_obs_t<NPL, 2>(a, jtwr, jtwj, shape, st);
+}
+
+hipError_t launch_gn_mixed(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+{
+    switch (a.n_pl) {
+        case 1: return launch_gn_obs_npl<1>(a, jtwr, jtwj, shape, st);
+        case 2: return launch_gn_obs_npl<2>(a, jtwr, jtwj, shape, st);
+        case 3: return launch_gn_obs_npl<3>(a, jtwr, jtwj, shape, st);
+        case 4: return launch_gn_obs_npl<4>(a, jtwr, jtwj, shape, st);
+        case 5: return launch_gn_obs_npl<5>(a, jtwr, jtwj, shape, st);
+        case 6: return launch_gn_obs_npl<6>(a, jtwr, jtwj, shape, st);
+        case 7: return launch_gn_obs_npl<7>(a, jtwr, jtwj, shape, st);
+        case 8: return launch_gn_obs_npl<8>(a, jtwr, jtwj, shape, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -331,10 +451,9 @@ hipError_t launch_gn_k(KernelFn kern, size_t per_wave, DenseArgs a, double *jtwr
 }
 
 template <int NB>
-hipError_t launch_gn_t(bool mixed, DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
+hipError_t launch_gn64_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape shape, hipStream_t st)
 {
-    return mixed ? launch_gn_k(k_gn32<NB>, gn32_lds_per_wave<NB>(), a, jtwr, jtwj, shape, st)
-                 : launch_gn_k(k_gn64<NB>, gn64_lds_per_wave<NB>(), a, jtwr, jtwj, shape, st);
+    return launch_gn_k(k_gn64<NB>, gn64_lds_per_wave<NB>(), a, jtwr, jtwj, shape, st);
 }
 
 }  // namespace
@@ -342,11 +461,11 @@ hipError_t launch_gn_t(bool mixed, DenseArgs a, double *jtwr, double *jtwj, Laun
 hipError_t launch_gn(DenseArgs a, double *jtwr, double *jtwj, Prec prec, LaunchShape shape, hipStream_t st)
 {
     if (a.n_sys <= 0) return hipSuccess;
-    const bool mixed = prec == Prec::Mixed;
+    if (prec == Prec::Mixed) return launch_gn_mixed(a, jtwr, jtwj, shape, st);
     const int ncol = 5 * a.n_pl + 2;   // parameters, offset, residual
-    if (ncol <= 16) return launch_gn_t<1>(mixed, a, jtwr, jtwj, shape, st);
-    if (ncol <= 32) return launch_gn_t<2>(mixed, a, jtwr, jtwj, shape, st);
-    if (ncol <= 48) return launch_gn_t<3>(mixed, a, jtwr, jtwj, shape, st);
+    if (ncol <= 16) return launch_gn64_t<1>(a, jtwr, jtwj, shape, st);
+    if (ncol <= 32) return launch_gn64_t<2>(a, jtwr, jtwj, shape, st);
+    if (ncol <= 48) return launch_gn64_t<3>(a, jtwr, jtwj, shape, st);
     return hipErrorInvalidValue;
 }
 

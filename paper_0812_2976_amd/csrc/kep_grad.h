@@ -131,6 +131,31 @@ __device__ __forceinline__ bool grad_setup_rec(int fixed_iter, double P, double 
     return ok;
 }
 
+// A compiler barrier: the planet records are read from LDS where they are
+// used, instead of every planet's record being held in registers across both
+// passes of the kernels with the lanes over observations.
+__device__ __forceinline__ void lds_reload_barrier() { __asm__ volatile("" ::: "memory"); }
+
+// One observation of the kernels with the lanes over observations (the mixed
+// adjoint and Gauss-Newton products).
+struct ObsG {
+    double tt, v;   // t - t0, observed velocity
+    float s2;       // sigma^2
+    bool in, ok;    // a real observation; t, v, sigma finite and sigma >= 0
+};
+
+__device__ __forceinline__ void load_obs_g(const DenseArgs &a, int64_t k, ObsG &o)
+{
+    o.in = k < a.n_obs;
+    const double t = o.in ? a.t[k] : a.t0;
+    const double v = o.in ? a.v[k] : 0.0;
+    const double s = o.in ? a.sigma[k] : 1.0;
+    o.ok = isfinite(t) && isfinite(v) && isfinite(s) && s >= 0.0;
+    o.tt = t - a.t0;
+    o.v = v;
+    o.s2 = (float)(s * s);
+}
+
 // Mean anomaly in binary64 for the corrected root, centred on [-pi, pi): the
 // quotient q = (t - t0)/P correctly rounded (the product with the correctly
 // rounded 1/P, then one correction by its exact remainder, t - t0 - q P by a
