@@ -240,9 +240,10 @@ __global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
 // ------------------------------------------------------------------ Kepler only
 // Standalone Kepler solve (the paper's Kepler-only mode): one lane per pair.
 // M is reduced to [-pi, pi] with 2 pi as a double-double; the root is returned
-// on the input's branch.
+// on the input's branch.  Mixed: from the starting-value table (the block's
+// LDS copy) and one quartic step where e <= KEP_TAB_EMAX, else the schedule.
 template <bool MIXED>
-__device__ __forceinline__ double kepler_one(double M, double e, int fixed, int max_iter)
+__device__ __forceinline__ double kepler_one(double M, double e, int fixed, int max_iter, const uint32_t *tab)
 {
     const bool ok = isfinite(M) && isfinite(e) && e >= 0.0 && e < 1.0;
     if (!ok) { M = 0.0; e = 0.0; }
@@ -254,7 +255,8 @@ __device__ __forceinline__ double kepler_one(double M, double e, int fixed, int 
         const Ecc32 k = make_ecc32(e);
         const int niter = fixed > 0 ? fixed : sched32(k.e);
         float sE, omcE;   // unused here: the standalone solve returns E only
-        E = (double)kepler32((float)Mr, k, niter, max_iter, fixed > 0, sE, omcE);
+        E = (double)kepler32_start((float)Mr, k, table_place(e, fixed <= 0), tab, niter, max_iter, fixed > 0, sE,
+                                   omcE);
     } else {
         E = kepler64(Mr, e, Mr >= 0.0 ? 1.0 : -1.0, fixed, max_iter);
     }
@@ -270,6 +272,12 @@ template <bool MIXED, int KU>
 __global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, const double *__restrict__ ev,
                                                double *__restrict__ Ev, int64_t n, int fixed, int max_iter)
 {
+    const uint32_t *tab = nullptr;
+    if constexpr (MIXED) {
+        __shared__ uint32_t tab_s[kTabWords];    // Kepler starting values
+        load_start_table(tab_s);
+        tab = tab_s;
+    }
     const int64_t tile = (int64_t)blockDim.x * KU;
     const int64_t stride = (int64_t)gridDim.x * tile;
     for (int64_t base = (int64_t)blockIdx.x * tile + threadIdx.x; base < n; base += stride) {
@@ -283,7 +291,7 @@ __global__ void __launch_bounds__(256) k_kepler(const double *__restrict__ Mv, c
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
             const int64_t i = base + (int64_t)u * blockDim.x;
-            const double E = kepler_one<MIXED>(M[u], e[u], fixed, max_iter);
+            const double E = kepler_one<MIXED>(M[u], e[u], fixed, max_iter, tab);
             if (i < n) Ev[i] = E;
         }
     }
