@@ -99,8 +99,8 @@ typedef struct kep_params {
                     eccentricity schedule (2 iterations for e <= 0.8525, 3 up to
                     0.975, 4 up to 0.9955, 5 up to 0.999, then a convergence
                     test), derived offline for a 1e-9 rad worst-case error.
-                    Every KEP_MIXED path except kepler_solve starts a planet
-                    with e <= 0.9 from a tabulated E(e, M) (bilinear, within
+                    Every KEP_MIXED path starts a planet (or a kepler_solve
+                    pair) with e <= 0.9 from a tabulated E(e, M) (bilinear, within
                     2e-3 rad; the tabulated guess of Sec. 5.4) and takes one
                     step: Halley's correction (the second-order member of
                     Danby's family) for e < 0.85 in the kernels that evaluate
