@@ -194,7 +194,7 @@ __host__ __device__ inline size_t gn_obs_lds_per_wave(int sb)
 }
 
 template <int NPL, int NCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gn_obs(DenseArgs a, double *jtwr,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gn_obs(DenseArgs a, double *jtwr,
                                                                                        double *jtwj)
 {
     constexpr int NC = gn_cols<NPL>();       // parameters, offset, residual
