@@ -35,12 +35,35 @@ __device__ __forceinline__ double uniform_double(double x)
     return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
-// Sum over the 64 lanes of a wavefront (butterfly; every lane gets the total).
+// A binary64 value moved across lanes by a DPP pattern (both halves with the same
+// pattern; lanes of rows outside ROWS get 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double x)
+{
+    const int64_t b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (every lane must be active), returned
+// wave-uniform.  Data-parallel moves instead of LDS permutes: pairs (quad_perm
+// 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror) and rows (row_mirror)
+// leave every lane of a row with the row's sum; row_bcast15 adds row 0 into
+// row 1 and row 2 into row 3, row_bcast31 rows 0-1 into row 3, so lane 63
+// holds the total.
 __device__ __forceinline__ double wave_sum(double x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp_f64<0xB1, 0xf>(x);    // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E, 0xf>(x);    // quad_perm [2, 3, 0, 1]
+    x += dpp_f64<0x141, 0xf>(x);   // row_half_mirror
+    x += dpp_f64<0x140, 0xf>(x);   // row_mirror
+    x += dpp_f64<0x142, 0xa>(x);   // row_bcast15 into rows 1 and 3
+    x += dpp_f64<0x143, 0xc>(x);   // row_bcast31 into rows 2 and 3
+    const int64_t b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
 __device__ __forceinline__ float rcp32(float x) { return __builtin_amdgcn_rcpf(x); }
