@@ -110,9 +110,11 @@ __device__ __forceinline__ float start_value(uint32_t w0, uint32_t w1, float twe
 }
 
 // Kepler solve of one lane for kernels whose lanes hold different planets: from
-// the LDS starting-value table at the planet's place and Danby's quartic step
-// (valid in every band; the cheaper Halley step would split the wavefront),
-// else kepler32.  Returns E and sin E, 1 - cos E.
+// the LDS starting-value table at the planet's place and one step, else
+// kepler32.  The step is Halley's when every lane taking the table start has
+// its planet in a Halley band, else Danby's quartic step for all of them (valid
+// in every band), so the choice never splits the wavefront.  Returns E and
+// sin E, 1 - cos E.
 __device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const TabPlace &tp, const uint32_t *tab,
                                                 int niter, int max_iter, bool check, float &sinE, float &omcE)
 {
@@ -121,10 +123,17 @@ __device__ __forceinline__ float kepler32_start(float M, const Ecc32 &k, const T
         const uint32_t *q = tab + tp.toff + start_knot(M, tp.mscale, wm);
         float E = start_value(q[0], q[1], tp.twe, wm, M);
         SinCos32 sc;
-        const float st = danby_step32<false, true>(E, M, k, 0.0f, 0.0f, sc);
-        sinE = sc.s;
-        omcE = sc.omc;
-        rotate32(sinE, omcE, st);
+        if (__all(tp.halley != 0)) {
+            const float d = halley_step32<true>(E, M, k, sc);
+            sinE = sc.s;
+            omcE = sc.omc;
+            rotate32_small(sinE, omcE, d);
+        } else {
+            const float st = danby_step32<false, true>(E, M, k, 0.0f, 0.0f, sc);
+            sinE = sc.s;
+            omcE = sc.omc;
+            rotate32(sinE, omcE, st);
+        }
         return E;
     }
     return kepler32(M, k, niter, max_iter, check, sinE, omcE);
