@@ -90,14 +90,18 @@ __device__ __forceinline__ void load_start_table(uint32_t *dst)
     __syncthreads();
 }
 
-// Knot of |M| and its fraction for mscale = knots / pi: |M| is clamped to pi
-// (binary32 pi, so j <= knots; a NaN clamps there too), so the two words j,
-// j + 1 read after it stay inside the row of knots + 2 words.
+// Knot of |M| and its fraction for mscale = knots / pi.  M is the centred phase
+// (|M| <= binary32 pi, so j <= knots) or NaN; v_cvt_i32_f32 turns a NaN into 0
+// (an IEEE-undefined conversion in C++, hence the instruction itself), so the
+// two words j, j + 1 read after it stay inside the row of knots + 2 words
+// without a clamp.
 __device__ __forceinline__ int start_knot(float M, float mscale, float &wm)
 {
-    const float fj = fminf(fabsf(M), KEP_PI_HI_F) * mscale;
+    const float fj = fabsf(M) * mscale;
     wm = __builtin_amdgcn_fractf(fj);
-    return (int)fj;
+    int j;
+    __asm__("v_cvt_i32_f32 %0, %1" : "=v"(j) : "v"(fj));
+    return j;
 }
 
 // Bilinear starting value from the words of knots j and j + 1 of a row:
