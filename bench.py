@@ -46,9 +46,9 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 #   orbital phase in binary64: (t - t0)/P + phase offset as one fused
 #     multiply-add 1, fraction 1, scale to [-pi, pi) 1, convert 1          4  [4 f64]
 #   starting value at e <= 0.9 (the table of kep_start_tab.h): |M|
-#     clamped and scaled 2, knot index and fraction 2, address 1, two
-#     interpolations in e 2 (binary16 operands widened inside the
-#     multiply-add), one in |M| 2, sign of M 1                             10  [one LDS read]
+#     scaled 1, knot index and fraction 2, address 1, two interpolations
+#     in e 2 (binary16 operands widened inside the multiply-add), one in
+#     |M| 2, sign of M 1                                                     9  [one LDS read]
 #   at e > 0.9 instead: the paper's starting guess 2, and each Danby
 #     step before the last: scale, hardware sin and cos 3, f and its
 #     three derivatives 5, three corrections with one reciprocal 11,
@@ -70,7 +70,7 @@ LANES_PER_CYCLE = {"f32": 32, "f64": 16, "trans": 8}
 # With e ~ U[0, e_max] the planets split into the three kinds by their share of
 # [0, e_max]; beyond the table (0.9 < e <= 0.975 on the eccentricity schedule)
 # a planet takes two steps before the last.
-OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST = 4, 10, 2, 20
+OPS_PHASE, OPS_TABLE, OPS_START, OPS_FAST = 4, 9, 2, 20
 OPS_HALLEY, OPS_LAST, OPS_ROT_SMALL, OPS_ROT = 25, 33, 8, 11
 OPS_VEL, OPS_SUM, OPS_OBS = 5, 2, 6
 F64_PHASE, F64_SUM, F64_OBS = 4, 2, 5

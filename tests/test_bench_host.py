@@ -18,7 +18,7 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
 
 
 def test_operation_count_of_the_mixed_formulation():
-    """phase 4 + table start 10 for the planets inside the table's range (e <= 0.9),
+    """phase 4 + table start 9 for the planets inside the table's range (e <= 0.9),
     else the paper's start 2 and two early steps of 20; last step with its rotation:
     Halley's 25 + 8 in the table's Halley bands (e < 0.85), Danby's quartic 33 + 11
     elsewhere; velocity 5 + binary64 planet sum 2 + 6 per observation shared by 4
@@ -27,7 +27,7 @@ def test_operation_count_of_the_mixed_formulation():
     assert bands[0][0] == 0.0 and bands[-1][1] == 0.9 and [h for _, _, h in bands] == [True, True, False]
     f, early, h = bench.table_fraction(0.9), bench.early_steps(0.9), bench.halley_fraction(0.9)
     assert f == 1.0 and early == 0.0 and abs(h - 0.85 / 0.9) < 1e-12
-    want = 4 + 10 + h * (25 + 8) + (1 - h) * (33 + 11) + 5 + 2 + 6 / 4
+    want = 4 + 9 + h * (25 + 8) + (1 - h) * (33 + 11) + 5 + 2 + 6 / 4
     assert abs(bench.mixed_ops_per_triple(4, f, early, h) - want) < 1e-12
     # beyond the table (e up to 0.975) the count is the schedule's
     assert abs(bench.table_fraction(0.975) - 0.9 / 0.975) < 1e-12
