@@ -6,7 +6,10 @@
 // ... (NCH chunks in registers, streamed in groups beyond 64 NCH), like the
 // dense chi-square kernel: every planet constant is wave-uniform (records in
 // the wavefront's LDS slice, built with the lanes over the systems of a
-// batch), the eccentricity schedule is uniform, nothing goes to scratch.
+// batch), the eccentricity schedule is uniform.  Three wavefronts per SIMD
+// (up to 168 VGPRs): at four the compiler spilled up to 220 bytes per lane,
+// and the spill slots' write-backs tripled the kernel's HBM writes for the
+// same time; at three at most 56 bytes remain (four planets, four chunks).
 // Per group of observations:
 //   pass 1, per planet: binary64 phase, binary32 Kepler solve (table start or
 //     schedule), binary64 correction of E and binary64 velocity (kep_grad.h);
@@ -36,7 +39,7 @@ __host__ __device__ inline size_t adj_table_offset(int wpb, int sb, int npl)
 }
 
 template <int NPL, int NCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_grad_obs(DenseArgs a, int nll)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_grad_obs(DenseArgs a, int nll)
 {
     constexpr int NROW = 5 * NPL + 1;
     constexpr int R = pow2_at_least(NROW);
@@ -50,9 +53,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     uint32_t *tab = reinterpret_cast<uint32_t *>(smem + adj_table_offset(wpb, a.sb, NPL));
     load_start_table(tab);
 
-    const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
-    const int64_t n_waves = (int64_t)gridDim.x * wpb;
-    const int64_t n_batches = (a.n_sys + a.sb - 1) / a.sb;
+    const SysShare share = sys_share<false>(a.n_sys, wpb, wib, a.sb);
     const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
     const bool has_jit = a.jitter != nullptr;
     const int row = lane / SPAN;
@@ -65,24 +66,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
     };
     if (n_groups <= 1) load_group(0);
 
-    for (int64_t bt = gw; bt < n_batches; bt += n_waves) {
-        const int64_t s0 = bt * a.sb;
-        const int nb = (int)min((int64_t)a.sb, a.n_sys - s0);
+    for (int64_t run0 = share.lo; run0 < share.hi; run0 += share.step) {
+        int64_t first;
+        const int nb = share_run(share, run0, a.sb, first);
         wave_sync_lds();
         if (lane < nb) {
-            const int64_t sys = s0 + lane;
+            const int64_t sys = first + (int64_t)share.stride * lane;
             bool ok = isfinite(a.t0);
             if (a.offset) ok = ok && isfinite(a.offset[sys]);
             if (has_jit) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
             sysbad[lane] = ok ? 0 : 1;
         }
         wave_sync_lds();
-        // planet records with the lanes over the batch's (planet, system) pairs,
-        // planet-major (each parameter plane read in one run)
+        // planet records with the lanes over the run's (planet, system) pairs,
+        // planet-major (the block's wavefronts together read whole runs of
+        // every parameter plane)
 #pragma nounroll
         for (int q = lane; q < nb * NPL; q += 64) {
             const int j = q / nb, sq = q - j * nb;
-            const int64_t p = (int64_t)j * a.n_sys + s0 + sq;
+            const int64_t p = (int64_t)j * a.n_sys + first + (int64_t)share.stride * sq;
             RecGrad r;
             if (!grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r)) sysbad[sq] = 1;
             recs[sq * NPL + j] = r;
@@ -90,7 +92,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         wave_sync_lds();
 
         for (int s = 0; s < nb; ++s) {
-            const int64_t sys = s0 + s;
+            const int64_t sys = first + (int64_t)share.stride * s;
             const double gam = a.offset ? a.offset[sys] : 0.0;
             const double jit = has_jit ? a.jitter[sys] : 0.0;
             const float jit2 = (float)(jit * jit);
@@ -220,8 +222,8 @@ hipError_t launch_grad_obs_t(DenseArgs a, bool nll, LaunchShape shape, hipStream
     int64_t sb = (a.n_sys + max_waves - 1) / (max_waves > 0 ? max_waves : 1);
     sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
     a.sb = (int)sb;
-    const int64_t n_batches = (a.n_sys + sb - 1) / sb;
-    int64_t grid = (n_batches + wpb - 1) / wpb;
+    // one block per wpb x sb systems, at most the resident count
+    int64_t grid = (a.n_sys + (int64_t)wpb * sb - 1) / ((int64_t)wpb * sb);
     const int64_t cap = (int64_t)device_cu_count() * per_cu;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;

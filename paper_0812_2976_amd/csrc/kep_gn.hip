@@ -210,9 +210,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     RecGrad *recs = reinterpret_cast<RecGrad *>(mine + (size_t)NC * kGnCol * sizeof(float));
     int *sysbad = reinterpret_cast<int *>(recs + (size_t)a.sb * NPL);
 
-    const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
-    const int64_t n_waves = (int64_t)gridDim.x * wpb;
-    const int64_t n_batches = (a.n_sys + a.sb - 1) / a.sb;
+    const SysShare share = sys_share<true>(a.n_sys, wpb, wib, a.sb);
     const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
     const bool has_jit = a.jitter != nullptr;
     const double nan = __builtin_nan("");
@@ -235,23 +233,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     };
     if (n_groups <= 1) load_group(0);
 
-    for (int64_t bt = gw; bt < n_batches; bt += n_waves) {
-        const int64_t s0 = bt * a.sb;
-        const int nb = (int)min((int64_t)a.sb, a.n_sys - s0);
+    for (int64_t run0 = share.lo; run0 < share.hi; run0 += share.step) {
+        int64_t first;
+        const int nb = share_run(share, run0, a.sb, first);
         wave_sync_lds();
         if (lane < nb) {
-            const int64_t sys = s0 + lane;
+            const int64_t sys = first + (int64_t)share.stride * lane;
             bool ok = isfinite(a.t0);
             if (a.offset) ok = ok && isfinite(a.offset[sys]);
             if (has_jit) ok = ok && isfinite(a.jitter[sys]) && a.jitter[sys] >= 0.0;
             sysbad[lane] = ok ? 0 : 1;
         }
         wave_sync_lds();
-        // planet records with the lanes over the batch's (planet, system) pairs
+        // planet records with the lanes over the run's (planet, system) pairs
 #pragma nounroll
         for (int q = lane; q < nb * NPL; q += 64) {
             const int j = q / nb, sq = q - j * nb;
-            const int64_t p = (int64_t)j * a.n_sys + s0 + sq;
+            const int64_t p = (int64_t)j * a.n_sys + first + (int64_t)share.stride * sq;
             RecGrad r;
             if (!grad_setup_rec(a.fixed_iter, a.P[p], a.K[p], a.e[p], a.w[p], a.M0[p], r)) sysbad[sq] = 1;
             recs[sq * NPL + j] = r;
@@ -259,7 +257,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         wave_sync_lds();
 
         for (int s = 0; s < nb; ++s) {
-            const int64_t sys = s0 + s;
+            const int64_t sys = first + (int64_t)share.stride * s;
             const double gam = a.offset ? a.offset[sys] : 0.0;
             const double jit = has_jit ? a.jitter[sys] : 0.0;
             const float jit2 = (float)(jit * jit);
@@ -397,8 +395,8 @@ hipError_t launch_gn_obs_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape 
     a.sb = (int)sb;
     const size_t lds = (size_t)wpb * gn_obs_lds_per_wave<NPL>(a.sb);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
-    const int64_t n_batches = (a.n_sys + sb - 1) / sb;
-    int64_t grid = (n_batches + wpb - 1) / wpb;
+    // one block per wpb x sb systems, at most the resident count
+    int64_t grid = (a.n_sys + (int64_t)wpb * sb - 1) / ((int64_t)wpb * sb);
     const int64_t cap = (int64_t)device_cu_count() * per_cu;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;

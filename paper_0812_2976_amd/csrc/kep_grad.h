@@ -136,6 +136,52 @@ __device__ __forceinline__ bool grad_setup_rec(int fixed_iter, double P, double 
 // passes of the kernels with the lanes over observations.
 __device__ __forceinline__ void lds_reload_barrier() { __asm__ volatile("" ::: "memory"); }
 
+// System assignment of the kernels with the lanes over observations (one
+// system per wavefront at a time, many output rows per system).  Runs of
+// systems are handed out round-robin, so the whole grid sweeps the batch in
+// order (contiguous shares per wavefront or block, which balance the last
+// runs better, ran 2-7% slower: the grid then writes all over every output
+// row at once).
+//   INTERLEAVE: block b takes runs b, b + G, ... of wpb x sb systems (G blocks);
+//     wavefront w of the block holds systems run + w + wpb i (i < nb), so the
+//     block's wavefronts write neighbouring systems' entries of every output
+//     row at about the same time and the L2 merges them into longer pieces
+//     (with sb consecutive systems per wavefront each row's line stays partly
+//     written for a whole batch and goes back to HBM in pieces).
+//   else: wavefront g of W takes runs g, g + W, ... of sb consecutive systems.
+struct SysShare {
+    int64_t lo, hi;   // first run's start; the number of systems
+    int64_t step;     // systems between a wavefront's runs
+    int stride, off;  // slot i of the run starting at r is system r + off + stride i
+};
+
+template <bool INTERLEAVE>
+__device__ __forceinline__ SysShare sys_share(int64_t n_sys, int wpb, int wib, int sb)
+{
+    SysShare q;
+    q.hi = n_sys;
+    if constexpr (INTERLEAVE) {
+        q.lo = (int64_t)blockIdx.x * wpb * sb;
+        q.step = (int64_t)gridDim.x * wpb * sb;
+        q.stride = wpb;
+        q.off = wib;
+    } else {
+        q.lo = ((int64_t)blockIdx.x * wpb + wib) * sb;
+        q.step = (int64_t)gridDim.x * wpb * sb;
+        q.stride = 1;
+        q.off = 0;
+    }
+    return q;
+}
+
+// Systems of this wavefront in the run starting at r: first + stride i, i < return value.
+__device__ __forceinline__ int share_run(const SysShare &q, int64_t r, int sb, int64_t &first)
+{
+    first = r + q.off;
+    const int64_t left = q.hi - first;
+    return left <= 0 ? 0 : (int)min((int64_t)sb, (left + q.stride - 1) / q.stride);
+}
+
 // One observation of the kernels with the lanes over observations (the mixed
 // adjoint and Gauss-Newton products).
 struct ObsG {
