@@ -371,8 +371,7 @@ __global__ void __launch_bounds__(256) k_grad_f64(DenseArgs a)
 // segmented scan over each group of 64 lanes returns every system's share: a
 // system's last partial group no longer leaves the rest of its wavefront idle.
 // Observations of one unit of a system's whole groups (up to G groups of 64),
-// loaded raw so that the loads of the next unit can be issued before the
-// current one is evaluated.
+// as loaded.
 template <int G>
 struct RawObs {
     double t[G], v[G], s[G];
@@ -460,9 +459,11 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x)
 
 // GMAX: largest observation group in 64-lane chunks (2 or 4): fewer chunks in
 // flight need fewer registers and allow more resident waves; the plan's
-// autotuner picks it.
+// autotuner picks it.  Five wavefronts per SIMD with two chunks (96 VGPRs, 16
+// bytes of scratch), four with four (128 VGPRs, 68 bytes): at c3 the four-chunk
+// form at four wavefronts runs 3% faster than the two-chunk one at four.
 template <int GMAX>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX == 2 ? 4 : 3))) k_ragged_mixed(RaggedArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX == 2 ? 5 : 4))) k_ragged_mixed(RaggedArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = __lane_id();
@@ -570,16 +571,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         }
         wave_sync_lds();
         // whole groups of 64 observations, one system at a time, in units of up to
-        // GMAX groups; the next unit's observations (of this or the next system)
-        // are loaded before the current unit is evaluated, so that the wave does
-        // not wait for global memory at the start of every unit
+        // GMAX groups.  Each unit's observations are loaded when it starts: the
+        // other resident wavefronts cover the wait, and loading the next unit's
+        // ahead (registers for two units) cost a wavefront per SIMD, 3% at c3.
         {
             auto has_units = [&](int q) { return uniform_int(meta[2 * q]) > 0 && uniform_i64(nfl[q]) > 0; };
             int us = 0;
             while (us < nb && !has_units(us)) ++us;
             int64_t ug = 0;
-            RawObs<GMAX> cur, nxt;
-            if (us < nb) load_unit<GMAX>(a, uniform_i64(obs0[us]), uniform_i64(nfl[us]), cur);
+            RawObs<GMAX> cur;
             PolMixed::ChiAcc chi;
             PolMixed::chi_init(chi);
             bool bad_obs = false;
@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                     while (ns < nb && !has_units(ns)) ++ns;
                     ng = 0;
                 }
-                if (ns < nb) load_unit<GMAX>(a, uniform_i64(obs0[ns]) + ng, uniform_i64(nfl[ns]) - ng, nxt);
+                load_unit<GMAX>(a, uniform_i64(obs0[us]) + ug, nf - ug, cur);
                 const int64_t left = nf - ug;
                 const int code = uniform_int(meta[2 * us]);
                 const double gam = gj[2 * us], jit = gj[2 * us + 1];
@@ -614,7 +614,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 }
                 us = ns;
                 ug = ng;
-                cur = nxt;
             }
         }
         wave_sync_lds();
