@@ -218,6 +218,12 @@ def time_oracle(fn, n, cores):
     return time.perf_counter() - t0
 
 
+# Launches of the secondary rows: timed after a warm-up long enough for the
+# shader clock to settle, and HIP graphs after more, since a graph's first
+# replays (about 25 here) run slower than its later ones.
+ROW_STEPS, ROW_WARMUP, GRAPH_WARMUP = 20, 10, 30
+
+
 def timed(fn, steps, warmup, torch):
     """Mean milliseconds per call of fn over `steps` calls after `warmup` calls."""
     for _ in range(warmup):
@@ -266,7 +272,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--rows", default="fp64,separate,grad,ragged,demc,astro,kepler",
                     help="extra paths to time (comma list or 'none')")
@@ -367,7 +373,7 @@ def main():
         o1 = torch.empty(w1.n_sys, dtype=torch.float64, device=dev)
         ms64, _ = timed(lambda: kp.rv_chisq(**g1, prec="fp64", out=o1), 3, 1, torch)
         ms64e, _ = timed(lambda: kp.rv_chisq(**g1, prec="fp64", out=o1, opts=dict(fixed_iter=-1)), 5, 1, torch)
-        msm1, _ = timed(lambda: kp.rv_chisq(**g1, prec="mixed", out=o1), 10, 2, torch)
+        msm1, _ = timed(lambda: kp.rv_chisq(**g1, prec="mixed", out=o1), ROW_STEPS, ROW_WARMUP, torch)
         r64 = w1.n_sys / (ms64 * 1e-3)
         result["fp64_gpu"] = {"workload": "c1 n_sys=65536 n_pl=4 n_obs=256", "chi2_per_s": r64,
                               "kepler_solves_per_s": r64 * 1024, "launch_ms": ms64,
@@ -396,7 +402,7 @@ def main():
         o2 = torch.empty(wl.n_sys, dtype=torch.float64, device=dev)
         msa, _ = timed(lambda: kp.rv_planet_velocities(g2["t"], g2["P"], g2["K"], g2["e"], g2["omega"], g2["M0"],
                                                        out=dv), 5, 1, torch)
-        msb, _ = timed(lambda: kp.rv_chisq_from_velocities(g2["t"], g2["v"], g2["sigma"], dv, out=o2), 10, 2, torch)
+        msb, _ = timed(lambda: kp.rv_chisq_from_velocities(g2["t"], g2["v"], g2["sigma"], dv, out=o2), ROW_STEPS, ROW_WARMUP, torch)
         dv_bytes = dv.numel() * 4
         # Kepler's equation only: every eccentric anomaly written (into the same buffer)
         mse, _ = timed(lambda: kp.rv_eccentric_anomalies(g2["t"], g2["P"], g2["K"], g2["e"], g2["omega"], g2["M0"],
@@ -419,14 +425,14 @@ def main():
                   omega=gpu(w4.w), M0=gpu(w4.M0), offset=gpu(w4.offset), t0=w4.t0)
         o4 = torch.empty(w4.n_sys, dtype=torch.float64, device=dev)
         gr = torch.empty((5 * w4.n_pl + 1, w4.n_sys), dtype=torch.float64, device=dev)
-        msg, _ = timed(lambda: kp.rv_chisq_grad(**g4, prec="mixed", out=o4, grad=gr), 10, 2, torch)
+        msg, _ = timed(lambda: kp.rv_chisq_grad(**g4, prec="mixed", out=o4, grad=gr), ROW_STEPS, ROW_WARMUP, torch)
         gn = torch.empty((5 * w4.n_pl + 2, w4.n_sys), dtype=torch.float64, device=dev)
         jit = gpu(w4.jitter)
-        msn, _ = timed(lambda: kp.rv_nll_grad(**g4, jitter=jit, prec="mixed", out=o4, grad=gn), 10, 2, torch)
+        msn, _ = timed(lambda: kp.rv_nll_grad(**g4, jitter=jit, prec="mixed", out=o4, grad=gn), ROW_STEPS, ROW_WARMUP, torch)
         npar = 5 * w4.n_pl + 1
         jr = torch.empty((npar, w4.n_sys), dtype=torch.float64, device=dev)
         jj = torch.empty((npar * (npar + 1) // 2, w4.n_sys), dtype=torch.float64, device=dev)
-        msgn, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="mixed", out=o4, jtwr=jr, jtwj=jj), 10, 2, torch)
+        msgn, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="mixed", out=o4, jtwr=jr, jtwj=jj), ROW_STEPS, ROW_WARMUP, torch)
         msgn64, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="fp64", out=o4, jtwr=jr, jtwj=jj), 3, 1, torch)
         # Gram matrix of sqrt(w)[J | 1 | r]: (np + 1)(np + 2)/2 multiply-adds per (system, observation)
         useful = w4.n_sys * w4.t.size * (npar + 1) * (npar + 2)
@@ -487,7 +493,8 @@ def main():
         plan = kp.RaggedPlan(gpu(rw.t), gpu(rw.v), gpu(rw.sigma), gpu(rw.obs_off), gpu(rw.P), gpu(rw.K),
                              gpu(rw.e), gpu(rw.w), gpu(rw.M0), gpu(rw.pl_off), t0=rw.t0)
         o3 = torch.empty(rw.n_sys, dtype=torch.float64, device=dev)
-        msr, _ = timed(lambda: plan(o3), 10, 2, torch)
+        msr, _ = timed(lambda: plan(o3), ROW_STEPS, GRAPH_WARMUP, torch)
+        msr_direct, _ = timed(lambda: plan.direct(o3), ROW_STEPS, ROW_WARMUP, torch)
         info = plan.info()
         # the formulation's operations summed over the batch: every triple as in the
         # dense count, the per-observation work once per observation of each system
@@ -500,6 +507,7 @@ def main():
         cls3 = {c: core[c] + (F64_OBS if c == "f64" else (OPS_OBS - F64_OBS if c == "f32" else 0)) * obs3 / tri3
                 for c in core}
         result["ragged_c3"] = {"chi2_per_s": rw.n_sys / (msr * 1e-3), "launch_ms": msr,
+                               "direct_launch_ms": msr_direct,
                                "kepler_solves_per_s": info["triples"] / (msr * 1e-3), "triples": info["triples"],
                                "roofline": roofline_entry(f"k_ragged_mixed<{info['group_chunks']}>", cls3, tri3, msr,
                                                           recorded_traffic("rv_chisq_ragged_c3")),
@@ -550,14 +558,14 @@ def main():
                 s.generations(gen[0], ng)
                 gen[0] += ng
 
-            ms_g, _ = timed(graph_step, 5, 1, torch)
-            ms_d, _ = timed(direct_step, 5, 1, torch)
+            ms_g, _ = timed(graph_step, 10, GRAPH_WARMUP // 2, torch)
+            ms_d, _ = timed(direct_step, 10, GRAPH_WARMUP // 2, torch)
             # the chi-square launch of one half alone, for the share of a generation it takes
             half = {k: gpu(np.ascontiguousarray(x0[0, a * 4:(a + 1) * 4])) for a, k in
                     enumerate(("P", "K", "e", "omega", "M0"))}
             obs = dict(t=gpu(w1.t), v=gpu(w1.v), sigma=gpu(w1.sigma), t0=w1.t0)
             oh = torch.empty(nh, dtype=torch.float64, device=dev)
-            ms_c, _ = timed(lambda: kp.rv_chisq(**obs, **half, prec="mixed", out=oh), 10, 2, torch)
+            ms_c, _ = timed(lambda: kp.rv_chisq(**obs, **half, prec="mixed", out=oh), ROW_STEPS, ROW_WARMUP, torch)
             acc = s.n_accept.sum().item() / (2 * nh * gen[0])
             best = min(ms_g, ms_d)
             demc[f"chains_{2 * nh}"] = {
@@ -582,7 +590,7 @@ def main():
                   e=gpu(wa.e), M0=gpu(wa.M0), A=gpu(wa.A), B=gpu(wa.B), F=gpu(wa.F), G=gpu(wa.G), x0=gpu(wa.x0),
                   y0=gpu(wa.y0), t0=wa.t0)
         oa = torch.empty(wa.n_sys, dtype=torch.float64, device=dev)
-        msa, _ = timed(lambda: kp.astro_chisq(**ga, prec="mixed", out=oa), 10, 2, torch)
+        msa, _ = timed(lambda: kp.astro_chisq(**ga, prec="mixed", out=oa), ROW_STEPS, ROW_WARMUP, torch)
         ms64, _ = timed(lambda: kp.astro_chisq(**ga, prec="fp64", out=oa), 3, 1, torch)
         ms64e, _ = timed(lambda: kp.astro_chisq(**ga, prec="fp64", out=oa, opts={"fixed_iter": -1}), 3, 1, torch)
         tri = wa.n_sys * wa.n_pl * wa.t.size
@@ -599,7 +607,7 @@ def main():
         M, e = synth.kepler_pairs(1 << 26)
         Mg, eg = gpu(M), gpu(e)
         Eg = torch.empty_like(Mg)
-        msk, _ = timed(lambda: kp.kepler_solve(Mg, eg, prec="mixed", out=Eg), 10, 2, torch)
+        msk, _ = timed(lambda: kp.kepler_solve(Mg, eg, prec="mixed", out=Eg), ROW_STEPS, ROW_WARMUP, torch)
         msk64, _ = timed(lambda: kp.kepler_solve(Mg, eg, prec="fp64", out=Eg), 3, 1, torch)
         n = M.size
         result["kepler_solve"] = {"n": n, "mixed_solves_per_s": n / (msk * 1e-3), "mixed_launch_ms": msk,
