@@ -37,7 +37,7 @@ struct RaggedArgs {
     int64_t n_items;          // number of work items = ceil(n_sys / sb)
     int sb;                   // systems per work item
     int gmax;                 // largest observation group, in 64-lane chunks (2 or 4)
-    unsigned int *queue;      // kQueueWords counters (kRaggedQueues work queues, waves done); zero at
+    unsigned int *queue;      // kQueueWords counters (kRaggedQueues work queues, blocks done); zero at
                               // launch, and the kernel leaves them zero
     double *out;
     int fixed_iter, max_iter;
@@ -47,10 +47,10 @@ struct RaggedArgs {
 // Work queues of the persistent ragged kernel: one counter per XCD (blocks go
 // to the XCDs round-robin), each on its own 128-byte line, queue q handing out
 // items q, q + kRaggedQueues, ...; a wave drains its own XCD's queue first,
-// then the others.  The waves-done counter follows the queues.
+// then the others.  The blocks-done counter follows the queues.
 constexpr int kRaggedQueues = 8;
 constexpr int kQueueStride = 32;                              // words between counters
-constexpr int kQueueDone = kRaggedQueues * kQueueStride;      // index of the waves-done counter
+constexpr int kQueueDone = kRaggedQueues * kQueueStride;      // index of the blocks-done counter
 constexpr int kQueueWords = kQueueDone + 1;
 
 // Astrometric batch (Thiele-Innes form): epochs t with measured offsets x
