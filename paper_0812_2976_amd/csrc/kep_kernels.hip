@@ -1042,8 +1042,9 @@ static size_t ragged_lds(int block, int sb)
 }
 
 // The block's LDS is the waves' dynamic slices plus the static copy of the
-// Kepler starting-value table.
-bool ragged_shape_fits(int block, int sb) { return ragged_lds(block, sb) + sizeof(kep_start_tab) <= 64 * 1024; }
+// Kepler starting-value table and the block's two queue words (16 bytes
+// allowed for them and their alignment).
+bool ragged_shape_fits(int block, int sb) { return ragged_lds(block, sb) + sizeof(kep_start_tab) + 16 <= 64 * 1024; }
 
 int ragged_max_grid(LaunchShape shape, int sb, int gmax)
 {
