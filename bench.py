@@ -127,11 +127,21 @@ DENSE_FILES = ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h"
 ADJOINT_FILES = ("kep_adjoint.hip", "kep_grad.h", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_start_tab.h")
 
 
+_CODE_TOKENS = re.compile(r'//[^\n]*|/\*.*?\*/|"(?:\\.|[^"\\])*"|\S+', re.S)
+
+
+def code_tokens(text):
+    """The source's tokens with comments dropped (string literals kept whole), so
+    that an edit of comments or layout leaves the hash unchanged."""
+    return [t for t in _CODE_TOKENS.findall(text) if not t.startswith(("//", "/*"))]
+
+
 def kernel_source_hash(files=DENSE_FILES):
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_0812_2976_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(" ".join(code_tokens(fh.read())).encode())
+            h.update(b"\0")
     return h.hexdigest()[:16]
 
 

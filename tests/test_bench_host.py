@@ -77,3 +77,13 @@ def test_adjoint_op_count_and_roofline_entry():
     e = bench.roofline_entry("k", c4, 1000, 1.0)
     assert abs(e["achieved"] - sum(c4.values()) * 1000 / 1e-3 / 1e12) < 1e-3
     assert abs(e["frac"] - e["achieved"] / e["peak"]) < 1e-3 and e["bound"] == "alu"
+
+
+def test_source_hash_ignores_comments_and_layout_only():
+    code = 'int f(int x) {\n    return x + 1;   // one more\n}\n/* block */ const char *s = "a // b";\n'
+    same = 'int f(int x)\n{ return x + 1;   // ONE MORE, reworded\n}\n/* other\n block */ const char *s = "a // b";\n'
+    other = 'int f(int x) {\n    return x + 2;   // one more\n}\n/* block */ const char *s = "a // b";\n'
+    lit = 'int f(int x) {\n    return x + 1;   // one more\n}\n/* block */ const char *s = "a // c";\n'
+    assert bench.code_tokens(code) == bench.code_tokens(same)
+    assert bench.code_tokens(code) != bench.code_tokens(other)
+    assert bench.code_tokens(code) != bench.code_tokens(lit)
