@@ -121,6 +121,23 @@ def early_steps(e_max, s3=0.975):
     return 2.0 * max(0.0, min(e_max, s3) - start_table_bands()[-1][1]) / e_max
 
 
+def op_fractions(e):
+    """(f_table, early, f_halley) of mixed_ops_per_triple for the given planets'
+    eccentricities: inside the table's bands one step (Halley's on its rows), beyond
+    it the eccentricity schedule's steps before the last (2 to e = 0.975, 3 to 0.9955,
+    4 to 0.999, 5 above)."""
+    e = np.asarray(e, dtype=np.float64).ravel()
+    bands = start_table_bands()
+    in_tab = e <= bands[-1][1]
+    halley = np.zeros(e.shape, dtype=bool)
+    for e0, e1, h in bands:
+        if h:
+            halley |= (e >= e0) & (e < e1)
+    steps = np.select([e <= 0.975, e <= 0.9955, e <= 0.999], [2.0, 3.0, 4.0], 5.0)
+    early = np.where(in_tab, 0.0, steps)
+    return float(in_tab.mean()), float(early.mean()), float((halley & in_tab).mean())
+
+
 # The sources each timed kernel is compiled from (its counter summaries under
 # profiles/ record their hash; a summary taken on other sources is not used).
 DENSE_FILES = ("kep_kernels.hip", "kep_policy.h", "kep_device.h", "kep_tables.h", "kep_start_tab.h", "kep_grad.h")
@@ -208,6 +225,15 @@ def roofline_entry(kernel, classes, units, ms, traffic=None, unit_name="triple")
             f"ops_per_{unit_name}": round(per_unit, 2),
             f"ops_per_{unit_name}_by_class": {c: round(n, 3) for c, n in classes.items()},
             "units_per_launch": units, "launch_ms": round(ms, 4)}
+
+
+def hbm_roofline(kernel, bytes_per_launch, ms, basis):
+    """The HBM roofline of a streaming kernel: algorithmic bytes of one launch over its
+    mean launch time, against the 8 TB/s of MI355X's HBM3E."""
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": kernel,
+            "bytes_per_launch": int(bytes_per_launch), "bytes_basis": basis, "launch_ms": round(ms, 4)}
 
 
 def cpu_threads():
@@ -411,17 +437,25 @@ def main():
         dv = torch.empty((wl.n_pl, wl.n_sys, wl.n_obs), dtype=torch.float32, device=dev)
         o2 = torch.empty(wl.n_sys, dtype=torch.float64, device=dev)
         msa, _ = timed(lambda: kp.rv_planet_velocities(g2["t"], g2["P"], g2["K"], g2["e"], g2["omega"], g2["M0"],
-                                                       out=dv), 5, 1, torch)
+                                                       out=dv), ROW_STEPS, ROW_WARMUP, torch)
         msb, _ = timed(lambda: kp.rv_chisq_from_velocities(g2["t"], g2["v"], g2["sigma"], dv, out=o2), ROW_STEPS, ROW_WARMUP, torch)
         dv_bytes = dv.numel() * 4
         # Kepler's equation only: every eccentric anomaly written (into the same buffer)
         mse, _ = timed(lambda: kp.rv_eccentric_anomalies(g2["t"], g2["P"], g2["K"], g2["e"], g2["omega"], g2["M0"],
-                                                         out=dv), 5, 1, torch)
+                                                         out=dv), ROW_STEPS, ROW_WARMUP, torch)
         result["separate_c2"] = {"chi2_per_s": wl.n_sys / ((msa + msb) * 1e-3), "velocities_ms": msa,
                                  "chisq_ms": msb, "intermediate_GB": dv_bytes / 1e9,
                                  "chisq_hbm_GBps": (dv_bytes + wl.n_sys * 8) / (msb * 1e-3) / 1e9,
                                  "time_vs_fused": (msa + msb) / ms,
+                                 "roofline_chisq": hbm_roofline(
+                                     "k_chisq_from_dv<4>", dv_bytes + wl.n_sys * 8, msb,
+                                     "binary32 velocities read (n_pl x n_sys x n_obs x 4 B) + chi-square out 8 B per "
+                                     "system"),
                                  "kepler_only": {"launch_ms": mse, "solves_per_s": dv.numel() / (mse * 1e-3),
+                                                 "roofline": hbm_roofline(
+                                                     "k_dense<PolMixed,4,3>", dv_bytes + wl.n_sys * wl.n_pl * 40, mse,
+                                                     "binary32 E written (n_pl x n_sys x n_obs x 4 B) + parameters "
+                                                     "40 B per planet read"),
                                                  "written_GB": dv_bytes / 1e9,
                                                  "hbm_write_GBps": dv_bytes / (mse * 1e-3) / 1e9,
                                                  "time_vs_fused_chisq": mse / ms}}
@@ -578,10 +612,16 @@ def main():
             ms_c, _ = timed(lambda: kp.rv_chisq(**obs, **half, prec="mixed", out=oh), ROW_STEPS, ROW_WARMUP, torch)
             acc = s.n_accept.sum().item() / (2 * nh * gen[0])
             best = min(ms_g, ms_d)
+            tri_gen = 2 * nh * w1.n_pl * w1.t.size
             demc[f"chains_{2 * nh}"] = {
                 "generations_per_s_graph": ng / (ms_g * 1e-3), "generations_per_s_direct": ng / (ms_d * 1e-3),
                 "proposals_per_s": 2 * nh * ng / (best * 1e-3), "generation_ms": best / ng,
-                "two_rv_chisq_calls_ms": 2 * ms_c, "acceptance": acc}
+                "two_rv_chisq_calls_ms": 2 * ms_c, "acceptance": acc,
+                # the chi-square part only (the dense formulation per triple); the
+                # proposal draws and the acceptance are not counted
+                "roofline": roofline_entry(f"k_demc_half<PolMixed,{(w1.t.size + 63) // 64}>",
+                                           mixed_op_classes(w1.n_pl, *op_fractions(
+                                               x0[:, 2 * w1.n_pl:3 * w1.n_pl, :])), tri_gen, best / ng)}
             s.close()
             del s, half, obs, oh
         result["demc_c1"] = demc
@@ -622,6 +662,8 @@ def main():
         n = M.size
         result["kepler_solve"] = {"n": n, "mixed_solves_per_s": n / (msk * 1e-3), "mixed_launch_ms": msk,
                                   "mixed_hbm_GBps": 24 * n / (msk * 1e-3) / 1e9,
+                                  "roofline": hbm_roofline("k_kepler<true,4>", 24 * n, msk,
+                                                           "M and e read, E written: 8 B each per pair"),
                                   "fp64_solves_per_s": n / (msk64 * 1e-3), "fp64_launch_ms": msk64}
         del Mg, eg, Eg
 

@@ -87,3 +87,19 @@ def test_source_hash_ignores_comments_and_layout_only():
     assert bench.code_tokens(code) == bench.code_tokens(same)
     assert bench.code_tokens(code) != bench.code_tokens(other)
     assert bench.code_tokens(code) != bench.code_tokens(lit)
+
+
+def test_op_fractions_match_the_uniform_closed_forms():
+    import numpy as np
+    for e_max in (0.8, 0.9, 0.975):
+        e = np.random.default_rng(7).uniform(0.0, e_max, 400_000)
+        f_tab, early, f_hal = bench.op_fractions(e)
+        assert abs(f_tab - bench.table_fraction(e_max)) < 5e-3
+        assert abs(early - bench.early_steps(e_max)) < 1e-2
+        assert abs(f_hal - bench.halley_fraction(e_max)) < 5e-3
+
+
+def test_hbm_roofline_entry():
+    r = bench.hbm_roofline("k", 4.0e9, 1.0, "basis")
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert abs(r["achieved"] - 4000.0) < 1e-6 and abs(r["frac"] - 0.5) < 1e-9
