@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kep_device.h"
+#include "kep_grad.h"
 #include "kep_internal.h"
 #include "kep_policy.h"
 
@@ -71,9 +72,10 @@ __device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int
     const double u = __builtin_amdgcn_fract(__builtin_amdgcn_fract(q) + r.ph.m0h);
     const double M = fma(u, kTwoPi, -kPi);
     float s32, omc32;
-    const double E0 = (double)kepler32_start((float)M, r.k, r.tp, tab, r.niter, max_iter, r.check != 0, s32, omc32);
+    const float E32 = kepler32_start((float)M, r.k, r.tp, tab, r.niter, max_iter, r.check != 0, s32, omc32);
+    const double E0 = (double)E32;
     double s, c;
-    sincos_reduced(E0, s, c);
+    sincos_root64<true>(E32, s, c);     // reduced by quadrants: shorter series than sincos_reduced's
     const double d = -(E0 - r.e * s - M) / (1.0 - r.e * c);
     const double hd2 = 0.5 * d * d;
     cE = c - d * s - hd2 * c;

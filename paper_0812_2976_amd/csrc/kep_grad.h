@@ -55,8 +55,13 @@ __device__ __forceinline__ bool grad_setup(double P, double K, double e, double 
 // centred mean anomaly, a little more after a caller-fixed step count):
 // E = y + n pi/2 with n the nearest integer to 2E/pi and pi/2 in two parts,
 // each product taken inside a fused multiply-add, then the Taylor series of
-// sin y to y^13 and of cos y to y^14 on |y| <= pi/4 (remainders below
-// 2.1e-14 and 1.1e-15; coefficients 1/n!), rotated by the quadrant n mod 4.
+// sin y and cos y on |y| <= pi/4 (coefficients 1/n!), rotated by the quadrant
+// n mod 4.  FULL = false: sin to y^13 and cos to y^14 (remainders below 2.1e-14
+// and 1.1e-15; after the rotation either of sin E and cos E may carry the
+// first: enough for the adjoint's binary32 derivative terms); FULL = true: sin
+// to y^17 and cos to y^18 (remainders below 8.4e-20 and 3.3e-21: a binary64
+// result to its last bits, for the astrometric positions).
+template <bool FULL = false>
 __device__ __forceinline__ void sincos_root64(float E, double &s, double &c)
 {
     const float nf = rintf(E * 0.636619772f);
@@ -64,20 +69,31 @@ __device__ __forceinline__ void sincos_root64(float E, double &s, double &c)
     const double dn = (double)nf;
     const double y = fma(-dn, 6.123233995736766036e-17, fma(-dn, 1.5707963267948965580, (double)E));
     const double y2 = y * y;
-    double ps = 1.0 / 6227020800.0;                 // 1/13!
-    ps = fma(ps, y2, -1.0 / 39916800.0);            // 1/11!
-    ps = fma(ps, y2, 1.0 / 362880.0);               // 1/9!
-    ps = fma(ps, y2, -1.0 / 5040.0);                // 1/7!
-    ps = fma(ps, y2, 1.0 / 120.0);                  // 1/5!
-    ps = fma(ps, y2, -1.0 / 6.0);                   // 1/3!
+    double ps, pc;
+    if constexpr (FULL) {
+        ps = 1.0 / 355687428096000.0;                // 1/17!
+        ps = fma(ps, y2, -1.0 / 1307674368000.0);    // 1/15!
+        ps = fma(ps, y2, 1.0 / 6227020800.0);        // 1/13!
+        pc = -1.0 / 6402373705728000.0;              // 1/18!
+        pc = fma(pc, y2, 1.0 / 20922789888000.0);    // 1/16!
+        pc = fma(pc, y2, -1.0 / 87178291200.0);      // 1/14!
+        pc = fma(pc, y2, 1.0 / 479001600.0);         // 1/12!
+    } else {
+        ps = 1.0 / 6227020800.0;                     // 1/13!
+        pc = -1.0 / 87178291200.0;                   // 1/14!
+        pc = fma(pc, y2, 1.0 / 479001600.0);         // 1/12!
+    }
+    ps = fma(ps, y2, -1.0 / 39916800.0);             // 1/11!
+    ps = fma(ps, y2, 1.0 / 362880.0);                // 1/9!
+    ps = fma(ps, y2, -1.0 / 5040.0);                 // 1/7!
+    ps = fma(ps, y2, 1.0 / 120.0);                   // 1/5!
+    ps = fma(ps, y2, -1.0 / 6.0);                    // 1/3!
     const double sy = fma(y * y2, ps, y);
-    double pc = -1.0 / 87178291200.0;               // 1/14!
-    pc = fma(pc, y2, 1.0 / 479001600.0);            // 1/12!
-    pc = fma(pc, y2, -1.0 / 3628800.0);             // 1/10!
-    pc = fma(pc, y2, 1.0 / 40320.0);                // 1/8!
-    pc = fma(pc, y2, -1.0 / 720.0);                 // 1/6!
-    pc = fma(pc, y2, 1.0 / 24.0);                   // 1/4!
-    pc = fma(pc, y2, -0.5);                         // 1/2!
+    pc = fma(pc, y2, -1.0 / 3628800.0);              // 1/10!
+    pc = fma(pc, y2, 1.0 / 40320.0);                 // 1/8!
+    pc = fma(pc, y2, -1.0 / 720.0);                  // 1/6!
+    pc = fma(pc, y2, 1.0 / 24.0);                    // 1/4!
+    pc = fma(pc, y2, -0.5);                          // 1/2!
     const double cy = fma(y2, pc, 1.0);
     // quadrant q = n mod 4: (sin, cos) = (sy, cy), (cy, -sy), (-sy, -cy), (-cy, sy)
     const int q = n & 3;
