@@ -8,9 +8,10 @@
 // over the observations, so it runs on MFMA: each lane (one observation)
 // forms its row of the augmented matrix sqrt(w) [J | 1 | r] from the
 // implicit-function derivative terms of the adjoint (kep_grad.h) and stores it
-// in the wavefront's slice of LDS; the wavefront then accumulates the
-// upper-triangular 16 x 16 blocks of its Gram matrix, four observations per
-// product.  The augmented column gives J^T W r and chi2 from the same products.
+// in the wavefront's slice of LDS; the wavefront then accumulates 16 x 16
+// blocks that cover the upper triangle of its Gram matrix, four observations
+// per product.  The augmented column gives J^T W r and chi2 from the same
+// products.
 //
 // binary64 path (k_gn64): rows in binary64, v_mfma_f64_16x16x4_f64.
 // Mixed path (k_gn_obs): rows in binary32 (the derivative terms are binary32
@@ -178,8 +179,19 @@ __global__ void __launch_bounds__(256) k_gn64(DenseArgs a, double *jtwr, double 
 // Observation 16 g + 4 s + u of the chunk feeds step u of lane group g = l/16
 // in the s-th run: the Gram matrix sums over all observations, so any fixed
 // assignment of observations to (step, k) slots, the same for both operands,
-// gives the same products.  Only the 5 n_pl + 2 live columns are stored; the
-// operands of the padding columns are zeros.
+// gives the same products.  Only the 5 n_pl + 2 live columns are stored.  An
+// operand lane past the live columns reads some live column instead: output
+// row i of a product depends only on row i of its first operand and output
+// column j only on column j of its second, so such lanes change nothing but
+// entries that are never stored.
+//
+// Block products per step of four observations: every pair of 16-column
+// blocks, except for 17 to 24 columns (three or four planets), where two
+// products cover the upper triangle: with the columns in groups
+// X = [0, g), Y = [g, g + 8), Z = [g + 8, NC), g = NC - 16, the product of the
+// operands X+Y (rows) and X+Z (columns) holds the pairs XX, XY, XZ and YZ, and
+// the square of Y+Z holds YY and ZZ (against three products for two blocks;
+// NC <= 24 makes each operand at most 16 columns).
 constexpr int kGnCol = 68;   // 64 observations + 4: consecutive columns start 4 banks apart
 
 template <int NPL>
@@ -200,7 +212,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     constexpr int NC = gn_cols<NPL>();       // parameters, offset, residual
     constexpr int NP = NC - 1;               // parameters and offset
     constexpr int NB = (NC + 15) / 16;       // 16-column blocks
-    constexpr int NPAIR = NB * (NB + 1) / 2;
+    constexpr bool TWO = NC > 16 && NC <= 24;
+    constexpr int GX = NC - 16;              // TWO: group X = [0, GX), Y = [GX, GX + 8), Z = [GX + 8, NC)
+    constexpr int NOP = TWO ? 3 : NB;        // operand column sets (TWO: X+Y, X+Z, Y+Z)
+    constexpr int NPAIR = TWO ? 2 : NB * (NB + 1) / 2;   // products per step
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = __lane_id();
     const int wpb = blockDim.x >> 6;
@@ -215,15 +230,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const bool has_jit = a.jitter != nullptr;
     const double nan = __builtin_nan("");
     float *col = T + lane;                   // this lane's observation in column 0
-    // operand columns of this lane: 16 b + l%16 in block b (clamped into the tile;
-    // zeros beyond the live columns)
-    const float *src[NB];
-    bool live[NB];
+    // operand columns of this lane, li = l%16: 16 b + li in block b, or with TWO
+    // li (X+Y), li or li + 8 (X+Z) and GX + li (Y+Z); lanes past the live
+    // columns read a live one
+    const int li = lane & 15;
+    const float *src[NOP];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int c = 16 * b + (lane & 15);
-        live[b] = c < NC;
-        src[b] = T + (live[b] ? c : NC - 1) * kGnCol + 16 * (lane >> 4);
+    for (int b = 0; b < NOP; ++b) {
+        int c;
+        if constexpr (TWO) c = b == 0 ? li : b == 1 ? (li < GX ? li : (li + 8 < NC ? li + 8 : li)) : GX + li;
+        else c = 16 * b + li < NC ? 16 * b + li : NC - 1;
+        src[b] = T + c * kGnCol + 16 * (lane >> 4);
     }
 
     ObsG o[NCH];
@@ -331,22 +348,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     for (int p = 0; p < NPAIR; ++p) accf[p] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int s4 = 0; s4 < 4; ++s4) {
-                        f4 av[NB];
+                        f4 av[NOP];
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) {
-                            const f4 v = *reinterpret_cast<const f4 *>(src[b] + 4 * s4);
-                            av[b] = live[b] ? v : f4{0.0f, 0.0f, 0.0f, 0.0f};
-                        }
+                        for (int b = 0; b < NOP; ++b) av[b] = *reinterpret_cast<const f4 *>(src[b] + 4 * s4);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            int p = 0;
+                            if constexpr (TWO) {
+                                accf[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][u], av[1][u], accf[0], 0, 0, 0);
+                                accf[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][u], av[2][u], accf[1], 0, 0, 0);
+                            } else {
+                                int p = 0;
 #pragma unroll
-                            for (int bi = 0; bi < NB; ++bi) {
+                                for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
-                                for (int bj = bi; bj < NB; ++bj) {
-                                    accf[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi][u], av[bj][u], accf[p], 0,
-                                                                                    0, 0);
-                                    ++p;
+                                    for (int bj = bi; bj < NB; ++bj) {
+                                        accf[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bi][u], av[bj][u], accf[p],
+                                                                                        0, 0, 0);
+                                        ++p;
+                                    }
                                 }
                             }
                         }
@@ -359,18 +378,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 }
             }
             const bool ok = !sbad && !__any(bad_obs);
-            // lane l holds entry (16 bi + 4 (l/16) + q, 16 bj + l%16) of block (bi, bj) in acc[.][q]
+            // lane l holds entry (4 (l/16) + q, l%16) of each product in acc[.][q]
             // (the binary32 16x16x4 product keeps four consecutive output rows per lane)
-            int p = 0;
+            if constexpr (TWO) {
 #pragma unroll
-            for (int bi = 0; bi < NB; ++bi) {
+                for (int q = 0; q < 4; ++q) {
+                    const int i = 4 * (lane >> 4) + q;
+                    // X+Y by X+Z: XX (upper triangle), YX (as XY), XZ and YZ
+                    const int c = li < GX ? li : li + 8;
+                    if (i < GX + 8 && li < GX + 8 && !(i < GX && c < GX && i > c))
+                        gn_store(a, jtwr, jtwj, sys, NP, i < c ? i : c, i < c ? c : i, ok ? acc[0][q] : nan);
+                    // Y+Z squared: YY and ZZ (upper triangles; YZ came from the first)
+                    const int p2 = GX + i, c2 = GX + li;
+                    if (p2 <= c2 && !(p2 < GX + 8 && c2 >= GX + 8))
+                        gn_store(a, jtwr, jtwj, sys, NP, p2, c2, ok ? acc[1][q] : nan);
+                }
+            } else {
+                int p = 0;
 #pragma unroll
-                for (int bj = bi; bj < NB; ++bj) {
+                for (int bi = 0; bi < NB; ++bi) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        gn_store(a, jtwr, jtwj, sys, NP, 16 * bi + 4 * (lane >> 4) + q, 16 * bj + (lane & 15),
-                                 ok ? acc[p][q] : nan);
-                    ++p;
+                    for (int bj = bi; bj < NB; ++bj) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            gn_store(a, jtwr, jtwj, sys, NP, 16 * bi + 4 * (lane >> 4) + q, 16 * bj + li,
+                                     ok ? acc[p][q] : nan);
+                        ++p;
+                    }
                 }
             }
         }

@@ -6,8 +6,9 @@ Cauchy-Schwarz scale sqrt(C_aa C_bb) (the largest |C_ab| can be):
   binary64: 1e-9; mixed (binary32 derivative terms, as rv_chisq_grad): 1e-5.
 J^T W r within the same normalised bounds against sqrt(C_aa chi2); chi2 as
 rv_chisq (binary64 relative 1e-12, mixed 1e-5).  Sizes cover one, two and three
-16-column blocks (n_pl = 1, 2..6, 7..8) and observation counts that are not
-multiples of 64.
+16-column blocks (n_pl = 1..2, 3..6, 7..8; in mixed precision the two-product
+cover of 17 to 24 columns at n_pl = 3, 4 and all three block products at
+n_pl = 5, 6) and observation counts that are not multiples of 64.
 """
 import numpy as np
 import pytest
@@ -44,6 +45,8 @@ def _check(wl, dev, prec, tol):
     dict(n_sys=120, n_pl=3, n_obs=70, jitter=True),
     dict(n_sys=60, n_pl=8, n_obs=45),
     dict(n_sys=50, n_pl=7, n_obs=130),
+    dict(n_sys=40, n_pl=5, n_obs=64),
+    dict(n_sys=40, n_pl=6, n_obs=190),
 ])
 def test_gn_matches_oracle(dev, prec, tol, case):
     wl = W.dense("c4", n_sys=case["n_sys"], n_pl=case["n_pl"], n_obs=case["n_obs"], jitter=case.get("jitter", False))
