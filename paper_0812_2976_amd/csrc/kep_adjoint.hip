@@ -38,6 +38,12 @@ __host__ __device__ inline size_t adj_table_offset(int wpb, int sb, int npl)
     return ((size_t)wpb * sb * npl * sizeof(RecGrad) + (size_t)wpb * sb * sizeof(int) + 15) & ~(size_t)15;
 }
 
+// The sin/cos knots follow the starting-value table.
+__host__ __device__ inline size_t adj_knots_offset(int wpb, int sb, int npl)
+{
+    return adj_table_offset(wpb, sb, npl) + ((sizeof(kep_start_tab) + 15) & ~(size_t)15);
+}
+
 template <int NPL, int NCH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_grad_obs(DenseArgs a, int nll)
 {
@@ -51,7 +57,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     RecGrad *recs = reinterpret_cast<RecGrad *>(smem) + (size_t)wib * a.sb * NPL;
     int *sysbad = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * NPL * sizeof(RecGrad)) + wib * a.sb;
     uint32_t *tab = reinterpret_cast<uint32_t *>(smem + adj_table_offset(wpb, a.sb, NPL));
-    load_start_table(tab);
+    double2 *knots = reinterpret_cast<double2 *>(smem + adj_knots_offset(wpb, a.sb, NPL));
+    fill_sincos64_knots(knots);
+    load_start_table(tab);          // ends with the block barrier
 
     const SysShare share = sys_share<false>(a.n_sys, wpb, wib, a.sb);
     const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
@@ -125,7 +133,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     PolMixed::solve<NCH, false>(k, uniform_int(rr.niter), uniform_int(rr.check) != 0, rr.tp, M, E,
                                                 sv, omc, a.max_iter, tab);
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) model[c] += refine_velocity(rr, E[c], M64[c], sj[c], cj[c]);
+                    for (int c = 0; c < NCH; ++c) model[c] += refine_velocity(rr, E[c], M64[c], knots, sj[c], cj[c]);
 #pragma unroll
                     for (int jj = 0; jj < NPL; ++jj) {
                         if (jj == j) {
@@ -208,13 +216,14 @@ hipError_t launch_grad_obs_t(DenseArgs a, bool nll, LaunchShape shape, hipStream
     const int block = shape.block > 0 ? shape.block : 256;
     const int wpb = block / 64;
     const size_t rec_bytes = (size_t)wpb * (NPL * sizeof(RecGrad) + sizeof(int));
-    // systems per setup batch: records and table within 40 KiB per block (four
+    // systems per setup batch: records and tables within 40 KiB per block (four
     // blocks of four wavefronts on a CU's 160 KiB), at most kMaxSB; a multiple
     // of 8 where possible (whole 64-byte runs of every parameter plane)
-    int64_t sb_cap = ((int64_t)(40 * 1024) - (int64_t)sizeof(kep_start_tab) - 16) / (int64_t)rec_bytes;
+    int64_t sb_cap =
+        ((int64_t)(40 * 1024) - (int64_t)sizeof(kep_start_tab) - (int64_t)kSc64Bytes - 32) / (int64_t)rec_bytes;
     sb_cap = sb_cap < 1 ? 1 : (sb_cap > kMaxSB ? kMaxSB : sb_cap);
     if (sb_cap > 8) sb_cap &= ~(int64_t)7;
-    auto lds_of = [&](int64_t sb) { return adj_table_offset(wpb, (int)sb, NPL) + sizeof(kep_start_tab); };
+    auto lds_of = [&](int64_t sb) { return adj_knots_offset(wpb, (int)sb, NPL) + kSc64Bytes; };
     void (*kern)(DenseArgs, int) = k_grad_obs<NPL, NCH>;
     int per_cu = shape.blocks_per_cu;
     if (per_cu <= 0) per_cu = cached_occupancy((const void *)kern, block, lds_of(sb_cap));

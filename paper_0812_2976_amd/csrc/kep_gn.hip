@@ -224,6 +224,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     float *T = reinterpret_cast<float *>(mine);
     RecGrad *recs = reinterpret_cast<RecGrad *>(mine + (size_t)NC * kGnCol * sizeof(float));
     int *sysbad = reinterpret_cast<int *>(recs + (size_t)a.sb * NPL);
+    double2 *knots = reinterpret_cast<double2 *>(smem + (size_t)wpb * gn_obs_lds_per_wave<NPL>(a.sb));
+    fill_sincos64_knots(knots);
+    __syncthreads();
 
     const SysShare share = sys_share<true>(a.n_sys, wpb, wib, a.sb);
     const int n_groups = (int)((a.n_obs + 64 * NCH - 1) / (64 * NCH));
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                     PolMixed::solve<NCH, false>(rr.k, uniform_int(rr.niter), uniform_int(rr.check) != 0, rr.tp, M, E,
                                                 sv, omc, a.max_iter, kep_start_tab);
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) model[c] += refine_velocity(rr, E[c], M64[c], sj[c], cj[c]);
+                    for (int c = 0; c < NCH; ++c) model[c] += refine_velocity(rr, E[c], M64[c], knots, sj[c], cj[c]);
 #pragma unroll
                     for (int jj = 0; jj < NPL; ++jj) {
                         if (jj == j) {
@@ -417,17 +420,19 @@ hipError_t launch_gn_obs_t(DenseArgs a, double *jtwr, double *jtwj, LaunchShape 
     const int block = shape.block > 0 ? shape.block : 256;
     const int wpb = block / 64;
     // systems per setup batch: tiles and records within 40 KiB per block (four
-    // blocks of four wavefronts on a CU's 160 KiB), at most kMaxSB
+    // blocks of four wavefronts on a CU's 160 KiB), at most kMaxSB; the
+    // block's sin/cos knots come on top
     int sb_cap = kMaxSB;
     while (sb_cap > 1 && (size_t)wpb * gn_obs_lds_per_wave<NPL>(sb_cap) > 40 * 1024) --sb_cap;
+    auto lds_of = [&](int sbv) { return (size_t)wpb * gn_obs_lds_per_wave<NPL>(sbv) + kSc64Bytes; };
     void (*kern)(DenseArgs, double *, double *) = k_gn_obs<NPL, NCH>;
     int per_cu = shape.blocks_per_cu;
-    if (per_cu <= 0) per_cu = cached_occupancy((const void *)kern, block, (size_t)wpb * gn_obs_lds_per_wave<NPL>(sb_cap));
+    if (per_cu <= 0) per_cu = cached_occupancy((const void *)kern, block, lds_of(sb_cap));
     const int64_t max_waves = (int64_t)device_cu_count() * per_cu * wpb;
     int64_t sb = (a.n_sys + max_waves - 1) / (max_waves > 0 ? max_waves : 1);
     sb = sb < 1 ? 1 : (sb > sb_cap ? sb_cap : sb);
     a.sb = (int)sb;
-    const size_t lds = (size_t)wpb * gn_obs_lds_per_wave<NPL>(a.sb);
+    const size_t lds = lds_of(a.sb);
     if (lds > 64 * 1024) return hipErrorInvalidValue;
     // one block per wpb x sb systems, at most the resident count
     int64_t grid = (a.n_sys + (int64_t)wpb * sb - 1) / ((int64_t)wpb * sb);

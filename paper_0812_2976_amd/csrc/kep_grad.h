@@ -103,6 +103,46 @@ __device__ __forceinline__ void sincos_root64(float E, double &s, double &c)
     c = (q == 1 || q == 2) ? -c0 : c0;
 }
 
+// Binary64 sin and cos at the knots n/64, |n| <= kSc64Half (|E| <= 3.25: the
+// centred range [-pi, pi] and the binary32 rounding of its ends), for the
+// binary64 correction of a binary32 root.  A block fills its copy in LDS
+// once per launch (16 bytes a knot, 6,672 in all).
+constexpr int kSc64Half = 208;
+constexpr int kSc64Knots = 2 * kSc64Half + 1;
+constexpr size_t kSc64Bytes = (size_t)kSc64Knots * 2 * sizeof(double);
+
+// Every thread of the block calls it; a block barrier must follow before any
+// wavefront reads the table.  n/64 is exact in binary32, and the full series
+// of sincos_root64 leaves only the rounding of its evaluation.
+__device__ __forceinline__ void fill_sincos64_knots(double2 *tab)
+{
+    for (int q = threadIdx.x; q < kSc64Knots; q += blockDim.x) {
+        double sv, cv;
+        sincos_root64<true>((float)(q - kSc64Half) * 0.015625f, sv, cv);
+        tab[q] = make_double2(sv, cv);
+    }
+}
+
+// sin and cos of the binary32 E, |E| <= 3.25 or NaN, in binary64 from the
+// nearest knot, n = rint(64 E): y = E - n/64 is exact in binary32
+// (|y| <= 2^-7, and E and n/64 are within a factor two of each other once
+// n != 0), sin y to y^5 and cos y to y^6 (remainders 3.5e-19 and 3.4e-22),
+// then the rotation by the knot's sin and cos.  A NaN reads knot 0 and
+// gives NaN.
+__device__ __forceinline__ void sincos_root64_knots(float E, const double2 *tab, double &s, double &c)
+{
+    const float fn = rintf(E * 64.0f);
+    int n;
+    __asm__("v_cvt_i32_f32 %0, %1" : "=v"(n) : "v"(fn));    // a NaN converts to 0
+    const double y = (double)fmaf(fn, -0.015625f, E);
+    const double2 k = tab[n + kSc64Half];
+    const double y2 = y * y;
+    const double sy = fma(y * y2, fma(y2, 1.0 / 120.0, -1.0 / 6.0), y);
+    const double cy = fma(y2, fma(y2, fma(y2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    s = fma(k.x, cy, k.y * sy);
+    c = fma(k.y, cy, -(k.x * sy));
+}
+
 // Per-planet record of the mixed adjoint (one per system and planet, in LDS).
 struct RecGrad {
     Phase64 ph;                    // P, 1/P, fract(M0/(2 pi) + 1/2)
@@ -237,12 +277,18 @@ __device__ __forceinline__ double mean_anomaly64_exact(double tt, const Phase64 
 // with d1 = -f / D, D = 1 - e cos E (Danby's second correction; the result is
 // within about d^3 e / (6 D) of the root), sin and cos rotated to E + d to
 // second order, and the velocity v = (A cos E + B sin E) / (1 - e cos E) in
-// binary64 (the reciprocal refined by one Newton step from the binary32 one).
-// Also returns sin E and cos E - e rounded to binary32 for the derivative terms.
-__device__ __forceinline__ double refine_velocity(const RecGrad &r, float E, double M64, float &sE, float &cme)
+// binary64 (the reciprocal refined by one Newton step from the binary32 one);
+// knots: the block's sin/cos knots (fill_sincos64_knots).  Also returns sin E
+// and cos E - e rounded to binary32 for the derivative terms.
+__device__ __forceinline__ double refine_velocity(const RecGrad &r, float E, double M64, const double2 *knots,
+                                                  float &sE, float &cme)
 {
+    // every root of a centred M (|M| <= pi) lies in [-3.25, 3.25], so moving an
+    // iterate outside it onto the interval only brings it nearer the root (a NaN
+    // stays NaN)
+    if (fabsf(E) > 3.25f) E = copysignf(3.25f, E);
     double s, c;
-    sincos_root64(E, s, c);
+    sincos_root64_knots(E, knots, s, c);
     const double f = fma(-r.e, s, (double)E - M64);
     const float rD = rcp32((float)fma(-r.e, c, 1.0));
     const float d1 = -(float)f * rD;

@@ -1,8 +1,10 @@
-"""Host checks of the binary64 sine/cosine series that the mixed kernels use to
-correct a binary32 Kepler root (kep_grad.h sincos_root64): the coefficients are
-read from the header and the quadrant reduction and Horner sums replayed in
-Python against math.sin / math.cos, so a wrong sign or factorial in the device
-code fails here on the CPU."""
+"""Host checks of the binary64 sine/cosine that the mixed kernels use to correct
+a binary32 Kepler root (kep_grad.h): the full quadrant-reduced series
+(sincos_root64) and the knot form (sincos_root64_knots: knots n/64 filled with
+the full series, short series of the exactly split remainder, rotation).  The
+coefficients and constants are read from the header and the arithmetic is
+replayed in Python against math.sin / math.cos, so a wrong sign, factorial or
+scale in the device code fails here on the CPU."""
 import math
 import os
 import re
@@ -65,3 +67,45 @@ def test_root_sincos_series(full, bound_s, bound_c):
         s, c = _sincos(float(x), ps, pc)
         es, ec = max(es, abs(s - math.sin(x))), max(ec, abs(c - math.cos(x)))
     assert es <= bound_s and ec <= bound_c, (es, ec)
+
+
+def _knot_form():
+    src = open(HDR).read()
+    half = int(re.search(r"constexpr int kSc64Half = (\d+);", src).group(1))
+    body = src[src.index("__device__ __forceinline__ void sincos_root64_knots"):]
+    body = body[:body.index("\n}\n")]
+    lit = r"(-?[0-9.]+(?: / [0-9.]+)?)"
+    scale = eval(re.search(r"rintf\(E \* " + lit + r"f\)", body).group(1))
+    step = eval(re.search(r"fmaf\(fn, " + lit + r"f, E\)", body).group(1))
+    s3, s5 = (eval(g) for g in re.search(r"const double sy = fma\(y \* y2, fma\(y2, " + lit + ", " + lit + r"\), y\)",
+                                          body).groups()[::-1])
+    c6, c4, c2 = (eval(g) for g in re.search(r"const double cy = fma\(y2, fma\(y2, fma\(y2, " + lit + ", " + lit +
+                                             r"\), " + lit + r"\), 1\.0\)", body).groups())
+    clamp = float(re.search(r"if \(fabsf\(E\) > ([0-9.]+)f\) E = copysignf\(([0-9.]+)f, E\)", src).group(1))
+    return half, scale, step, (s3, s5), (c2, c4, c6), clamp
+
+
+def test_root_sincos_knot_form():
+    half, scale, step, (s3, s5), (c2, c4, c6), clamp = _knot_form()
+    assert scale == 64.0 and step == -1.0 / 64.0 and clamp == half / 64.0 == 3.25
+    assert (s3, s5) == (-1.0 / 6.0, 1.0 / 120.0) and (c2, c4, c6) == (-0.5, 1.0 / 24.0, -1.0 / 720.0)
+    ps, pc = _series(True)
+    knots = {n: _sincos(n / 64.0, ps, pc) for n in range(-half, half + 1)}
+    for n in (-half, -100, -1, 0, 1, 37, half):
+        assert abs(knots[n][0] - math.sin(n / 64.0)) <= 2.3e-16 and abs(knots[n][1] - math.cos(n / 64.0)) <= 2.3e-16
+    rng = np.random.default_rng(12)
+    E = np.concatenate([rng.uniform(-clamp, clamp, 20000), np.linspace(-clamp, clamp, 4001),
+                        np.arange(-half, half + 1) / 64.0 + 1.0 / 128.0]).astype(np.float32)
+    E = E[np.abs(E) <= clamp]
+    es = ec = 0.0
+    for x in E:
+        fn = float(np.rint(np.float32(x) * np.float32(scale)))
+        y = float(x) + fn * step                       # the device's fmaf
+        assert float(np.float32(y)) == y and abs(y) <= 1.0 / 128.0 and abs(fn) <= half
+        ks, kc = knots[int(fn)]
+        y2 = y * y
+        sy = y * y2 * (y2 * s5 + s3) + y
+        cy = y2 * (y2 * (y2 * c6 + c4) + c2) + 1.0
+        sv, cv = ks * cy + kc * sy, kc * cy - ks * sy
+        es, ec = max(es, abs(sv - math.sin(float(x)))), max(ec, abs(cv - math.cos(float(x))))
+    assert es <= 4.5e-16 and ec <= 4.5e-16, (es, ec)
