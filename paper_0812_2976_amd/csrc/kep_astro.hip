@@ -61,10 +61,12 @@ __device__ __forceinline__ bool astro_setup(const AstroArgs &a, int64_t p, Astro
 
 // cos E and sin E of one planet at tt = t - t0, mixed precision: binary64
 // centred phase M, binary32 Danby iteration on (float)M (from the starting-value
-// table where e <= KEP_TAB_EMAX), one binary64 Newton step against M, sin/cos
-// carried to the corrected E to second order.
+// table where e <= KEP_TAB_EMAX), one binary64 Newton step against M (binary64
+// sin/cos of the binary32 root from the block's knots; 1/(1 - e cos E) from the
+// binary32 reciprocal and one Newton step, relative 1e-14 on a step of ~1e-7
+// rad), sin/cos carried to the corrected E to second order.
 __device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int max_iter, const uint32_t *tab,
-                                               double &cE, double &sE)
+                                               const double2 *knots, double &cE, double &sE)
 {
     const double q0 = tt * r.ph.rP;
     const double res = fma(-q0, r.ph.P, tt);
@@ -72,11 +74,14 @@ __device__ __forceinline__ void astro_cs_mixed(const AstroRec &r, double tt, int
     const double u = __builtin_amdgcn_fract(__builtin_amdgcn_fract(q) + r.ph.m0h);
     const double M = fma(u, kTwoPi, -kPi);
     float s32, omc32;
-    const float E32 = kepler32_start((float)M, r.k, r.tp, tab, r.niter, max_iter, r.check != 0, s32, omc32);
+    const float E32 = clamp_root(kepler32_start((float)M, r.k, r.tp, tab, r.niter, max_iter, r.check != 0, s32,
+                                                omc32));
     const double E0 = (double)E32;
     double s, c;
-    sincos_root64<true>(E32, s, c);     // reduced by quadrants: shorter series than sincos_reduced's
-    const double d = -(E0 - r.e * s - M) / (1.0 - r.e * c);
+    sincos_root64_knots(E32, knots, s, c);
+    const double D = fma(-r.e, c, 1.0);
+    const double r0 = (double)rcp32((float)D);
+    const double d = -fma(-r.e, s, E0 - M) * fma(r0, fma(-D, r0, 1.0), r0);
     const double hd2 = 0.5 * d * d;
     cE = c - d * s - hd2 * c;
     sE = s + d * c - hd2 * s;
@@ -106,10 +111,14 @@ __global__ void __launch_bounds__(256) k_astro(AstroArgs a)
     int *sysbad = reinterpret_cast<int *>(smem + (size_t)wpb * a.sb * npl * sizeof(AstroRec)) + wib * a.sb;
     // mixed: the block's copy of the Kepler starting-value table
     const uint32_t *tab = nullptr;
+    const double2 *knots = nullptr;
     if constexpr (MIXED) {
         __shared__ uint32_t tab_s[kTabWords];
-        load_start_table(tab_s);
+        __shared__ double2 knots_s[kSc64Knots];
+        fill_sincos64_knots(knots_s);
+        load_start_table(tab_s);        // ends with the block barrier
         tab = tab_s;
+        knots = knots_s;
     }
 
     const int64_t gw = (int64_t)blockIdx.x * wpb + wib;
@@ -183,7 +192,7 @@ __global__ void __launch_bounds__(256) k_astro(AstroArgs a)
                     for (int c = 0; c < NCH; ++c) {
                         if (!o[c].in) continue;
                         double cE, sE;
-                        if (MIXED) astro_cs_mixed(r, o[c].t - a.t0, a.max_iter, tab, cE, sE);
+                        if (MIXED) astro_cs_mixed(r, o[c].t - a.t0, a.max_iter, tab, knots, cE, sE);
                         else astro_cs_f64(r, o[c].t - a.t0, fixed, a.max_iter, cE, sE);
                         const double X = cE - r.e, Y = r.b * sE;
                         ra[c] = fma(r.B, X, fma(r.G, Y, ra[c]));
@@ -220,7 +229,12 @@ hipError_t launch_astro_t(AstroArgs a, LaunchShape shape, hipStream_t st)
     const int block = shape.block > 0 ? shape.block : 256;
     const int wpb = block / 64;
     const size_t rec_bytes = (size_t)wpb * a.n_pl * sizeof(AstroRec) + (size_t)wpb * sizeof(int);
-    int64_t sb_cap = (int64_t)(48 * 1024) / (int64_t)rec_bytes;
+    // records and (mixed) the block's tables within 32 KiB, so that five blocks
+    // of four wavefronts share a CU's 160 KiB (the binary32-iteration kernels
+    // fit five wavefronts per SIMD in registers; at 1,048,576 x 2 x 128,
+    // 48 KiB and three blocks: 1.15 ms, 40 KiB: 1.08 ms, 32 KiB: 1.06 ms)
+    const int64_t tables = MIXED ? (int64_t)(sizeof(kep_start_tab) + kSc64Bytes) : 0;
+    int64_t sb_cap = ((int64_t)(32 * 1024) - tables) / (int64_t)rec_bytes;
     sb_cap = sb_cap < 1 ? 1 : (sb_cap > kMaxSB ? kMaxSB : sb_cap);
     const int nch_needed = (int)((a.n_obs + 63) / 64);
     void (*kern)(AstroArgs);

@@ -123,6 +123,11 @@ __device__ __forceinline__ void fill_sincos64_knots(double2 *tab)
     }
 }
 
+// Every root of a centred M (|M| <= pi) lies in [-3.25, 3.25], so moving an
+// iterate outside it onto the interval only brings it nearer the root (a NaN
+// stays NaN); the knots below cover the interval.
+__device__ __forceinline__ float clamp_root(float E) { return fabsf(E) > 3.25f ? copysignf(3.25f, E) : E; }
+
 // sin and cos of the binary32 E, |E| <= 3.25 or NaN, in binary64 from the
 // nearest knot, n = rint(64 E): y = E - n/64 is exact in binary32
 // (|y| <= 2^-7, and E and n/64 are within a factor two of each other once
@@ -283,10 +288,7 @@ __device__ __forceinline__ double mean_anomaly64_exact(double tt, const Phase64 
 __device__ __forceinline__ double refine_velocity(const RecGrad &r, float E, double M64, const double2 *knots,
                                                   float &sE, float &cme)
 {
-    // every root of a centred M (|M| <= pi) lies in [-3.25, 3.25], so moving an
-    // iterate outside it onto the interval only brings it nearer the root (a NaN
-    // stays NaN)
-    if (fabsf(E) > 3.25f) E = copysignf(3.25f, E);
+    E = clamp_root(E);
     double s, c;
     sincos_root64_knots(E, knots, s, c);
     const double f = fma(-r.e, s, (double)E - M64);
