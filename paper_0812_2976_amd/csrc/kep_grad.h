@@ -51,17 +51,12 @@ __device__ __forceinline__ bool grad_setup(double P, double K, double e, double 
 // cos E; the derivative terms stay binary32 (their relative error enters the
 // gradient only relative to that scale).
 
-// sin E and cos E in binary64 of a binary32 Kepler root (|E| <= pi for a
-// centred mean anomaly, a little more after a caller-fixed step count):
+// sin E and cos E in binary64 of a binary32 value (the knots below):
 // E = y + n pi/2 with n the nearest integer to 2E/pi and pi/2 in two parts,
 // each product taken inside a fused multiply-add, then the Taylor series of
 // sin y and cos y on |y| <= pi/4 (coefficients 1/n!), rotated by the quadrant
-// n mod 4.  FULL = false: sin to y^13 and cos to y^14 (remainders below 2.1e-14
-// and 1.1e-15; after the rotation either of sin E and cos E may carry the
-// first: enough for the adjoint's binary32 derivative terms); FULL = true: sin
-// to y^17 and cos to y^18 (remainders below 8.4e-20 and 3.3e-21: a binary64
-// result to its last bits, for the astrometric positions).
-template <bool FULL = false>
+// n mod 4: sin to y^17 and cos to y^18 (remainders below 8.4e-20 and
+// 3.3e-21), a binary64 result to its last bits.
 __device__ __forceinline__ void sincos_root64(float E, double &s, double &c)
 {
     const float nf = rintf(E * 0.636619772f);
@@ -69,20 +64,13 @@ __device__ __forceinline__ void sincos_root64(float E, double &s, double &c)
     const double dn = (double)nf;
     const double y = fma(-dn, 6.123233995736766036e-17, fma(-dn, 1.5707963267948965580, (double)E));
     const double y2 = y * y;
-    double ps, pc;
-    if constexpr (FULL) {
-        ps = 1.0 / 355687428096000.0;                // 1/17!
-        ps = fma(ps, y2, -1.0 / 1307674368000.0);    // 1/15!
-        ps = fma(ps, y2, 1.0 / 6227020800.0);        // 1/13!
-        pc = -1.0 / 6402373705728000.0;              // 1/18!
-        pc = fma(pc, y2, 1.0 / 20922789888000.0);    // 1/16!
-        pc = fma(pc, y2, -1.0 / 87178291200.0);      // 1/14!
-        pc = fma(pc, y2, 1.0 / 479001600.0);         // 1/12!
-    } else {
-        ps = 1.0 / 6227020800.0;                     // 1/13!
-        pc = -1.0 / 87178291200.0;                   // 1/14!
-        pc = fma(pc, y2, 1.0 / 479001600.0);         // 1/12!
-    }
+    double ps = 1.0 / 355687428096000.0;             // 1/17!
+    ps = fma(ps, y2, -1.0 / 1307674368000.0);        // 1/15!
+    ps = fma(ps, y2, 1.0 / 6227020800.0);            // 1/13!
+    double pc = -1.0 / 6402373705728000.0;           // 1/18!
+    pc = fma(pc, y2, 1.0 / 20922789888000.0);        // 1/16!
+    pc = fma(pc, y2, -1.0 / 87178291200.0);          // 1/14!
+    pc = fma(pc, y2, 1.0 / 479001600.0);             // 1/12!
     ps = fma(ps, y2, -1.0 / 39916800.0);             // 1/11!
     ps = fma(ps, y2, 1.0 / 362880.0);                // 1/9!
     ps = fma(ps, y2, -1.0 / 5040.0);                 // 1/7!
@@ -118,7 +106,7 @@ __device__ __forceinline__ void fill_sincos64_knots(double2 *tab)
 {
     for (int q = threadIdx.x; q < kSc64Knots; q += blockDim.x) {
         double sv, cv;
-        sincos_root64<true>((float)(q - kSc64Half) * 0.015625f, sv, cv);
+        sincos_root64((float)(q - kSc64Half) * 0.015625f, sv, cv);
         tab[q] = make_double2(sv, cv);
     }
 }

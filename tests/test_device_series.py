@@ -1,5 +1,5 @@
 """Host checks of the binary64 sine/cosine that the mixed kernels use to correct
-a binary32 Kepler root (kep_grad.h): the full quadrant-reduced series
+a binary32 Kepler root (kep_grad.h): the quadrant-reduced series
 (sincos_root64) and the knot form (sincos_root64_knots: knots n/64 filled with
 the full series, short series of the exactly split remainder, rotation).  The
 coefficients and constants are read from the header and the arithmetic is
@@ -20,17 +20,11 @@ def _coeffs(var, text):
     return [eval(m.group(1)) for m in re.finditer(pat, text)]
 
 
-def _series(full):
+def _series():
     src = open(HDR).read()
-    body = src[src.index("__device__ __forceinline__ void sincos_root64"):]
+    body = src[src.index("__device__ __forceinline__ void sincos_root64(float E"):]
     body = body[:body.index("\n}\n")]
-    branch = body[body.index("if constexpr (FULL) {"):body.index("const double sy")]
-    head = (branch[:branch.index("} else {")] if full
-            else branch[branch.index("} else {"):branch.index("ps = fma(ps, y2, -1.0 / 39916800.0)")])
-    ps = _coeffs("ps", head) + _coeffs("ps", body[body.index("ps = fma(ps, y2, -1.0 / 39916800.0)"):
-                                                  body.index("const double sy")])
-    pc = _coeffs("pc", head) + _coeffs("pc", body[body.index("const double sy"):body.index("const double cy")])
-    return ps, pc
+    return _coeffs("ps", body), _coeffs("pc", body)
 
 
 def _sincos(E, ps, pc):
@@ -50,11 +44,10 @@ def _sincos(E, ps, pc):
     return (-s0 if q & 2 else s0), (-c0 if q in (1, 2) else c0)
 
 
-@pytest.mark.parametrize("full,bound_s,bound_c", [(False, 2.2e-14, 2.2e-14), (True, 3e-16, 3e-16)])
-def test_root_sincos_series(full, bound_s, bound_c):
-    ps, pc = _series(full)
-    # degrees: sin to y^13 / y^17, cos to y^14 / y^18, with 1/n! magnitudes and alternating signs
-    assert len(ps) == (8 if full else 6) and len(pc) == (9 if full else 7)
+def test_root_sincos_series():
+    ps, pc = _series()
+    # sin to y^17, cos to y^18, with 1/n! magnitudes and alternating signs
+    assert len(ps) == 8 and len(pc) == 9
     for k, c in enumerate(reversed(ps)):
         assert c == pytest.approx((-1) ** (k + 1) / math.factorial(2 * k + 3), rel=1e-15)
     for k, c in enumerate(reversed(pc)):
@@ -66,7 +59,7 @@ def test_root_sincos_series(full, bound_s, bound_c):
     for x in E:
         s, c = _sincos(float(x), ps, pc)
         es, ec = max(es, abs(s - math.sin(x))), max(ec, abs(c - math.cos(x)))
-    assert es <= bound_s and ec <= bound_c, (es, ec)
+    assert es <= 3e-16 and ec <= 3e-16, (es, ec)
 
 
 def _knot_form():
@@ -81,7 +74,10 @@ def _knot_form():
                                           body).groups()[::-1])
     c6, c4, c2 = (eval(g) for g in re.search(r"const double cy = fma\(y2, fma\(y2, fma\(y2, " + lit + ", " + lit +
                                              r"\), " + lit + r"\), 1\.0\)", body).groups())
-    clamp = float(re.search(r"if \(fabsf\(E\) > ([0-9.]+)f\) E = copysignf\(([0-9.]+)f, E\)", src).group(1))
+    m = re.search(r"float clamp_root\(float E\) \{ return fabsf\(E\) > ([0-9.]+)f \? copysignf\(([0-9.]+)f, E\) : E; \}",
+                  src)
+    assert m.group(1) == m.group(2)
+    clamp = float(m.group(1))
     return half, scale, step, (s3, s5), (c2, c4, c6), clamp
 
 
@@ -89,7 +85,7 @@ def test_root_sincos_knot_form():
     half, scale, step, (s3, s5), (c2, c4, c6), clamp = _knot_form()
     assert scale == 64.0 and step == -1.0 / 64.0 and clamp == half / 64.0 == 3.25
     assert (s3, s5) == (-1.0 / 6.0, 1.0 / 120.0) and (c2, c4, c6) == (-0.5, 1.0 / 24.0, -1.0 / 720.0)
-    ps, pc = _series(True)
+    ps, pc = _series()
     knots = {n: _sincos(n / 64.0, ps, pc) for n in range(-half, half + 1)}
     for n in (-half, -100, -1, 0, 1, 37, half):
         assert abs(knots[n][0] - math.sin(n / 64.0)) <= 2.3e-16 and abs(knots[n][1] - math.cos(n / 64.0)) <= 2.3e-16
