@@ -508,7 +508,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         int64_t item = -1;
         while (tried < kRaggedQueues) {               // uniform: every lane takes part in the shuffle
             const int q = (home + tried) % kRaggedQueues;
-            if ((uniform_int((int)drained) >> q) & 1) {
+            // a relaxed read: a mark not yet seen costs one more probe, nothing else
+            const unsigned int seen = __hip_atomic_load(&drained, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if ((uniform_int((int)seen) >> q) & 1) {
                 ++tried;
                 continue;
             }
