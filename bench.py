@@ -183,13 +183,14 @@ def recorded_traffic(name, files=DENSE_FILES):
 #     remainder, correction, fraction, offset, fraction, scale) and the
 #     conversion 8 f64; starting value 10; last step 25 on the Halley rows of
 #     the table, 33 (Danby's quartic) above them (1 trans);
-#   binary64 correction: sin/cos of the binary32 root (reduction by n pi/2 4,
-#     square 1, degree-13 and degree-14 Taylor series 16; quadrant selects and
-#     signs 9 f32-class), residual of Kepler's equation 2, D 1 + its binary32
+#   binary64 correction: the root moved onto [-3.25, 3.25] 3 f32-class;
+#     sin/cos of the binary32 root from the nearest knot n/64 (scale,
+#     rounding, conversion, remainder and address 5 f32-class; remainder to
+#     binary64 1, square 1, sin y to y^5 3, cos y to y^6 3, rotation by the
+#     knot 4: 12 f64), residual of Kepler's equation 2, D 1 + its binary32
 #     reciprocal (1 trans), corrected step with the second-order term 5 f64
 #     + 6 f32, sin/cos carried to the corrected root 6 f64 + 2 f32, velocity
-#     8 f64 (1 trans), sin E and cos E - e for pass 2 3, planet sum 1:
-#     44 f64, 17 f32, 2 trans;
+#     8 f64 (1 trans), planet sum 1: 35 f64, 16 f32, 2 trans;
 #   pass 2: 1/D (1 trans), cos f, sin f, sin(w+f), df/dM and the five terms
 #     (two in their cancellation-free forms) 23, the quotient for dv/dP 2 f64,
 #     five weighted accumulations 5: 28 f32, 2 f64, 1 trans;
@@ -198,7 +199,7 @@ def recorded_traffic(name, files=DENSE_FILES):
 #   per group of 64 NCH observations: the 5 n_pl + 1 lane sums reduced across
 #     the wavefront (R - 1 exchanges, two selects and an add each, R the next
 #     power of two), spread over the group's 64 NCH n_pl triples per lane.
-ADJ_F64, ADJ_F32, ADJ_TRANS = 8 + 44 + 2, 10 + 17 + 28, 1 + 2 + 1
+ADJ_F64, ADJ_F32, ADJ_TRANS = 8 + 35 + 2, 10 + 16 + 28, 1 + 2 + 1
 ADJ_OBS = {"f64": 3, "f32": 4, "trans": 1}
 
 
@@ -478,10 +479,12 @@ def main():
         jj = torch.empty((npar * (npar + 1) // 2, w4.n_sys), dtype=torch.float64, device=dev)
         msgn, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="mixed", out=o4, jtwr=jr, jtwj=jj), ROW_STEPS, ROW_WARMUP, torch)
         msgn64, _ = timed(lambda: kp.rv_chisq_gn(**g4, prec="fp64", out=o4, jtwr=jr, jtwj=jj), 3, 1, torch)
-        # Gram matrix of sqrt(w)[J | 1 | r]: (np + 1)(np + 2)/2 multiply-adds per (system, observation)
+        # Gram matrix of sqrt(w)[J | 1 | r]: (np + 1)(np + 2)/2 multiply-adds per (system, observation);
+        # 16x16x4 products per four observations: two for 17 to 24 columns, else one per pair of blocks
         useful = w4.n_sys * w4.t.size * (npar + 1) * (npar + 2)
         nb = (npar + 1 + 15) // 16
-        issued = w4.n_sys * (w4.t.size // 4) * (nb * (nb + 1) // 2) * 2048
+        nprod = 2 if 16 < npar + 1 <= 24 else nb * (nb + 1) // 2
+        issued = w4.n_sys * (w4.t.size // 4) * nprod * 2048
         tri4 = w4.n_sys * w4.n_pl * w4.t.size
         nch4 = 1 if w4.t.size <= 64 else (2 if (w4.n_pl > 4 or w4.t.size <= 128) else 4)
         result["gradient_c4"] = {"chi2_grad_per_s": w4.n_sys / (msg * 1e-3), "launch_ms": msg,
