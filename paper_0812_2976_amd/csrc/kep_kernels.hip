@@ -219,11 +219,24 @@ __global__ void __launch_bounds__(256) k_chisq_from_dv(DenseArgs a)
         PolMixed::ModelAcc m[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) PolMixed::model_init(m[c]);
-        for (int j = 0; j < a.n_pl; ++j) {
-            const float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
+        // every planet's row is requested before the first is summed (one row at a
+        // time left too few bytes in flight to fill HBM); the sum keeps planet order
+        float dv[kMaxPl][NCH];
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)      // read once: nontemporal loads (4% at c2)
-                m[c].add(o[c].in ? __builtin_nontemporal_load(row + c * 64 + lane) : 0.0f);
+        for (int j = 0; j < kMaxPl; ++j) {
+            if (j < a.n_pl) {
+                const float *row = a.dv + ((int64_t)j * a.n_sys + sys) * a.n_obs;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)  // read once: nontemporal loads (4% at c2)
+                    dv[j][c] = o[c].in ? __builtin_nontemporal_load(row + c * 64 + lane) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kMaxPl; ++j) {
+            if (j < a.n_pl) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) m[c].add(dv[j][c]);
+            }
         }
         PolMixed::ChiAcc chi;
         PolMixed::chi_init(chi);
