@@ -549,6 +549,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 const int64_t sys = code;
                 const int64_t p0 = a.pl_off[sys];
                 const int64_t o0 = a.obs_off[sys], n = a.obs_off[sys + 1] - o0;
+                // the system's offset and jitter with its offsets, not behind the
+                // planet parameters (one dependent round trip fewer per item)
+                gj[2 * lane] = a.offset ? a.offset[sys] : 0.0;
+                gj[2 * lane + 1] = a.jitter ? a.jitter[sys] : 0.0;
                 meta[2 * lane] = (int)(a.pl_off[sys + 1] - p0);
                 meta[2 * lane + 1] = (int)sys;
                 pofs[lane] = p0;
@@ -561,6 +565,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
                 // its offsets are not read again and its chi-square is NaN
                 meta[2 * lane] = 0;
                 meta[2 * lane + 1] = -1 - code;
+                gj[2 * lane] = 0.0;
+                gj[2 * lane + 1] = 0.0;
                 pofs[lane] = 0;
                 tail0[lane] = 0;
                 obs0[lane] = 0;
@@ -593,16 +599,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GMAX =
         wave_sync_lds();
         if (lane < nb) {
             const int npl = meta[2 * lane];
-            const int64_t sys = meta[2 * lane + 1];
             bool ok = isfinite(a.t0) && npl >= 1 && npl <= kMaxPl;
             for (int j = 0; j < kMaxPl; ++j)
                 if (j < npl) ok = ok && okpl[lane * kMaxPl + j] != 0;
-            const double g = a.offset ? a.offset[sys] : 0.0;
-            const double sj = a.jitter ? a.jitter[sys] : 0.0;
+            const double g = gj[2 * lane], sj = gj[2 * lane + 1];
             if (a.offset) ok = ok && isfinite(g);
             if (a.jitter) ok = ok && isfinite(sj) && sj >= 0.0;
-            gj[2 * lane] = g;
-            gj[2 * lane + 1] = sj;
             meta[2 * lane] = ok ? npl : -npl;
         }
         wave_sync_lds();
