@@ -543,6 +543,10 @@ def main():
         msr, _ = timed(lambda: plan(o3), ROW_STEPS, GRAPH_WARMUP, torch)
         msr_direct, _ = timed(lambda: plan.direct(o3), ROW_STEPS, ROW_WARMUP, torch)
         info = plan.info()
+        plan64 = kp.RaggedPlan(gpu(rw.t), gpu(rw.v), gpu(rw.sigma), gpu(rw.obs_off), gpu(rw.P), gpu(rw.K),
+                               gpu(rw.e), gpu(rw.w), gpu(rw.M0), gpu(rw.pl_off), t0=rw.t0, prec="fp64")
+        msr64, _ = timed(lambda: plan64(o3), 3, 1, torch)
+        plan64.close()
         # the formulation's operations summed over the batch: every triple as in the
         # dense count, the per-observation work once per observation of each system
         npl_i = np.diff(rw.pl_off)
@@ -559,6 +563,7 @@ def main():
         result["ragged_c3"] = {"chi2_per_s": rw.n_sys / (msr_direct * 1e-3), "launch_ms": msr_direct,
                                "launch_call": "rv_chisq_ragged_direct",
                                "graph_launch_ms": msr, "graph_chi2_per_s": rw.n_sys / (msr * 1e-3),
+                               "fp64_launch_ms": msr64, "speedup_vs_fp64": msr64 / msr_direct,
                                "kepler_solves_per_s": info["triples"] / (msr_direct * 1e-3),
                                "triples": info["triples"],
                                "roofline": roofline_entry(f"k_ragged_mixed<{info['group_chunks']}>", cls3, tri3,

@@ -278,14 +278,17 @@ typedef struct kep_plan kep_plan;   /* opaque; owned by the library */
    work-queue counters at zero for the next launch, so no reset is
    recorded).  May allocate and synchronises `stream`.  The plan keeps the
    other input pointers: their contents may change between calls, their
-   addresses and sizes may not.  Only KEP_MIXED is implemented for ragged batches
-   (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */
+   addresses and sizes may not.  KEP_FP64 plans (the plain binary64 path of
+   rv_chisq, Sec. 5.1: IEEE quotient, 30 Danby steps by default) skip the
+   autotuner and the graph: one wavefront per system over the work order,
+   launched directly by both calls below; block_threads at most 256. */
 kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, kep_prec prec,
                            const kep_options *opts, void *stream, kep_plan **out);
 
 /* Chi-square of every system of the plan's batch into chi2[n_sys] (one graph
-   launch on `stream`; does not allocate or synchronise).  Calls on one plan
-   must not overlap in time (they share the plan's work-queue counters). */
+   launch on `stream`, a direct launch for KEP_FP64 plans; does not allocate
+   or synchronise).  Calls on one plan must not overlap in time (they share
+   the plan's work-queue counters). */
 kep_status rv_chisq_ragged(kep_plan *plan, double *chi2, void *stream);
 
 /* Same work launched directly, without the graph (for comparison). */
@@ -310,7 +313,10 @@ kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream);
    give n_pl outside [1, KEP_MAX_PL] gets a NaN chi-square (other systems are
    unaffected).  Every call on one GPU shares the work area: calls that
    overlap in time on the same GPU (different streams, threads) race and
-   must not be made.  Only KEP_MIXED (KEP_FP64 returns KEP_ERR_UNSUPPORTED). */
+   must not be made.  KEP_FP64: one kernel, the binary64 path of the plans,
+   in system order with every system's offsets checked by the wavefront that
+   evaluates it (same NaN rule); it uses no work area, so neither the n_sys
+   limit nor the sharing between calls applies to it. */
 kep_status rv_chisq_ragged_static(const kep_obs_csr *obs, const kep_params_csr *par, double *chi2, kep_prec prec,
                                   const kep_options *opts, void *stream);
 

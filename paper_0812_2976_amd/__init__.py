@@ -464,7 +464,8 @@ def rv_chisq_ragged_static(t, v, sigma, obs_off, P, K, e, omega, M0, pl_off, off
     """chi-square of a CSR batch in one call without a plan and without any
     device allocation by the library (the offsets are checked and the systems
     ordered on the device, in the library's static work area); n_sys <= 2^21.
-    Calls that overlap in time on one GPU must not be made."""
+    Calls that overlap in time on one GPU must not be made.  prec="fp64" runs
+    the binary64 kernel, which uses no work area (no size limit, no sharing)."""
     t, v, sigma = (_dev(x, n, 1) for x, n in ((t, "t"), (v, "v"), (sigma, "sigma")))
     obs_off = _dev(obs_off, "obs_off", 1, torch.int64)
     pl_off = _dev(pl_off, "pl_off", 1, torch.int64)

@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkepler.so")
-SOURCES = ["kep_kernels.hip", "kep_adjoint.hip", "kep_demc.hip", "kep_astro.hip", "kep_gn.hip", "kep_api.cpp"]
+SOURCES = ["kep_kernels.hip", "kep_adjoint.hip", "kep_demc.hip", "kep_astro.hip", "kep_gn.hip", "kep_ragged64.hip",
+           "kep_api.cpp"]
 # Per-source flags.  The Gauss-Newton kernel's matrix products accumulate in
 # ordinary VGPRs (gfx950 allows it): without this the compiler moves the
 # accumulators to AGPRs and back around every unrolled group of products and

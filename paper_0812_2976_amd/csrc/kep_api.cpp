@@ -356,6 +356,7 @@ struct kep_plan {
     int64_t *d_pl_off = nullptr;
     unsigned int *d_queue = nullptr;
     double *bound_out = nullptr;      // output pointer recorded in the graph
+    bool fp64 = false;                // KEP_FP64: the binary64 kernel, launched directly (no tuning, no graph)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t kernel_node = nullptr;
@@ -511,7 +512,6 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     *out = nullptr;
     if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
     if (kep_status s = check_prec(prec, fn)) return s;
-    if (prec != KEP_MIXED) return fail(KEP_ERR_UNSUPPORTED, "%s: only KEP_MIXED is implemented for ragged batches", fn);
     Opts o;
     if (kep_status s = parse_opts(opts, fn, o)) return s;
     const int64_t n_sys = par->n_sys;
@@ -611,6 +611,24 @@ kep_status kep_plan_ragged(const kep_obs_csr *obs, const kep_params_csr *par, ke
     a.fixed_iter = o.fixed_iter;
     a.max_iter = o.max_iter;
 
+    if (prec == KEP_FP64) {
+        // the binary64 kernel: one wavefront per system over the work order
+        // (decreasing work first balances the grid-stride), no tuning, no graph
+        p->fp64 = true;
+        p->shape.block = o.shape.block > 0 ? o.shape.block : 256;
+        p->shape.blocks_per_cu = o.shape.blocks_per_cu;
+        if (p->shape.block > 256) {
+            plan_free(p);
+            return fail(KEP_ERR_ARG, "%s: block_threads above 256 for KEP_FP64", fn);
+        }
+        a.sb = 1;
+        a.gmax = 4;
+        a.n_items = n_sys;
+        p->grid = n_sys > 0 ? kep::ragged64_grid(p->shape, n_sys) : 0;
+        *out = p;
+        return KEP_OK;
+    }
+
     auto configure = [&](int block, int sb, int gmax) {
         p->shape.block = block;
         p->shape.blocks_per_cu = o.shape.blocks_per_cu;
@@ -709,6 +727,11 @@ kep_status rv_chisq_ragged(kep_plan *plan, double *chi2, void *stream)
     static const char *fn = "rv_chisq_ragged";
     if (kep_status s = ragged_check(plan, chi2, fn)) return s;
     if (plan->args.n_sys == 0) return KEP_OK;
+    if (plan->fp64) {
+        kep::RaggedArgs a = plan->args;
+        a.out = chi2;
+        return launch_status(kep::launch_ragged64(a, plan->shape, (hipStream_t)stream), fn);
+    }
     if (!plan->exec || plan->bound_out != chi2) {
         // (re)record the graph for this output buffer
         plan->args.out = chi2;
@@ -742,6 +765,7 @@ kep_status rv_chisq_ragged_direct(kep_plan *plan, double *chi2, void *stream)
     kep::RaggedArgs a = plan->args;
     a.out = chi2;
     hipStream_t st = (hipStream_t)stream;
+    if (plan->fp64) return launch_status(kep::launch_ragged64(a, plan->shape, st), fn);
     hipError_t err = kep::launch_ragged(a, plan->shape, plan->grid, st);
     return launch_status(err, fn);
 }
@@ -752,12 +776,11 @@ kep_status rv_chisq_ragged_static(const kep_obs_csr *obs, const kep_params_csr *
     static const char *fn = "rv_chisq_ragged_static";
     if (!obs || !par) return fail(KEP_ERR_ARG, "%s: obs and params must not be NULL", fn);
     if (kep_status s = check_prec(prec, fn)) return s;
-    if (prec != KEP_MIXED) return fail(KEP_ERR_UNSUPPORTED, "%s: only KEP_MIXED is implemented for ragged batches", fn);
     Opts o;
     if (kep_status s = parse_opts(opts, fn, o)) return s;
     const int64_t n_sys = par->n_sys;
     if (n_sys < 0) return fail(KEP_ERR_ARG, "%s: n_sys = %lld < 0", fn, (long long)n_sys);
-    if (n_sys > kep::kStaticMaxSys)
+    if (prec == KEP_MIXED && n_sys > kep::kStaticMaxSys)
         return fail(KEP_ERR_SHAPE, "%s: n_sys = %lld exceeds the %lld systems of the static work area (use a plan)",
                     fn, (long long)n_sys, (long long)kep::kStaticMaxSys);
     if (obs->n_obs_total < 0 || par->n_pl_total < 0) return fail(KEP_ERR_ARG, "%s: negative totals", fn);
@@ -789,6 +812,14 @@ kep_status rv_chisq_ragged_static(const kep_obs_csr *obs, const kep_params_csr *
     a.out = chi2;
     a.fixed_iter = o.fixed_iter;
     a.max_iter = o.max_iter;
+    if (prec == KEP_FP64) {
+        // the binary64 kernel needs no work area: one wavefront per system in
+        // system order, each checking its own offsets against the totals
+        a.order = nullptr;
+        kep::LaunchShape shape64 = o.shape;
+        if (shape64.block > 256) return fail(KEP_ERR_ARG, "%s: block_threads above 256 for KEP_FP64", fn);
+        return launch_status(kep::launch_ragged64(a, shape64, (hipStream_t)stream), fn);
+    }
     // the launch shape the autotuner picks for the c3-like batches it has seen:
     // 16 systems per work item, observation groups of up to four 64-lane chunks
     a.sb = 16;

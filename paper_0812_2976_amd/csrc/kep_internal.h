@@ -121,6 +121,10 @@ int ragged_max_grid(LaunchShape shape, int sb, int gmax);
 // (into the static scratch array), then runs the persistent kernel; a.order
 // and a.queue are set here.  a.sb and a.gmax must be set.  No allocation.
 hipError_t launch_ragged_static(RaggedArgs a, LaunchShape shape, hipStream_t st);
+// Plain binary64 ragged chi-square (kep_ragged64.hip): one wavefront per system, grid-stride over the
+// work order (a.order, or the systems in order when null); checks every system's offsets itself.
+hipError_t launch_ragged64(RaggedArgs a, LaunchShape shape, hipStream_t st);
+int ragged64_grid(LaunchShape shape, int64_t n_sys);   // the blocks launch_ragged64 launches
 bool ragged_shape_fits(int block, int sb);   // LDS of the persistent kernel (slices + table) within 64 KiB
 hipError_t launch_astro(AstroArgs a, Prec prec, bool model, LaunchShape shape, hipStream_t st);
 // Gauss-Newton products: chi2 into a.out, J^T W r [np][n_sys], packed J^T W J

@@ -84,10 +84,15 @@ def test_ragged_argument_errors(lib):
     out = ctypes.c_void_p()
     obs = kp.KepObsCSR(None, None, None, None, 0, 0.0)
     par = kp.KepParamsCSR(None, None, None, None, None, None, None, None, 4, 0)
-    code, msg = _status(lib.kep_plan_ragged(ctypes.byref(obs), ctypes.byref(par), 0, None, None, ctypes.byref(out)), lib)
-    assert code == 5 and "KEP_MIXED" in msg
-    code, msg = _status(lib.kep_plan_ragged(ctypes.byref(obs), ctypes.byref(par), 1, None, None, ctypes.byref(out)), lib)
-    assert code == 1 and "pl_off" in msg
+    for prec in (0, 1):          # KEP_FP64 and KEP_MIXED both reach the argument checks
+        code, msg = _status(lib.kep_plan_ragged(ctypes.byref(obs), ctypes.byref(par), prec, None, None,
+                                                ctypes.byref(out)), lib)
+        assert code == 1 and "pl_off" in msg
+        code, msg = _status(lib.rv_chisq_ragged_static(ctypes.byref(obs), ctypes.byref(par), None, prec, None,
+                                                       None), lib)
+        assert code == 1 and "chi2" in msg
+    code, msg = _status(lib.kep_plan_ragged(ctypes.byref(obs), ctypes.byref(par), 7, None, None, ctypes.byref(out)), lib)
+    assert code == 1 and "prec" in msg
     assert lib.rv_chisq_ragged(None, None, None) == 1
     lib.kep_plan_destroy(None)
 

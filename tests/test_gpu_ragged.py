@@ -1,6 +1,9 @@
 """GPU parity of the ragged (CSR) persistent kernel, its HIP-graph replay and its
 autotuned launch shape, against the oracle.  Mixed precision: chi2 relative
-error <= 1e-5 (relative to max(chi2, 1))."""
+error <= 1e-5 (relative to max(chi2, 1)).  The plain binary64 ragged path
+(plans and the allocation-free call with KEP_FP64): relative 1e-12, as the
+dense binary64 chi-square, and NaN exactly for the systems whose offsets are
+inconsistent."""
 import numpy as np
 import pytest
 import torch
@@ -24,10 +27,18 @@ def _ragged(n_sys, seed=None, n_obs_range=(16, 1024), uniform=None, offsets=Fals
     return rw
 
 
-def _plan(rw, dev, opts=None):
+def _plan(rw, dev, opts=None, prec="mixed"):
     g = lambda x: None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev)
     return kp.RaggedPlan(g(rw.t), g(rw.v), g(rw.sigma), g(rw.obs_off), g(rw.P), g(rw.K), g(rw.e), g(rw.w),
-                         g(rw.M0), g(rw.pl_off), g(rw.offset), g(rw.jitter), rw.t0, "mixed", opts)
+                         g(rw.M0), g(rw.pl_off), g(rw.offset), g(rw.jitter), rw.t0, prec, opts)
+
+
+def _static(rw, dev, prec, obs_off=None, pl_off=None):
+    g = lambda x: None if x is None else torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    return kp.rv_chisq_ragged_static(g(rw.t), g(rw.v), g(rw.sigma), g(rw.obs_off if obs_off is None else obs_off),
+                                     g(rw.P), g(rw.K), g(rw.e), g(rw.w), g(rw.M0),
+                                     g(rw.pl_off if pl_off is None else pl_off), g(rw.offset), g(rw.jitter), rw.t0,
+                                     prec=prec).cpu().numpy()
 
 
 def _oracle(rw):
@@ -55,6 +66,60 @@ def test_ragged_matches_oracle(dev, case):
     else:
         # down to one observation per system: the bound a velocity error can cause
         assert np.all(np.abs(chi2 - ref) <= W.chi2_tol_mixed_ragged(rw, ref))
+
+
+@pytest.mark.parametrize("case", [
+    dict(n_sys=600),
+    dict(n_sys=700, n_obs_range=(1, 70), offsets=True, jitter=True),
+])
+def test_ragged_fp64_matches_oracle(dev, case):
+    """KEP_FP64 ragged: the plan's two calls and the allocation-free call give the
+    same bits (one wavefront per system whatever the order) and match the oracle
+    to 1e-12 relative."""
+    rw = _ragged(case["n_sys"], seed=31, n_obs_range=case.get("n_obs_range", (16, 1024)),
+                 offsets=case.get("offsets", False), jitter=case.get("jitter", False))
+    print(f"[ragged fp64] {case}", flush=True)
+    plan = _plan(rw, dev, prec="fp64")
+    chi2 = plan().cpu().numpy()
+    direct = plan.direct().cpu().numpy()
+    info = plan.info()
+    plan.close()
+    static = _static(rw, dev, "fp64")
+    ref = _oracle(rw)
+    err = W.rel_err_chi2(chi2, ref)
+    print(f"[ragged fp64 {case}] max rel {err.max():.3e}; info {info}", flush=True)
+    assert np.all(np.isfinite(chi2))
+    assert err.max() <= 1e-12
+    assert np.array_equal(direct, chi2) and np.array_equal(static, chi2)
+    assert info["tuned"] == 0 and info["blocks"] >= 1 and info["sys_per_batch"] == 1
+
+
+def test_ragged_fp64_static_rejects_bad_offsets_per_system(dev):
+    """The binary64 kernel checks each system's offsets itself: inconsistent ones
+    (past the arrays, decreasing, too many planets) give NaN for exactly those
+    systems, the others keep their chi-square."""
+    rw = _ragged(300, seed=32, n_obs_range=(16, 300))
+    good = _static(rw, dev, "fp64")
+    n_obs_total, n_pl_total = int(rw.obs_off[-1]), int(rw.pl_off[-1])
+    bad_obs = rw.obs_off.copy()
+    bad_obs[101] = n_obs_total + 5               # system 100 ends, system 101 starts, past the array
+    bad_obs[201] = bad_obs[200] - 1              # system 200 decreases (201 stays valid, longer)
+    bad_pl = rw.pl_off.copy()
+    bad_pl[51] = bad_pl[50] + kp.KEP_MAX_PL + 1  # system 50 with nine planets (51 then decreases)
+    bad_pl[-1] = n_pl_total + 2                  # the last system ends past the planet array
+    o0, o1, p0, p1 = bad_obs[:-1], bad_obs[1:], bad_pl[:-1], bad_pl[1:]
+    valid = ((o0 >= 0) & (o0 <= o1) & (o1 <= n_obs_total) & (p0 >= 0) & (p0 < p1) & (p1 <= n_pl_total)
+             & (p1 - p0 <= kp.KEP_MAX_PL))
+    # system 51 starts after system 50's nine planets: it decreases or, if its old end
+    # lies beyond that, stays valid with other planets
+    assert {50, 100, 101, 200, rw.n_sys - 1} <= set(np.flatnonzero(~valid).tolist())
+    assert set(np.flatnonzero(~valid).tolist()) <= {50, 51, 100, 101, 200, rw.n_sys - 1}
+    got = _static(rw, dev, "fp64", obs_off=bad_obs, pl_off=bad_pl)
+    assert np.all(np.isnan(got[~valid]))
+    assert np.all(np.isfinite(got[valid]))
+    same = valid.copy()
+    same[[51, 201]] = False                      # valid or not, with other inputs than in `good`
+    assert np.array_equal(got[same], good[same])
 
 
 def test_ragged_graph_replay_equals_direct(dev):
