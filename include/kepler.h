@@ -65,7 +65,7 @@ typedef enum kep_status {
     KEP_ERR_SHAPE = 2,        /* sizes inconsistent with each other (n_pl, CSR offsets) */
     KEP_ERR_DEVICE = 3,       /* no usable HIP device or a HIP runtime call failed */
     KEP_ERR_LAUNCH = 4,       /* a kernel launch was rejected */
-    KEP_ERR_UNSUPPORTED = 5   /* valid request this build does not implement */
+    KEP_ERR_UNSUPPORTED = 5   /* valid request the library does not implement */
 } kep_status;
 
 typedef enum kep_prec {
