@@ -232,6 +232,26 @@ def test_ragged_packed_tails_edges(dev):
         assert _check_edge(_plan(rw, dev, opts=dict(block_threads=block))().cpu().numpy(), rw, invalid)
 
 
+def test_ragged_fp64_edges(dev):
+    """KEP_FP64 on the same edge batch: NaN exactly where the oracle has it, zero
+    for systems without observations, within 1e-12 elsewhere; plans with 256-
+    and 64-thread blocks and the allocation-free call give the same bits."""
+    rw, invalid = _edge_batch(500, seed=43)
+    ref = _oracle(rw)
+    bad = np.isnan(ref)
+    assert set(np.nonzero(bad)[0]) == invalid
+    empty = np.diff(rw.obs_off) == 0
+    assert np.any(empty & ~bad)
+    runs = [_plan(rw, dev, prec="fp64")().cpu().numpy(),
+            _plan(rw, dev, opts=dict(block_threads=64), prec="fp64")().cpu().numpy(),
+            _static(rw, dev, "fp64")]
+    for got in runs:
+        assert np.array_equal(np.isnan(got), bad)
+        assert np.all(got[empty & ~bad] == 0.0)
+        assert W.rel_err_chi2(got[~bad], ref[~bad]).max() <= 1e-12
+        assert np.array_equal(got[~bad], runs[0][~bad])
+
+
 _SHAPES_SCRIPT = r"""
 import json, sys
 import numpy as np, torch
